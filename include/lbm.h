@@ -1,0 +1,232 @@
+/*
+ * lbm.h — C ABI of the MI355X (gfx950) D3Q7 reactive-diffusion lattice Boltzmann
+ * solver for voxelised catalyst-layer structures.
+ *
+ * Method: Chen, Wu, Kang, Holby, Tao, "Nanoscale study of reactive transport in
+ * catalyst layer of proton exchange membrane fuel cells with precious and
+ * non-precious catalysts using lattice Boltzmann method", arXiv 1410.1914.
+ *   - phases and local diffusivity: Section 3.1 (Eqs. 7-9), Section 3.2 (Eqs. 14-15);
+ *   - pore size for Knudsen diffusion: 13-direction averaging, Section 2.1.3;
+ *   - proton conduction: Section 3.3 (Eq. 16);
+ *   - first-order surface reaction: Section 3.4 (Eqs. 17b, 18a) with uniform
+ *     ionomer potential (Section 3.5.2);
+ *   - boundary conditions: Section 3.5.1 (Eq. 19) and 3.5.2 (Eqs. 20a, 20b);
+ *   - LBM evolution, equilibrium, moments and tau-D relation: Section 4,
+ *     Eqs. (21)-(24), on the D3Q7 lattice (rest weight w0, c_s^2 = (1 - w0)/3).
+ *
+ * Conventions
+ *   - Every function returns an int status: LBM_OK (0), LBM_NOT_CONVERGED (1,
+ *     results readable but flagged), or a negative error.  No exception, abort or
+ *     exit crosses this boundary.
+ *   - Arrays named *_host are host memory; arrays named *_dev are device memory
+ *     on the device current when lbm_bind was called.
+ *   - Dense voxel arrays are x fastest: v = (z*ny + y)*nx + x.  Population arrays
+ *     are [7][N] in the order rest, +x, -x, +y, -y, +z, -z.
+ *   - Lattice units: dx = dt = 1.  All scalars are FP64 at the ABI; distributions
+ *     are FP32 on the device, reductions FP64.
+ *   - Ownership: the caller owns every pointer it passes.  The phase map is copied
+ *     by lbm_create.  The device workspace handed to lbm_bind must stay allocated
+ *     until lbm_destroy (or a re-bind).  The library allocates no device memory.
+ *   - Streams: all device work is enqueued on the stream given to lbm_bind.
+ *     Functions that return host values synchronise that stream.
+ *   - Threading: a solver handle must not be used by two threads at once.
+ */
+#ifndef PAPER_1410_1914_AMD_LBM_H
+#define PAPER_1410_1914_AMD_LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_ABI_VERSION 1
+
+/* phase ids of the input map (Section 2: pore, carbon, Pt, ionomer) */
+enum { LBM_PORE = 0, LBM_CARBON = 1, LBM_PT = 2, LBM_IONOMER = 3 };
+
+/* problems (Section 3.5): effective O2 diffusivity, reactive O2 transport,
+ * effective proton conductivity (ionomer is the only conducting phase) */
+enum { LBM_MODE_DEFF = 0, LBM_MODE_REACT = 1, LBM_MODE_PROTON = 2 };
+
+enum {
+    LBM_OK = 0,
+    LBM_NOT_CONVERGED = 1,
+    LBM_ERR_INVALID_ARG = -1,   /* NULL pointer, bad size or parameter        */
+    LBM_ERR_BAD_PHASE = -2,     /* phase id outside 0..3                       */
+    LBM_ERR_WRONG_MODE = -3,    /* e.g. lbm_deff on a reactive problem         */
+    LBM_ERR_NO_PERCOLATION = -4,/* no transport path between the Dirichlet faces
+                                   (lbm_deff still returns 0 through its output) */
+    LBM_ERR_DIVERGED = -5,      /* NaN or Inf in the distributions             */
+    LBM_ERR_HIP = -6,           /* a HIP runtime call failed                   */
+    LBM_ERR_UNBOUND = -7,       /* no workspace bound yet                      */
+    LBM_ERR_WORKSPACE = -8,     /* workspace too small or misaligned           */
+    LBM_ERR_UNSTABLE = -9       /* k*n >= 1 somewhere, or tau <= 1/2           */
+};
+
+typedef struct lbm_solver lbm_solver; /* opaque, owned by the library */
+typedef struct lbm_batch lbm_batch;   /* opaque, owned by the library */
+
+typedef struct {
+    int32_t nx, ny, nz; /* structure size in voxels (x is the transport direction) */
+    double voxel_m;     /* voxel edge in metres (Knudsen diffusivity, Eq. 8)       */
+} lbm_grid;
+
+typedef struct {
+    uint32_t struct_size;      /* = sizeof(lbm_params); guards against ABI drift    */
+    int32_t mode;              /* LBM_MODE_*                                        */
+    double c_in, c_out;        /* Dirichlet values at x = 0 and x = L (c_out unused
+                                  in LBM_MODE_REACT, whose outlet is zero-gradient) */
+    double tau_ref;            /* relaxation time given to D_ref (default 1)        */
+    double w0;                 /* D3Q7 rest weight (default 1/4)                    */
+    int32_t knudsen;           /* 1: pore D by Bosanquet with local Knudsen D       */
+    double T_K, p_atm, M_kg_mol; /* temperature, pressure, molar mass (353, 1, 0.032) */
+    double d_ionomer_rel;      /* ionomer D / D0 (default 1e-3)                     */
+    double d_ref_rel;          /* 0: D_ref = largest simulated D; else D_ref/D0     */
+    double k_lat;              /* first-order rate per catalyst face, lattice units */
+    uint32_t catalyst_phases;  /* bit mask over phase ids (default 1 << LBM_PT)     */
+    uint32_t reactive_fluids;  /* bit mask of fluid phases that react (pore|ionomer)*/
+    int32_t reservoir_plane;   /* REACT: prepend one pore plane at the inlet (1)    */
+    double tol_change;         /* stop: max|C_t - C_{t-K}| / (K max|C|) below this  */
+    double tol_flux;           /* stop: estimated remaining relative error of the
+                                  output (flux or rate) and of the total mass below
+                                  this (default 1e-5)                               */
+    double tol_balance;        /* stop: |J_in - J_out - R| / |J_in| below this      */
+    int32_t check_every;       /* K: steps between convergence checks (even)        */
+    int64_t max_steps;         /* give up (LBM_NOT_CONVERGED) after this many steps */
+} lbm_params;
+
+typedef struct {
+    int64_t steps;      /* LBM steps taken since the last initialisation          */
+    double residual;    /* max|C_t - C_{t-K}| / (K max|C_t|) at the last check    */
+    double j_in;        /* net flux through the inlet face, per unit area         */
+    double j_out;       /* net flux through the outlet face, per unit area        */
+    double j_vol;       /* net x flux averaged over all interior faces, per area  */
+    double rate;        /* total sink sum k n C, per unit cross-section area      */
+    double mass;        /* total sum of C over simulated voxels                   */
+    double est_error;   /* estimated remaining relative error of the output       */
+    int32_t status;     /* LBM_OK, LBM_NOT_CONVERGED or an error                  */
+    int32_t checks;     /* number of convergence checks made                      */
+} lbm_run_info;
+
+typedef struct {
+    int32_t nx, ny, nz;    /* simulated grid (REACT with reservoir: nx + 1)       */
+    int32_t nx_struct;     /* structure size along x                              */
+    int64_t n_active;      /* simulated voxels (transport, connected)             */
+    int64_t n_segments;    /* 64-voxel row segments of the simulated grid         */
+    double d0;             /* D0 (m^2/s; 1 in proton mode)                        */
+    double d_ref;          /* D_ref (same units)                                  */
+    double d0_lat;         /* D0 in lattice units                                 */
+    int32_t percolates;    /* transport path joins the Dirichlet faces            */
+    int32_t mode;
+} lbm_info;
+
+/* Fill *p with the defaults listed above.  Returns LBM_ERR_INVALID_ARG on NULL. */
+int lbm_params_default(lbm_params *p);
+
+/* Preprocess a structure (host only, no device call): phases -> transport mask,
+ * 13-direction pore size (Section 2.1.3), local D (Eqs. 7-9, 15), tau (Eq. 24),
+ * catalyst neighbour counts (Eq. 18a), dead-pocket removal, and the segment
+ * bitmasks used by the kernels.  phase_host is nz*ny*nx bytes, copied.  On
+ * success *out receives a new handle.  Errors: INVALID_ARG, BAD_PHASE, UNSTABLE. */
+int lbm_create(const lbm_grid *g, const uint8_t *phase_host, const lbm_params *p, lbm_solver **out);
+
+/* Sizes and reference values of a created solver. */
+int lbm_get_info(const lbm_solver *s, lbm_info *info);
+
+/* Host copies of the preprocessed fields on the simulated grid (dense, N bytes or
+ * floats each).  Any pointer may be NULL.  active: 1 for simulated voxels;
+ * n_cat: catalyst face-neighbour count (0..6) of every voxel; omega: 1/tau of
+ * simulated voxels (FP32 as used on the device), 0 elsewhere. */
+int lbm_get_host_fields(const lbm_solver *s, uint8_t *active_host, uint8_t *n_cat_host, float *omega_host);
+
+/* Device bytes the solver needs (distributions, metadata, reduction scratch). */
+int lbm_workspace_bytes(const lbm_solver *s, size_t *bytes);
+
+/* Hand the solver a device workspace (>= lbm_workspace_bytes, 256-byte aligned)
+ * and a HIP stream (hipStream_t, may be NULL for the default stream).  Uploads the
+ * metadata and initialises the distributions to equilibrium at C = c_out (REACT:
+ * C = 0).  Errors: INVALID_ARG, WORKSPACE, HIP. */
+int lbm_bind(lbm_solver *s, void *workspace_dev, size_t bytes, void *hip_stream);
+
+/* Initialise the distributions to equilibrium f_i = w_i C (Eq. 23) from a dense
+ * FP32 concentration field on the simulated grid (NULL: cold start as in
+ * lbm_bind).  Resets the step count and the convergence history. */
+int lbm_set_initial_concentration(lbm_solver *s, const float *c_dev);
+
+/* Set the stored post-collision distributions from a dense FP32 [7][N] array on
+ * the simulated grid (values of non-simulated voxels are ignored). */
+int lbm_set_populations(lbm_solver *s, const float *f_dev);
+
+/* Copy the stored post-collision distributions to a dense FP32 [7][N] array
+ * (non-simulated voxels receive 0). */
+int lbm_get_populations(const lbm_solver *s, float *f_dev);
+
+/* Advance nsteps >= 0 fused stream-collide steps (Eq. 21) without checks. */
+int lbm_step(lbm_solver *s, int64_t nsteps);
+
+/* FP64 reductions of the current state (no stepping): the fluxes of the next
+ * streaming, the sink and the mass, exactly as the steady-state outputs use them.
+ * Fills j_in, j_out, j_vol, rate, mass; leaves the convergence fields alone. */
+int lbm_measure(lbm_solver *s, lbm_run_info *info);
+
+/* Step to the steady state.  Checks follow windows of K steps (doubled while the
+ * mass still decays by less than half per window); the run stops when the windowed
+ * residual, the estimated remaining relative error of the output and of the total
+ * mass (geometric extrapolation with the decay rate measured on the mass), and the
+ * flux balance are all below their tolerances, or after max_steps.  Returns LBM_OK, LBM_NOT_CONVERGED,
+ * LBM_ERR_DIVERGED or LBM_ERR_NO_PERCOLATION (D_eff problems without a path). */
+int lbm_run_to_steady(lbm_solver *s, lbm_run_info *info);
+
+/* D_eff/D0 (LBM_MODE_DEFF) or sigma_eff/sigma (LBM_MODE_PROTON) from the volume
+ * averaged x flux of the last measurement, Eq. (19) with L = nx:
+ * J * nx / ((c_in - c_out) * D0_lat).  WRONG_MODE in LBM_MODE_REACT. */
+int lbm_deff(const lbm_solver *s, double *deff_over_d0);
+
+/* Total reaction rate per unit cross-section area (sum k n C / (ny nz)) and the
+ * inlet flux per unit area (lattice units), LBM_MODE_REACT only. */
+int lbm_reaction_rate(const lbm_solver *s, double *rate_per_area, double *j_in);
+
+/* Dense FP32 concentration on the simulated grid (0 off the simulated voxels). */
+int lbm_concentration(const lbm_solver *s, float *c_dev);
+
+/* Release the handle (NULL is a no-op). The workspace stays the caller's. */
+void lbm_destroy(lbm_solver *s);
+
+/* Static text for a status code. */
+const char *lbm_status_string(int status);
+
+/* Text naming the first HIP call that failed in the calling thread's last failing
+ * operation ("" if none); valid until the next call on this thread. */
+const char *lbm_last_error(void);
+
+/* ---------------------------------------------------------------- batched form
+ * Many independent structures of uneven size in one launch per step, captured in
+ * a HIP graph, with per-instance FP64 reductions and retirement at check
+ * boundaries.  All instances share mode and the Knudsen switch; every other
+ * parameter (k, c_in, tau_ref, ...) is per instance. */
+
+/* n >= 1 structures; grids[i], phases_host[i] (nz*ny*nx bytes), params[i]. */
+int lbm_batch_create(int32_t n, const lbm_grid *grids, const uint8_t *const *phases_host,
+                     const lbm_params *params, lbm_batch **out);
+int lbm_batch_workspace_bytes(const lbm_batch *b, size_t *bytes);
+int lbm_batch_bind(lbm_batch *b, void *workspace_dev, size_t bytes, void *hip_stream);
+/* Tiling chosen by lbm_batch_autotune (or set explicitly): segments per wave
+ * (1, 2, 4), waves per workgroup (1, 2, 4, 8), XCD-aware block order (0/1). */
+int lbm_batch_set_tiling(lbm_batch *b, int32_t segs_per_wave, int32_t waves_per_block, int32_t xcd_remap);
+int lbm_batch_get_tiling(const lbm_batch *b, int32_t *segs_per_wave, int32_t *waves_per_block, int32_t *xcd_remap);
+/* Time every tiling on the live workload (steps_per_trial steps each, state is
+ * restored afterwards) and keep the fastest; ms_best receives its time per step. */
+int lbm_batch_autotune(lbm_batch *b, int32_t steps_per_trial, double *ms_best);
+/* Run all instances to their steady states; infos[n] receives per-instance results. */
+int lbm_batch_run(lbm_batch *b, lbm_run_info *infos);
+int lbm_batch_deff(const lbm_batch *b, int32_t i, double *deff_over_d0);
+int lbm_batch_reaction_rate(const lbm_batch *b, int32_t i, double *rate_per_area, double *j_in);
+int lbm_batch_get_info(const lbm_batch *b, int32_t i, lbm_info *info);
+void lbm_batch_destroy(lbm_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

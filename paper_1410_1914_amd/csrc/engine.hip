@@ -1,0 +1,894 @@
+// Solver engine behind the C ABI of include/lbm.h: workspace layout, block
+// tables, HIP-graph-captured check windows, per-instance convergence control.
+//
+// A single solver is an engine with one instance; the batched form is the same
+// engine with many instances concatenated (segments, compact fluid arrays) and
+// one launch per step covering every live instance.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <memory>
+#include <new>
+#include <vector>
+
+#include "kernels.h"
+#include "prep.h"
+
+namespace cl {
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kMeasMaxBlocks = 512;
+constexpr int kMeasWaves = 4;
+constexpr int64_t kMaxWindow = int64_t(1) << 22;  // longest check window (steps)
+
+size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
+
+thread_local char g_last_error[256] = "";
+
+// record the first failing HIP call of an operation (read by lbm_last_error)
+hipError_t note(hipError_t e, const char *what) {
+    if (e != hipSuccess) snprintf(g_last_error, sizeof(g_last_error), "%s: %s (%d)", what, hipGetErrorName(e), (int)e);
+    return e;
+}
+
+struct RunState {
+    lbm_run_info info{};
+    double q_prev = 0, m_prev = 0;  // output and mass at the previous check
+    double dm_prev = 0;             // mass change over the previous window
+    int64_t k_prev = 0;             // length of the previous window (0: none)
+    int have_prev = 0;
+    int slow = 0;                   // mass decays by less than half per window
+    int done = 0;
+    int measured = 0;
+};
+
+struct Engine {
+    std::vector<Prepared> P;
+    int mode = 0;
+    bool knudsen = false, react = false;
+    int ninst = 0;
+    int64_t nseg_total = 0, nf_total = 0, stride = 0;
+    std::vector<int64_t> seg_base, fluid_base, dense_base;
+    int check_every = 1000;
+
+    // workspace
+    size_t ws_need = 0;
+    size_t off_f0 = 0, off_f1 = 0, off_om = 0, off_snap = 0, off_mf = 0, off_mi = 0, off_mr = 0, off_mc = 0,
+           off_pre = 0, off_inst = 0, off_dbase = 0, off_sblk = 0, off_cblk = 0, off_mblk = 0, off_rng = 0,
+           off_part = 0, off_res = 0;
+    int64_t cap_sblk = 0, cap_cblk = 0, cap_mblk = 0;
+
+    bool bound = false;
+    int device = 0;
+    hipStream_t st = nullptr;
+    char *ws = nullptr;
+    double *res_host = nullptr;
+    Lattice L{};
+    float *f[2] = {nullptr, nullptr};
+    float *csnap = nullptr;
+    int cur = 0;
+
+    int waves = 4, spw = 1, xcd = 1;
+    int step_nblk = 0, meas_nblk = 0, conv_nblk = 0;
+    std::vector<int> live;
+    std::vector<RunState> rs;
+
+    hipGraphExec_t gexec = nullptr;
+    int g_cur = -1, g_nblk = -1;
+    bool g_valid = false;
+
+    ~Engine() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (res_host) (void)hipHostFree(res_host);
+    }
+
+    template <typename T>
+    T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
+
+    void layout() {
+        nseg_total = nf_total = 0;
+        seg_base.resize(ninst);
+        fluid_base.resize(ninst);
+        dense_base.resize(ninst);
+        int64_t dense = 0;
+        for (int i = 0; i < ninst; ++i) {
+            seg_base[i] = nseg_total;
+            fluid_base[i] = nf_total;
+            dense_base[i] = dense;
+            nseg_total += P[i].nseg;
+            nf_total += P[i].n_fluid;
+            dense += (int64_t)P[i].nx * P[i].ny * P[i].nz;
+        }
+        stride = (int64_t)align_up((size_t)std::max<int64_t>(nf_total, 1), 64);
+        cap_sblk = nseg_total + ninst;
+        cap_cblk = nseg_total / 4 + ninst + 1;
+        cap_mblk = (int64_t)ninst * kMeasMaxBlocks;
+        size_t o = 0;
+        auto take = [&](size_t bytes) {
+            const size_t r = o;
+            o = align_up(o + std::max<size_t>(bytes, 1));
+            return r;
+        };
+        off_f0 = take(sizeof(float) * 7 * stride);
+        off_f1 = take(sizeof(float) * 7 * stride);
+        off_om = knudsen ? take(sizeof(float) * stride) : 0;
+        off_snap = take(sizeof(float) * stride);
+        off_mf = take(sizeof(uint64_t) * nseg_total);
+        off_mi = take(sizeof(uint64_t) * nseg_total);
+        off_mr = take(sizeof(uint64_t) * nseg_total);
+        off_mc = take(sizeof(uint64_t) * nseg_total);
+        off_pre = take(sizeof(uint32_t) * nseg_total);
+        off_inst = take(sizeof(InstDev) * ninst);
+        off_dbase = take(sizeof(int64_t) * ninst);
+        off_sblk = take(sizeof(int2) * cap_sblk);
+        off_cblk = take(sizeof(int2) * cap_cblk);
+        off_mblk = take(sizeof(int4) * cap_mblk);
+        off_rng = take(sizeof(int2) * ninst);
+        off_part = take(sizeof(double) * NQ * cap_mblk);
+        off_res = take(sizeof(double) * NQ * ninst);
+        ws_need = o;
+    }
+
+    InstDev inst_dev(int i) const {
+        const Prepared &p = P[i];
+        InstDev d{};
+        d.nx = p.nx;
+        d.ny = p.ny;
+        d.nz = p.nz;
+        d.nsx = p.nsx;
+        d.seg_base = seg_base[i];
+        d.nseg = p.nseg;
+        d.sh0 = p.sh0;
+        d.slope = p.slope;
+        d.w0 = p.w0;
+        d.w1 = p.w1;
+        d.pull_dx = p.w1 * p.slope;
+        d.abb_in = 2.0 * p.w1 * (p.params.c_in - p.sh0);
+        d.abb_out = 2.0 * p.w1 * (p.params.c_out - (p.sh0 - p.slope * (p.nx - 1)));
+        d.k = p.params.k_lat;
+        d.om_pore = p.om_pore;
+        d.om_ion = p.om_ion;
+        return d;
+    }
+
+    hipError_t upload_tables() {
+        // step table over live instances
+        std::vector<int2> sb;
+        const int per = waves * spw;
+        for (int i : live) {
+            const int64_t nb = (P[i].nseg + per - 1) / per;
+            for (int64_t b = 0; b < nb; ++b) sb.push_back(make_int2(i, (int)(b * per)));
+        }
+        step_nblk = (int)sb.size();
+        // measure table and per-instance partial ranges
+        std::vector<int4> mb;
+        std::vector<int2> rg(ninst, make_int2(0, 0));
+        for (int i : live) {
+            int64_t nb = (P[i].nseg + kMeasWaves * 16 - 1) / (kMeasWaves * 16);
+            nb = std::max<int64_t>(1, std::min<int64_t>(nb, kMeasMaxBlocks));
+            rg[i] = make_int2((int)mb.size(), (int)nb);
+            for (int64_t b = 0; b < nb; ++b) mb.push_back(make_int4(i, (int)b, (int)nb, (int)mb.size()));
+        }
+        meas_nblk = (int)mb.size();
+        hipError_t e = hipSuccess;
+        if (!sb.empty()) e = hipMemcpyAsync(at<int2>(off_sblk), sb.data(), sizeof(int2) * sb.size(), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess && !mb.empty())
+            e = hipMemcpyAsync(at<int4>(off_mblk), mb.data(), sizeof(int4) * mb.size(), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(at<int2>(off_rng), rg.data(), sizeof(int2) * ninst, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);  // host vectors go out of scope
+        g_valid = false;
+        return e;
+    }
+
+    hipError_t bind(void *mem, size_t bytes, hipStream_t stream) {
+        if (gexec) {
+            (void)hipGraphExecDestroy(gexec);
+            gexec = nullptr;
+        }
+        g_valid = false;
+        ws = static_cast<char *>(mem);
+        st = stream;
+        g_last_error[0] = 0;
+        hipError_t e = note(hipGetDevice(&device), "hipGetDevice");
+        if (e != hipSuccess) return e;
+        if (!res_host) {
+            e = note(hipHostMalloc((void **)&res_host, sizeof(double) * NQ * ninst, hipHostMallocDefault), "hipHostMalloc");
+            if (e != hipSuccess) return e;
+        }
+        f[0] = at<float>(off_f0);
+        f[1] = at<float>(off_f1);
+        csnap = at<float>(off_snap);
+        L.m_fluid = at<uint64_t>(off_mf);
+        L.m_ion = at<uint64_t>(off_mi);
+        L.m_react = at<uint64_t>(off_mr);
+        L.m_cat = at<uint64_t>(off_mc);
+        L.prefix = at<uint32_t>(off_pre);
+        L.omega = knudsen ? at<float>(off_om) : nullptr;
+        L.inst = at<InstDev>(off_inst);
+        L.stride = stride;
+        // metadata (host staging, then one synchronisation)
+        std::vector<uint64_t> mf(nseg_total), mi(nseg_total), mr(nseg_total), mc(nseg_total);
+        std::vector<uint32_t> pre(nseg_total);
+        std::vector<float> om(knudsen ? nf_total : 0);
+        std::vector<InstDev> id(ninst);
+        std::vector<int2> cb;
+        for (int i = 0; i < ninst; ++i) {
+            const Prepared &p = P[i];
+            std::copy(p.m_fluid.begin(), p.m_fluid.end(), mf.begin() + seg_base[i]);
+            std::copy(p.m_ion.begin(), p.m_ion.end(), mi.begin() + seg_base[i]);
+            std::copy(p.m_react.begin(), p.m_react.end(), mr.begin() + seg_base[i]);
+            std::copy(p.m_cat.begin(), p.m_cat.end(), mc.begin() + seg_base[i]);
+            for (int64_t s = 0; s < p.nseg; ++s) pre[seg_base[i] + s] = (uint32_t)(p.prefix[s] + fluid_base[i]);
+            if (knudsen) std::copy(p.omega_c.begin(), p.omega_c.end(), om.begin() + fluid_base[i]);
+            id[i] = inst_dev(i);
+            for (int64_t b = 0; b < (p.nseg + 3) / 4; ++b) cb.push_back(make_int2(i, (int)(b * 4)));
+        }
+        conv_nblk = (int)cb.size();
+        if (nf_total > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
+        auto up = [&](size_t off, const void *src, size_t n) {
+            return note(n ? hipMemcpyAsync(ws + off, src, n, hipMemcpyHostToDevice, st) : hipSuccess, "upload");
+        };
+        if ((e = up(off_mf, mf.data(), 8 * mf.size())) != hipSuccess) return e;
+        if ((e = up(off_mi, mi.data(), 8 * mi.size())) != hipSuccess) return e;
+        if ((e = up(off_mr, mr.data(), 8 * mr.size())) != hipSuccess) return e;
+        if ((e = up(off_mc, mc.data(), 8 * mc.size())) != hipSuccess) return e;
+        if ((e = up(off_pre, pre.data(), 4 * pre.size())) != hipSuccess) return e;
+        if (knudsen && (e = up(off_om, om.data(), 4 * om.size())) != hipSuccess) return e;
+        if ((e = up(off_inst, id.data(), sizeof(InstDev) * id.size())) != hipSuccess) return e;
+        if ((e = up(off_dbase, dense_base.data(), 8 * dense_base.size())) != hipSuccess) return e;
+        if ((e = up(off_cblk, cb.data(), sizeof(int2) * cb.size())) != hipSuccess) return e;
+        if ((e = note(hipStreamSynchronize(st), "bind sync")) != hipSuccess) return e;
+        bound = true;
+        live.clear();
+        for (int i = 0; i < ninst; ++i) live.push_back(i);
+        if ((e = note(upload_tables(), "upload_tables")) != hipSuccess) return e;
+        return note(init(nullptr), "init");
+    }
+
+    hipError_t init(const float *c_dense) {
+        cur = 0;
+        rs.assign(ninst, RunState{});
+        live.clear();
+        for (int i = 0; i < ninst; ++i) live.push_back(i);
+        hipError_t e = upload_tables();
+        if (e != hipSuccess) return e;
+        return note(launch_init_eq(L, conv_nblk, at<int2>(off_cblk), react, c_dense, at<int64_t>(off_dbase), f[0], csnap, st),
+                    "k_init_eq launch");
+    }
+
+    // the user-level step/measure calls act on every instance
+    hipError_t all_live() {
+        if ((int)live.size() == ninst) return hipSuccess;
+        live.clear();
+        for (int i = 0; i < ninst; ++i) live.push_back(i);
+        return upload_tables();
+    }
+
+    StepLaunch step_launch() const {
+        StepLaunch s{};
+        s.waves = waves;
+        s.spw = spw;
+        s.xcd = xcd;
+        s.nblk = step_nblk;
+        s.blk = at<int2>(off_sblk);
+        return s;
+    }
+
+    hipError_t steps(int64_t n) {
+        const StepLaunch s = step_launch();
+        for (int64_t k = 0; k < n; ++k) {
+            hipError_t e = launch_step(L, s, knudsen, react, f[cur], f[cur ^ 1], st);
+            if (e != hipSuccess) return e;
+            cur ^= 1;
+        }
+        return hipSuccess;
+    }
+
+    hipError_t measure_enqueue(int update_snap) {
+        MeasureLaunch m{};
+        m.nblk = meas_nblk;
+        m.blk = at<int4>(off_mblk);
+        m.partial = at<double>(off_part);
+        m.update_snap = update_snap;
+        m.csnap = csnap;
+        hipError_t e = launch_measure(L, m, react, f[cur], st);
+        if (e != hipSuccess) return e;
+        return launch_finish(at<double>(off_part), at<int2>(off_rng), ninst, at<double>(off_res), st);
+    }
+
+    hipError_t read_results() {
+        hipError_t e = hipMemcpyAsync(res_host, at<double>(off_res), sizeof(double) * NQ * ninst, hipMemcpyDeviceToHost, st);
+        if (e != hipSuccess) return e;
+        return hipStreamSynchronize(st);
+    }
+
+    // One check window: `reps` launches of a captured graph of K0 steps, then the
+    // FP64 reductions (which also refresh the concentration snapshot).
+    hipError_t window(int K0, int64_t reps) {
+        if (st == nullptr) {  // the legacy default stream cannot be captured
+            for (int64_t r = 0; r < reps; ++r) {
+                hipError_t e = steps(K0);
+                if (e != hipSuccess) return e;
+            }
+            return measure_enqueue(1);
+        }
+        if (!g_valid || g_cur != cur || g_nblk != step_nblk) {
+            if (gexec) {
+                (void)hipGraphExecDestroy(gexec);
+                gexec = nullptr;
+            }
+            hipGraph_t graph = nullptr;
+            hipError_t e = note(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+            if (e != hipSuccess) return e;
+            const int c0 = cur;
+            hipError_t e1 = steps(K0);
+            cur = c0;
+            e = note(hipStreamEndCapture(st, &graph), "hipStreamEndCapture");
+            if (e1 != hipSuccess) return e1;
+            if (e != hipSuccess) return e;
+            e = note(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) return e;
+            g_valid = true;
+            g_cur = cur;
+            g_nblk = step_nblk;
+        }
+        for (int64_t r = 0; r < reps; ++r) {
+            hipError_t e = note(hipGraphLaunch(gexec, st), "hipGraphLaunch");
+            if (e != hipSuccess) return e;
+            if (K0 & 1) cur ^= 1;
+        }
+        if (K0 & 1) g_valid = false;  // the next window starts from the other lattice
+        return measure_enqueue(1);
+    }
+
+    void fill_info(int i, const double *r, int64_t K, lbm_run_info &info) const {
+        const Prepared &p = P[i];
+        const double A = (double)p.ny * p.nz;
+        info.j_in = r[Q_JIN] / A;
+        info.j_out = r[Q_JOUT] / A;
+        info.j_vol = p.nx > 1 ? r[Q_JINT] / ((double)(p.nx - 1) * A) : info.j_in;
+        info.rate = r[Q_RATE] / A;
+        info.mass = r[Q_MASS];
+        if (K > 0) info.residual = r[Q_CMAX] > 0 ? r[Q_DCMAX] / ((double)K * r[Q_CMAX]) : 0.0;
+    }
+
+    // Stop rule for one instance after a check window of K steps; true when finished.
+    //
+    // The iteration converges geometrically; its rate per window, rho, is taken from
+    // the total mass (an FP64 sum over every voxel, far less noisy than any flux),
+    // using two consecutive windows of equal length.  The remaining error of a
+    // quantity that changed by d over the last window is d rho / (1 - rho).  Both the
+    // output (volume-averaged flux, or total reaction rate) and the mass must be
+    // within tol_flux by that estimate, and the output's last change itself too;
+    // the windowed residual and the flux balance are checked as well.
+    bool evaluate(int i, const double *r, int64_t K) {
+        RunState &s = rs[i];
+        const lbm_params &pp = P[i].params;
+        lbm_run_info &info = s.info;
+        fill_info(i, r, K, info);
+        s.measured = 1;
+        info.checks += 1;
+        info.steps += K;
+        if (r[Q_BAD] > 0.0) {
+            info.status = LBM_ERR_DIVERGED;
+            return true;
+        }
+        const double Q = react ? info.rate : info.j_vol;
+        const double M = info.mass;
+        const double inf = std::numeric_limits<double>::infinity();
+        double est = inf;
+        s.slow = 0;  // no rate estimate yet (or the window length just changed): keep it
+        if (s.have_prev) {
+            const double dq = Q - s.q_prev, dm = M - s.m_prev;
+            const double rq = std::fabs(dq) / std::max(std::fabs(Q), 1e-300);
+            const double rm = std::fabs(dm) / std::max(std::fabs(M), 1e-300);
+            if (s.k_prev == K && s.dm_prev != 0.0) {
+                const double rho = dm / s.dm_prev;
+                if (rho <= 0.0 || dm == 0.0) {  // the mass change is at its noise floor
+                    est = std::max(rq, rm);
+                    s.slow = 0;
+                } else if (rho < 1.0) {
+                    const double amp = rho / (1.0 - rho);
+                    est = std::max(std::max(rq, rm) * amp, rq);
+                    s.slow = rho > 0.5;
+                } else {
+                    s.slow = 1;  // not contracting yet at this window length
+                }
+            } else if (dm == 0.0 && s.k_prev == K) {
+                est = rq;
+                s.slow = 0;
+            }
+            s.dm_prev = dm;
+        }
+        s.q_prev = Q;
+        s.m_prev = M;
+        s.k_prev = K;
+        s.have_prev = 1;
+        info.est_error = est;
+        const double jref = std::max(std::fabs(info.j_in), 1e-300);
+        double bal = react ? std::fabs(info.j_in - info.rate) / jref : std::fabs(info.j_in - info.j_out) / jref;
+        if (std::fabs(info.j_in) < 1e-30 && std::fabs(info.j_out) < 1e-30 && std::fabs(info.rate) < 1e-30) bal = 0.0;
+        const bool conv = info.checks >= 3 && est < pp.tol_flux && info.residual < pp.tol_change && bal < pp.tol_balance;
+        if (conv) {
+            info.status = LBM_OK;
+            return true;
+        }
+        info.status = LBM_NOT_CONVERGED;
+        return info.steps >= pp.max_steps;
+    }
+
+    int run(lbm_run_info *out) {
+        if (!bound) return LBM_ERR_UNBOUND;
+        const int K = check_every;
+        // instances without a percolating path are finished before the first step
+        std::vector<int> still;
+        for (int i : live) {
+            if (rs[i].done) continue;
+            if (!react && !P[i].percolates) {
+                rs[i].done = 1;
+                rs[i].info.status = LBM_ERR_NO_PERCOLATION;
+            } else {
+                still.push_back(i);
+            }
+        }
+        if (still.size() != live.size()) {
+            live = still;
+            if (upload_tables() != hipSuccess) return LBM_ERR_HIP;
+        }
+        int64_t reps = 1;  // window = reps * K steps; doubled while every live instance is slow
+        while (!live.empty()) {
+            if (window(K, reps) != hipSuccess) return LBM_ERR_HIP;
+            if (read_results() != hipSuccess) return LBM_ERR_HIP;
+            std::vector<int> keep;
+            bool all_slow = true;
+            for (int i : live) {
+                if (evaluate(i, res_host + (size_t)i * NQ, (int64_t)K * reps)) {
+                    rs[i].done = 1;
+                } else {
+                    keep.push_back(i);
+                    all_slow = all_slow && rs[i].slow;
+                }
+            }
+            if (keep.size() != live.size()) {
+                live = keep;
+                if (upload_tables() != hipSuccess) return LBM_ERR_HIP;
+            }
+            if (!live.empty() && all_slow && (int64_t)K * reps * 2 <= kMaxWindow) reps *= 2;
+        }
+        int worst = LBM_OK;
+        for (int i = 0; i < ninst; ++i) {
+            if (out) out[i] = rs[i].info;
+            const int s = rs[i].info.status;
+            if (s < 0 && (worst >= 0 || s < worst)) worst = s;
+            if (s == LBM_NOT_CONVERGED && worst == LBM_OK) worst = LBM_NOT_CONVERGED;
+        }
+        return worst;
+    }
+
+    int deff(int i, double *out) const {
+        const Prepared &p = P[i];
+        if (react) return LBM_ERR_WRONG_MODE;
+        if (!p.percolates) {
+            *out = 0.0;
+            return LBM_ERR_NO_PERCOLATION;
+        }
+        if (!rs[i].measured) return LBM_ERR_UNBOUND;
+        const double dc = p.params.c_in - p.params.c_out;
+        if (dc == 0.0) return LBM_ERR_INVALID_ARG;
+        *out = rs[i].info.j_vol * p.nx / (dc * p.d0_lat);
+        return rs[i].info.status == LBM_NOT_CONVERGED ? LBM_NOT_CONVERGED : LBM_OK;
+    }
+
+    int rate(int i, double *r, double *jin) const {
+        if (!react) return LBM_ERR_WRONG_MODE;
+        if (!rs[i].measured) return LBM_ERR_UNBOUND;
+        if (r) *r = rs[i].info.rate;
+        if (jin) *jin = rs[i].info.j_in;
+        return rs[i].info.status == LBM_NOT_CONVERGED ? LBM_NOT_CONVERGED : LBM_OK;
+    }
+
+    void info_of(int i, lbm_info &o) const {
+        const Prepared &p = P[i];
+        o.nx = p.nx;
+        o.ny = p.ny;
+        o.nz = p.nz;
+        o.nx_struct = p.nx_struct;
+        o.n_active = p.n_fluid;
+        o.n_segments = p.nseg;
+        o.d0 = p.d0;
+        o.d_ref = p.d_ref;
+        o.d0_lat = p.d0_lat;
+        o.percolates = p.percolates ? 1 : 0;
+        o.mode = p.mode;
+    }
+};
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int now = -1;
+        if (prev >= 0 && hipGetDevice(&now) == hipSuccess && now != prev) (void)hipSetDevice(prev);
+    }
+};
+
+int hip_status_at(hipError_t e, const char *where) {
+    if (e == hipSuccess) return LBM_OK;
+    if (!g_last_error[0]) snprintf(g_last_error, sizeof(g_last_error), "%s: %s (%d)", where, hipGetErrorName(e), (int)e);
+    return LBM_ERR_HIP;
+}
+#define hip_status(e) hip_status_at((e), __func__)
+
+int make_engine(int n, const lbm_grid *grids, const uint8_t *const *phases, const lbm_params *params,
+                std::unique_ptr<Engine> &out) {
+    if (n <= 0 || !grids || !phases || !params) return LBM_ERR_INVALID_ARG;
+    auto E = std::make_unique<Engine>();
+    E->ninst = n;
+    E->P.resize(n);
+    for (int i = 0; i < n; ++i) {
+        if (!phases[i]) return LBM_ERR_INVALID_ARG;
+        const int st = prepare(grids[i], phases[i], params[i], E->P[i]);
+        if (st != LBM_OK) return st;
+        if (i > 0 && (params[i].mode != params[0].mode || E->P[i].knudsen != E->P[0].knudsen))
+            return LBM_ERR_INVALID_ARG;
+    }
+    E->mode = params[0].mode;
+    E->knudsen = E->P[0].knudsen;
+    E->react = E->mode == LBM_MODE_REACT;
+    E->check_every = params[0].check_every;
+    E->layout();
+    E->rs.assign(n, RunState{});
+    out = std::move(E);
+    return LBM_OK;
+}
+
+}  // namespace
+}  // namespace cl
+
+struct lbm_solver {
+    std::unique_ptr<cl::Engine> E;
+};
+struct lbm_batch {
+    std::unique_ptr<cl::Engine> E;
+};
+
+#define LBM_GUARD_BEGIN try {
+#define LBM_GUARD_END                     \
+    }                                     \
+    catch (const std::bad_alloc &) {      \
+        return LBM_ERR_INVALID_ARG;       \
+    }                                     \
+    catch (...) {                         \
+        return LBM_ERR_INVALID_ARG;       \
+    }
+
+extern "C" {
+
+int lbm_params_default(lbm_params *p) {
+    if (!p) return LBM_ERR_INVALID_ARG;
+    std::memset(p, 0, sizeof(*p));
+    p->struct_size = sizeof(lbm_params);
+    p->mode = LBM_MODE_DEFF;
+    p->c_in = 1.0;
+    p->c_out = 0.0;
+    p->tau_ref = 1.0;
+    p->w0 = 0.25;
+    p->knudsen = 0;
+    p->T_K = 353.0;
+    p->p_atm = 1.0;
+    p->M_kg_mol = 0.032;
+    p->d_ionomer_rel = 1e-3;
+    p->d_ref_rel = 0.0;
+    p->k_lat = 0.0;
+    p->catalyst_phases = 1u << LBM_PT;
+    p->reactive_fluids = (1u << LBM_PORE) | (1u << LBM_IONOMER);
+    p->reservoir_plane = 1;
+    p->tol_change = 1e-8;
+    p->tol_flux = 1e-5;
+    p->tol_balance = 1e-3;
+    p->check_every = 1000;
+    p->max_steps = 50000000;
+    return LBM_OK;
+}
+
+int lbm_create(const lbm_grid *g, const uint8_t *phase, const lbm_params *p, lbm_solver **out) {
+    LBM_GUARD_BEGIN
+    if (!g || !phase || !p || !out) return LBM_ERR_INVALID_ARG;
+    *out = nullptr;
+    std::unique_ptr<cl::Engine> E;
+    const int st = cl::make_engine(1, g, &phase, p, E);
+    if (st != LBM_OK) return st;
+    auto *s = new lbm_solver;
+    s->E = std::move(E);
+    *out = s;
+    return LBM_OK;
+    LBM_GUARD_END
+}
+
+int lbm_get_info(const lbm_solver *s, lbm_info *info) {
+    if (!s || !info) return LBM_ERR_INVALID_ARG;
+    std::memset(info, 0, sizeof(*info));
+    s->E->info_of(0, *info);
+    return LBM_OK;
+}
+
+int lbm_get_host_fields(const lbm_solver *s, uint8_t *active, uint8_t *n_cat, float *omega) {
+    if (!s) return LBM_ERR_INVALID_ARG;
+    const cl::Prepared &p = s->E->P[0];
+    if (active) std::copy(p.active.begin(), p.active.end(), active);
+    if (n_cat) std::copy(p.n_cat.begin(), p.n_cat.end(), n_cat);
+    if (omega) std::copy(p.omega_dense.begin(), p.omega_dense.end(), omega);
+    return LBM_OK;
+}
+
+int lbm_workspace_bytes(const lbm_solver *s, size_t *bytes) {
+    if (!s || !bytes) return LBM_ERR_INVALID_ARG;
+    *bytes = s->E->ws_need;
+    return LBM_OK;
+}
+
+int lbm_bind(lbm_solver *s, void *ws, size_t bytes, void *stream) {
+    LBM_GUARD_BEGIN
+    if (!s || !ws) return LBM_ERR_INVALID_ARG;
+    if (bytes < s->E->ws_need || (reinterpret_cast<uintptr_t>(ws) % cl::kAlign) != 0) return LBM_ERR_WORKSPACE;
+    return cl::hip_status(s->E->bind(ws, bytes, static_cast<hipStream_t>(stream)));
+    LBM_GUARD_END
+}
+
+int lbm_set_initial_concentration(lbm_solver *s, const float *c_dev) {
+    LBM_GUARD_BEGIN
+    if (!s) return LBM_ERR_INVALID_ARG;
+    if (!s->E->bound) return LBM_ERR_UNBOUND;
+    cl::DeviceGuard dg(s->E->device);
+    return cl::hip_status(s->E->init(c_dev));
+    LBM_GUARD_END
+}
+
+int lbm_set_populations(lbm_solver *s, const float *f_dev) {
+    if (!s || !f_dev) return LBM_ERR_INVALID_ARG;
+    cl::Engine &E = *s->E;
+    if (!E.bound) return LBM_ERR_UNBOUND;
+    cl::DeviceGuard dg(E.device);
+    const int64_t N = (int64_t)E.P[0].nx * E.P[0].ny * E.P[0].nz;
+    return cl::hip_status(cl::launch_set_pop(E.L, E.conv_nblk, E.at<int2>(E.off_cblk), f_dev, E.at<int64_t>(E.off_dbase),
+                                             N, E.f[E.cur], E.st));
+}
+
+int lbm_get_populations(const lbm_solver *s, float *f_dev) {
+    if (!s || !f_dev) return LBM_ERR_INVALID_ARG;
+    const cl::Engine &E = *s->E;
+    if (!E.bound) return LBM_ERR_UNBOUND;
+    cl::DeviceGuard dg(E.device);
+    const int64_t N = (int64_t)E.P[0].nx * E.P[0].ny * E.P[0].nz;
+    hipError_t e = cl::launch_get_pop(E.L, E.conv_nblk, E.at<int2>(E.off_cblk), E.f[E.cur], E.at<int64_t>(E.off_dbase),
+                                      N, f_dev, E.st);
+    if (e == hipSuccess) e = hipStreamSynchronize(E.st);
+    return cl::hip_status(e);
+}
+
+int lbm_step(lbm_solver *s, int64_t n) {
+    if (!s || n < 0) return LBM_ERR_INVALID_ARG;
+    if (!s->E->bound) return LBM_ERR_UNBOUND;
+    cl::DeviceGuard dg(s->E->device);
+    cl::Engine &E = *s->E;
+    hipError_t e = E.all_live();
+    if (e == hipSuccess) e = E.steps(n);
+    E.rs[0].info.steps += n;
+    return cl::hip_status(e);
+}
+
+int lbm_measure(lbm_solver *s, lbm_run_info *info) {
+    if (!s || !info) return LBM_ERR_INVALID_ARG;
+    cl::Engine &E = *s->E;
+    if (!E.bound) return LBM_ERR_UNBOUND;
+    cl::DeviceGuard dg(E.device);
+    hipError_t e = E.all_live();
+    if (e == hipSuccess) e = E.measure_enqueue(0);
+    if (e == hipSuccess) e = E.read_results();
+    if (e != hipSuccess) return LBM_ERR_HIP;
+    E.fill_info(0, E.res_host, 0, E.rs[0].info);
+    E.rs[0].measured = 1;
+    *info = E.rs[0].info;
+    return E.res_host[cl::Q_BAD] > 0 ? LBM_ERR_DIVERGED : LBM_OK;
+}
+
+int lbm_run_to_steady(lbm_solver *s, lbm_run_info *info) {
+    LBM_GUARD_BEGIN
+    if (!s) return LBM_ERR_INVALID_ARG;
+    cl::DeviceGuard dg(s->E->device);
+    cl::Engine &E = *s->E;
+    if (!E.bound) return LBM_ERR_UNBOUND;
+    E.rs[0].done = 0;
+    if (E.all_live() != hipSuccess) return LBM_ERR_HIP;
+    lbm_run_info tmp{};
+    const int st = E.run(&tmp);
+    if (info) *info = tmp;
+    return st < 0 ? st : tmp.status;
+    LBM_GUARD_END
+}
+
+int lbm_deff(const lbm_solver *s, double *out) {
+    if (!s || !out) return LBM_ERR_INVALID_ARG;
+    return s->E->deff(0, out);
+}
+
+int lbm_reaction_rate(const lbm_solver *s, double *rate, double *jin) {
+    if (!s) return LBM_ERR_INVALID_ARG;
+    return s->E->rate(0, rate, jin);
+}
+
+int lbm_concentration(const lbm_solver *s, float *c_dev) {
+    if (!s || !c_dev) return LBM_ERR_INVALID_ARG;
+    const cl::Engine &E = *s->E;
+    if (!E.bound) return LBM_ERR_UNBOUND;
+    cl::DeviceGuard dg(E.device);
+    hipError_t e = cl::launch_conc(E.L, E.conv_nblk, E.at<int2>(E.off_cblk), E.react, E.f[E.cur],
+                                   E.at<int64_t>(E.off_dbase), c_dev, E.st);
+    if (e == hipSuccess) e = hipStreamSynchronize(E.st);
+    return cl::hip_status(e);
+}
+
+void lbm_destroy(lbm_solver *s) { delete s; }
+
+const char *lbm_last_error(void) { return cl::g_last_error; }
+
+const char *lbm_status_string(int st) {
+    switch (st) {
+        case LBM_OK: return "ok";
+        case LBM_NOT_CONVERGED: return "not converged";
+        case LBM_ERR_INVALID_ARG: return "invalid argument";
+        case LBM_ERR_BAD_PHASE: return "phase id outside 0..3";
+        case LBM_ERR_WRONG_MODE: return "wrong mode for this output";
+        case LBM_ERR_NO_PERCOLATION: return "no transport path between the Dirichlet faces";
+        case LBM_ERR_DIVERGED: return "diverged (NaN or Inf)";
+        case LBM_ERR_HIP: return "HIP runtime error";
+        case LBM_ERR_UNBOUND: return "no workspace bound or nothing measured yet";
+        case LBM_ERR_WORKSPACE: return "workspace too small or misaligned";
+        case LBM_ERR_UNSTABLE: return "unstable parameters (k n >= 1 or tau <= 1/2)";
+        default: return "unknown status";
+    }
+}
+
+// ------------------------------------------------------------------ batched form
+
+int lbm_batch_create(int32_t n, const lbm_grid *grids, const uint8_t *const *phases, const lbm_params *params,
+                     lbm_batch **out) {
+    LBM_GUARD_BEGIN
+    if (!out) return LBM_ERR_INVALID_ARG;
+    *out = nullptr;
+    std::unique_ptr<cl::Engine> E;
+    const int st = cl::make_engine(n, grids, phases, params, E);
+    if (st != LBM_OK) return st;
+    auto *b = new lbm_batch;
+    b->E = std::move(E);
+    *out = b;
+    return LBM_OK;
+    LBM_GUARD_END
+}
+
+int lbm_batch_workspace_bytes(const lbm_batch *b, size_t *bytes) {
+    if (!b || !bytes) return LBM_ERR_INVALID_ARG;
+    *bytes = b->E->ws_need;
+    return LBM_OK;
+}
+
+int lbm_batch_bind(lbm_batch *b, void *ws, size_t bytes, void *stream) {
+    LBM_GUARD_BEGIN
+    if (!b || !ws) return LBM_ERR_INVALID_ARG;
+    if (bytes < b->E->ws_need || (reinterpret_cast<uintptr_t>(ws) % cl::kAlign) != 0) return LBM_ERR_WORKSPACE;
+    return cl::hip_status(b->E->bind(ws, bytes, static_cast<hipStream_t>(stream)));
+    LBM_GUARD_END
+}
+
+int lbm_batch_set_tiling(lbm_batch *b, int32_t spw, int32_t waves, int32_t xcd) {
+    if (!b) return LBM_ERR_INVALID_ARG;
+    if (!(spw == 1 || spw == 2 || spw == 4) || !(waves == 1 || waves == 2 || waves == 4 || waves == 8))
+        return LBM_ERR_INVALID_ARG;
+    cl::Engine &E = *b->E;
+    E.spw = spw;
+    E.waves = waves;
+    E.xcd = xcd ? 1 : 0;
+    if (E.bound) {
+        cl::DeviceGuard dg(E.device);
+        return cl::hip_status(E.upload_tables());
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_get_tiling(const lbm_batch *b, int32_t *spw, int32_t *waves, int32_t *xcd) {
+    if (!b) return LBM_ERR_INVALID_ARG;
+    if (spw) *spw = b->E->spw;
+    if (waves) *waves = b->E->waves;
+    if (xcd) *xcd = b->E->xcd;
+    return LBM_OK;
+}
+
+int lbm_batch_autotune(lbm_batch *b, int32_t steps_per_trial, double *ms_best) {
+    LBM_GUARD_BEGIN
+    if (!b || steps_per_trial < 2) return LBM_ERR_INVALID_ARG;
+    cl::Engine &E = *b->E;
+    if (!E.bound) return LBM_ERR_UNBOUND;
+    cl::DeviceGuard dg(E.device);
+    if (steps_per_trial & 1) ++steps_per_trial;  // even: the state stays in its lattice
+    // Trial steps are ordinary solver steps: they advance every live instance toward
+    // its steady state, so nothing has to be saved or restored.
+    hipError_t e = hipSuccess;
+    int64_t trial_steps = 0;
+    hipEvent_t t0, t1;
+    if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) return LBM_ERR_HIP;
+    const int spws[3] = {1, 2, 4};
+    const int wavs[4] = {1, 2, 4, 8};
+    double best = 1e300;
+    int bs = E.spw, bw = E.waves, bx = E.xcd;
+    for (int xi = 0; xi < 2 && e == hipSuccess; ++xi)
+        for (int si = 0; si < 3 && e == hipSuccess; ++si)
+            for (int wi = 0; wi < 4 && e == hipSuccess; ++wi) {
+                E.spw = spws[si];
+                E.waves = wavs[wi];
+                E.xcd = xi;
+                if ((e = E.upload_tables()) != hipSuccess) break;
+                if ((e = E.steps(2)) != hipSuccess) break;  // warm-up
+                if ((e = hipEventRecord(t0, E.st)) != hipSuccess) break;
+                if ((e = E.steps(steps_per_trial)) != hipSuccess) break;
+                trial_steps += steps_per_trial + 2;
+                if ((e = hipEventRecord(t1, E.st)) != hipSuccess) break;
+                if ((e = hipEventSynchronize(t1)) != hipSuccess) break;
+                float ms = 0.f;
+                if ((e = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess) break;
+                const double per = ms / steps_per_trial;
+                if (per < best) {
+                    best = per;
+                    bs = E.spw;
+                    bw = E.waves;
+                    bx = E.xcd;
+                }
+            }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    E.spw = bs;
+    E.waves = bw;
+    E.xcd = bx;
+    if (e == hipSuccess) e = E.upload_tables();
+    for (int i : E.live) E.rs[i].info.steps += trial_steps;
+    if (ms_best) *ms_best = best;
+    return cl::hip_status(e);
+    LBM_GUARD_END
+}
+
+int lbm_batch_run(lbm_batch *b, lbm_run_info *infos) {
+    LBM_GUARD_BEGIN
+    if (!b) return LBM_ERR_INVALID_ARG;
+    cl::DeviceGuard dg(b->E->device);
+    return b->E->run(infos);
+    LBM_GUARD_END
+}
+
+int lbm_batch_deff(const lbm_batch *b, int32_t i, double *out) {
+    if (!b || !out || i < 0 || i >= b->E->ninst) return LBM_ERR_INVALID_ARG;
+    return b->E->deff(i, out);
+}
+
+int lbm_batch_reaction_rate(const lbm_batch *b, int32_t i, double *rate, double *jin) {
+    if (!b || i < 0 || i >= b->E->ninst) return LBM_ERR_INVALID_ARG;
+    return b->E->rate(i, rate, jin);
+}
+
+int lbm_batch_get_info(const lbm_batch *b, int32_t i, lbm_info *info) {
+    if (!b || !info || i < 0 || i >= b->E->ninst) return LBM_ERR_INVALID_ARG;
+    std::memset(info, 0, sizeof(*info));
+    b->E->info_of(i, *info);
+    return LBM_OK;
+}
+
+void lbm_batch_destroy(lbm_batch *b) { delete b; }
+
+}  // extern "C"

@@ -1,0 +1,71 @@
+// Device data structures and launch entry points of the D3Q7 kernels (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace cl {
+
+// Per-instance constants, device resident (one entry per structure of a batch).
+struct alignas(64) InstDev {
+    int32_t nx, ny, nz, nsx;  // simulated grid, segments per row
+    int64_t seg_base;         // first global segment of the instance
+    int64_t nseg;             // segments of the instance
+    // Stored populations are g_i = f_i - w_i c_sh(x) with c_sh(x) = sh0 - slope * x
+    // (the linear empty-box profile for Dirichlet problems, a constant when reacting).
+    double sh0, slope;
+    double pull_dx;           // w1 * slope: added to a population pulled from x - 1
+    double abb_in;            // 2 w1 (c_in - c_sh(0)): anti-bounce-back at x = 0
+    double abb_out;           // 2 w1 (c_out - c_sh(nx - 1)): anti-bounce-back at x = nx
+    double k;                 // first-order rate per catalyst face
+    double w0, w1;            // rest and moving weights
+    float om_pore, om_ion;    // relaxation rates when not stored per voxel
+};
+
+// Device views of the workspace.
+struct Lattice {
+    const uint64_t *m_fluid, *m_ion, *m_react, *m_cat;  // per segment bitmasks
+    const uint32_t *prefix;   // global compact index of the first fluid voxel of a segment
+    const float *omega;       // per fluid voxel 1/tau (Knudsen problems), else null
+    const InstDev *inst;
+    int64_t stride;           // elements per population array
+};
+
+// Quantities reduced per instance, in this order.
+enum { Q_JIN = 0, Q_JOUT, Q_JINT, Q_RATE, Q_MASS, Q_DCMAX, Q_CMAX, Q_BAD, NQ };
+
+struct StepLaunch {
+    int32_t waves;        // waves per workgroup: 1, 2, 4, 8
+    int32_t spw;          // segments per wave: 1, 2, 4
+    int32_t xcd;          // XCD-aware block order
+    int32_t nblk;         // workgroups
+    const int2 *blk;      // per workgroup: {instance, first local segment}
+};
+
+struct MeasureLaunch {
+    int32_t nblk;
+    const int4 *blk;      // per workgroup: {instance, block within instance, blocks of instance, partial slot}
+    double *partial;      // [nblk][NQ]
+    int32_t update_snap;
+    float *csnap;         // per fluid voxel concentration snapshot
+};
+
+hipError_t launch_step(const Lattice &L, const StepLaunch &S, bool knudsen, bool react, const float *fin,
+                       float *fout, hipStream_t st);
+hipError_t launch_measure(const Lattice &L, const MeasureLaunch &M, bool react, const float *f, hipStream_t st);
+// results[i*NQ + q] from partials of blocks [base_i, base_i + count_i): ranges[i] = {base, count}
+hipError_t launch_finish(const double *partial, const int2 *ranges, int32_t ninst, double *results, hipStream_t st);
+
+// dense <-> compact conversions over all segments of the listed instances
+// (blk as for the step kernel with waves = 4, spw = 1)
+hipError_t launch_init_eq(const Lattice &L, int32_t nblk, const int2 *blk, bool react, const float *c_dense,
+                          const int64_t *dense_base, float *f, float *csnap, hipStream_t st);
+hipError_t launch_set_pop(const Lattice &L, int32_t nblk, const int2 *blk, const float *f_dense,
+                          const int64_t *dense_base, int64_t dense_stride, float *f, hipStream_t st);
+hipError_t launch_get_pop(const Lattice &L, int32_t nblk, const int2 *blk, const float *f,
+                          const int64_t *dense_base, int64_t dense_stride, float *f_dense, hipStream_t st);
+hipError_t launch_conc(const Lattice &L, int32_t nblk, const int2 *blk, bool react, const float *f,
+                       const int64_t *dense_base, float *c_dense, hipStream_t st);
+
+}  // namespace cl

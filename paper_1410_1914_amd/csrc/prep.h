@@ -1,0 +1,44 @@
+// Host-side preprocessing of a catalyst-layer structure into the per-segment
+// bitmasks and compact per-fluid-voxel arrays the stream-collide kernels read.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "../../include/lbm.h"
+
+namespace cl {
+
+constexpr int kSeg = 64;  // voxels per row segment = one wave64, one 64-bit mask word
+
+struct Prepared {
+    lbm_params params{};
+    int mode = 0;
+    bool knudsen = false;
+    int nx = 0, ny = 0, nz = 0;  // simulated grid
+    int nx_struct = 0;
+    int nsx = 0;                 // segments per row
+    int64_t nseg = 0;
+    int64_t n_fluid = 0;
+    bool percolates = false;
+    double d0 = 0, d_ref = 0, d0_lat = 0;
+    double sh0 = 0, slope = 0;   // stored populations are shifted by w_i (sh0 - slope * x)
+    double w0 = 0.25, w1 = 0.125;
+    float om_pore = 1.f, om_ion = 1.f;  // relaxation rates when not per voxel
+    // dense over the simulated grid
+    std::vector<uint8_t> active, n_cat;
+    std::vector<float> omega_dense;
+    // per segment
+    std::vector<uint64_t> m_fluid, m_ion, m_react, m_cat;
+    std::vector<uint32_t> prefix;  // compact index of the first fluid voxel of the segment
+    // compact (fluid voxels in x-fastest order)
+    std::vector<float> omega_c;
+};
+
+// Returns an LBM_* status.
+int prepare(const lbm_grid &g, const uint8_t *phase, const lbm_params &p, Prepared &out);
+
+// 13-direction averaged pore size (voxel edges) of every voxel of `pore`.
+void pore_size_13(int nx, int ny, int nz, const uint8_t *pore, std::vector<double> &dp);
+
+}  // namespace cl

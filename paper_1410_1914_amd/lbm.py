@@ -1,0 +1,480 @@
+"""Python binding of the C ABI in ``include/lbm.h`` (ctypes; argument marshalling only).
+
+Every function keeps the C name and meaning; negative status codes raise
+``LbmError``.  Device memory and streams come from PyTorch (``Solver`` and
+``Batch`` below allocate the workspace as a torch tensor and run on a torch
+stream); all solver arithmetic runs in the HIP library ``_liblbm.so``.  There is
+no CPU fallback: without the built library or a GPU these calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_liblbm.so")
+
+PORE, CARBON, PT, IONOMER = 0, 1, 2, 3
+MODE_DEFF, MODE_REACT, MODE_PROTON = 0, 1, 2
+OK, NOT_CONVERGED = 0, 1
+ERR_INVALID_ARG, ERR_BAD_PHASE, ERR_WRONG_MODE, ERR_NO_PERCOLATION = -1, -2, -3, -4
+ERR_DIVERGED, ERR_HIP, ERR_UNBOUND, ERR_WORKSPACE, ERR_UNSTABLE = -5, -6, -7, -8, -9
+
+c_int32, c_int64, c_double, c_uint32, c_uint8, c_float = (ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
+                                                          ctypes.c_uint32, ctypes.c_uint8, ctypes.c_float)
+
+
+class lbm_grid(ctypes.Structure):
+    _fields_ = [("nx", c_int32), ("ny", c_int32), ("nz", c_int32), ("voxel_m", c_double)]
+
+
+class lbm_params(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", c_uint32), ("mode", c_int32),
+        ("c_in", c_double), ("c_out", c_double), ("tau_ref", c_double), ("w0", c_double),
+        ("knudsen", c_int32),
+        ("T_K", c_double), ("p_atm", c_double), ("M_kg_mol", c_double),
+        ("d_ionomer_rel", c_double), ("d_ref_rel", c_double), ("k_lat", c_double),
+        ("catalyst_phases", c_uint32), ("reactive_fluids", c_uint32),
+        ("reservoir_plane", c_int32),
+        ("tol_change", c_double), ("tol_flux", c_double), ("tol_balance", c_double),
+        ("check_every", c_int32), ("max_steps", c_int64),
+    ]
+
+
+class lbm_run_info(ctypes.Structure):
+    _fields_ = [("steps", c_int64), ("residual", c_double), ("j_in", c_double), ("j_out", c_double),
+                ("j_vol", c_double), ("rate", c_double), ("mass", c_double), ("est_error", c_double),
+                ("status", c_int32), ("checks", c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class lbm_info(ctypes.Structure):
+    _fields_ = [("nx", c_int32), ("ny", c_int32), ("nz", c_int32), ("nx_struct", c_int32),
+                ("n_active", c_int64), ("n_segments", c_int64),
+                ("d0", c_double), ("d_ref", c_double), ("d0_lat", c_double),
+                ("percolates", c_int32), ("mode", c_int32)]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, fn, status):
+        detail = lbm_last_error() if status == ERR_HIP else ""
+        super().__init__(f"{fn}: {lbm_status_string(status)} ({status}) {detail}".rstrip())
+        self.status = status
+
+
+_lib = None
+_P = ctypes.c_void_p
+_PP = ctypes.POINTER(ctypes.c_void_p)
+
+# name -> (argtypes, restype); every C symbol declared in include/lbm.h
+SIGNATURES = {
+    "lbm_params_default": ([ctypes.POINTER(lbm_params)], c_int32),
+    "lbm_create": ([ctypes.POINTER(lbm_grid), ctypes.POINTER(c_uint8), ctypes.POINTER(lbm_params), _PP], c_int32),
+    "lbm_get_info": ([_P, ctypes.POINTER(lbm_info)], c_int32),
+    "lbm_get_host_fields": ([_P, ctypes.POINTER(c_uint8), ctypes.POINTER(c_uint8), ctypes.POINTER(c_float)], c_int32),
+    "lbm_workspace_bytes": ([_P, ctypes.POINTER(ctypes.c_size_t)], c_int32),
+    "lbm_bind": ([_P, _P, ctypes.c_size_t, _P], c_int32),
+    "lbm_set_initial_concentration": ([_P, _P], c_int32),
+    "lbm_set_populations": ([_P, _P], c_int32),
+    "lbm_get_populations": ([_P, _P], c_int32),
+    "lbm_step": ([_P, c_int64], c_int32),
+    "lbm_measure": ([_P, ctypes.POINTER(lbm_run_info)], c_int32),
+    "lbm_run_to_steady": ([_P, ctypes.POINTER(lbm_run_info)], c_int32),
+    "lbm_deff": ([_P, ctypes.POINTER(c_double)], c_int32),
+    "lbm_reaction_rate": ([_P, ctypes.POINTER(c_double), ctypes.POINTER(c_double)], c_int32),
+    "lbm_concentration": ([_P, _P], c_int32),
+    "lbm_destroy": ([_P], None),
+    "lbm_status_string": ([c_int32], ctypes.c_char_p),
+    "lbm_last_error": ([], ctypes.c_char_p),
+    "lbm_batch_create": ([c_int32, ctypes.POINTER(lbm_grid), ctypes.POINTER(ctypes.POINTER(c_uint8)),
+                          ctypes.POINTER(lbm_params), _PP], c_int32),
+    "lbm_batch_workspace_bytes": ([_P, ctypes.POINTER(ctypes.c_size_t)], c_int32),
+    "lbm_batch_bind": ([_P, _P, ctypes.c_size_t, _P], c_int32),
+    "lbm_batch_set_tiling": ([_P, c_int32, c_int32, c_int32], c_int32),
+    "lbm_batch_get_tiling": ([_P, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32), ctypes.POINTER(c_int32)], c_int32),
+    "lbm_batch_autotune": ([_P, c_int32, ctypes.POINTER(c_double)], c_int32),
+    "lbm_batch_run": ([_P, ctypes.POINTER(lbm_run_info)], c_int32),
+    "lbm_batch_deff": ([_P, c_int32, ctypes.POINTER(c_double)], c_int32),
+    "lbm_batch_reaction_rate": ([_P, c_int32, ctypes.POINTER(c_double), ctypes.POINTER(c_double)], c_int32),
+    "lbm_batch_get_info": ([_P, c_int32, ctypes.POINTER(lbm_info)], c_int32),
+    "lbm_batch_destroy": ([_P], None),
+}
+
+
+def load():
+    """Load ``_liblbm.so``; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        # torch first: the library then binds to the HIP runtime torch already
+        # loaded, so both share one runtime (device pointers and streams agree)
+        import torch  # noqa: F401
+
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library missing: {LIB_PATH} (run paper_1410_1914_amd.build)")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = lib
+    return _lib
+
+
+def require_gpu():
+    """Raise unless the HIP library is built and a GPU is visible."""
+    load()
+    import torch
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: the solver has no CPU path")
+
+
+def _check(fn, st):
+    if st < 0:
+        raise LbmError(fn, st)
+    return st
+
+
+def lbm_status_string(status: int) -> str:
+    return load().lbm_status_string(status).decode()
+
+
+def lbm_last_error() -> str:
+    return load().lbm_last_error().decode()
+
+
+def lbm_params_default(**overrides) -> lbm_params:
+    p = lbm_params()
+    _check("lbm_params_default", load().lbm_params_default(ctypes.byref(p)))
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+def lbm_create(phase: np.ndarray, params: lbm_params, voxel_m: float = 2e-9):
+    ph = np.ascontiguousarray(phase, dtype=np.uint8)
+    if ph.ndim != 3:
+        raise ValueError("phase map must be (nz, ny, nx)")
+    nz, ny, nx = ph.shape
+    g = lbm_grid(nx, ny, nz, voxel_m)
+    h = ctypes.c_void_p()
+    _check("lbm_create", load().lbm_create(ctypes.byref(g), ph.ctypes.data_as(ctypes.POINTER(c_uint8)),
+                                           ctypes.byref(params), ctypes.byref(h)))
+    return h
+
+
+def lbm_get_info(h) -> lbm_info:
+    i = lbm_info()
+    _check("lbm_get_info", load().lbm_get_info(h, ctypes.byref(i)))
+    return i
+
+
+def lbm_get_host_fields(h):
+    i = lbm_get_info(h)
+    shape = (i.nz, i.ny, i.nx)
+    act = np.zeros(shape, np.uint8)
+    ncat = np.zeros(shape, np.uint8)
+    om = np.zeros(shape, np.float32)
+    _check("lbm_get_host_fields", load().lbm_get_host_fields(
+        h, act.ctypes.data_as(ctypes.POINTER(c_uint8)), ncat.ctypes.data_as(ctypes.POINTER(c_uint8)),
+        om.ctypes.data_as(ctypes.POINTER(c_float))))
+    return act, ncat, om
+
+
+def lbm_workspace_bytes(h) -> int:
+    n = ctypes.c_size_t()
+    _check("lbm_workspace_bytes", load().lbm_workspace_bytes(h, ctypes.byref(n)))
+    return n.value
+
+
+def lbm_bind(h, workspace_ptr: int, nbytes: int, stream_handle: int):
+    return _check("lbm_bind", load().lbm_bind(h, workspace_ptr, nbytes, stream_handle or None))
+
+
+def lbm_set_initial_concentration(h, c_ptr):
+    return _check("lbm_set_initial_concentration", load().lbm_set_initial_concentration(h, c_ptr or None))
+
+
+def lbm_set_populations(h, f_ptr):
+    return _check("lbm_set_populations", load().lbm_set_populations(h, f_ptr))
+
+
+def lbm_get_populations(h, f_ptr):
+    return _check("lbm_get_populations", load().lbm_get_populations(h, f_ptr))
+
+
+def lbm_step(h, n: int):
+    return _check("lbm_step", load().lbm_step(h, n))
+
+
+def lbm_measure(h) -> lbm_run_info:
+    r = lbm_run_info()
+    _check("lbm_measure", load().lbm_measure(h, ctypes.byref(r)))
+    return r
+
+
+def lbm_run_to_steady(h):
+    r = lbm_run_info()
+    st = load().lbm_run_to_steady(h, ctypes.byref(r))
+    if st < 0 and st != ERR_NO_PERCOLATION:
+        raise LbmError("lbm_run_to_steady", st)
+    return st, r
+
+
+def lbm_deff(h):
+    v = c_double()
+    st = load().lbm_deff(h, ctypes.byref(v))
+    if st < 0 and st != ERR_NO_PERCOLATION:
+        raise LbmError("lbm_deff", st)
+    return st, v.value
+
+
+def lbm_reaction_rate(h):
+    r, j = c_double(), c_double()
+    st = _check("lbm_reaction_rate", load().lbm_reaction_rate(h, ctypes.byref(r), ctypes.byref(j)))
+    return st, r.value, j.value
+
+
+def lbm_concentration(h, c_ptr):
+    return _check("lbm_concentration", load().lbm_concentration(h, c_ptr))
+
+
+def lbm_destroy(h):
+    if h:
+        load().lbm_destroy(h)
+
+
+def lbm_batch_create(phases, params_list, voxel_m: float = 2e-9):
+    n = len(phases)
+    grids = (lbm_grid * n)()
+    arrs = [np.ascontiguousarray(p, dtype=np.uint8) for p in phases]
+    ptrs = (ctypes.POINTER(c_uint8) * n)()
+    for i, a in enumerate(arrs):
+        nz, ny, nx = a.shape
+        grids[i] = lbm_grid(nx, ny, nz, voxel_m)
+        ptrs[i] = a.ctypes.data_as(ctypes.POINTER(c_uint8))
+    pars = (lbm_params * n)(*params_list)
+    h = ctypes.c_void_p()
+    _check("lbm_batch_create", load().lbm_batch_create(n, grids, ptrs, pars, ctypes.byref(h)))
+    return h
+
+
+def lbm_batch_workspace_bytes(h) -> int:
+    n = ctypes.c_size_t()
+    _check("lbm_batch_workspace_bytes", load().lbm_batch_workspace_bytes(h, ctypes.byref(n)))
+    return n.value
+
+
+def lbm_batch_bind(h, workspace_ptr, nbytes, stream_handle):
+    return _check("lbm_batch_bind", load().lbm_batch_bind(h, workspace_ptr, nbytes, stream_handle or None))
+
+
+def lbm_batch_set_tiling(h, segs_per_wave, waves_per_block, xcd_remap):
+    return _check("lbm_batch_set_tiling", load().lbm_batch_set_tiling(h, segs_per_wave, waves_per_block, xcd_remap))
+
+
+def lbm_batch_get_tiling(h):
+    a, b, c = c_int32(), c_int32(), c_int32()
+    _check("lbm_batch_get_tiling", load().lbm_batch_get_tiling(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def lbm_batch_autotune(h, steps_per_trial: int = 20):
+    ms = c_double()
+    _check("lbm_batch_autotune", load().lbm_batch_autotune(h, steps_per_trial, ctypes.byref(ms)))
+    return ms.value
+
+
+def lbm_batch_run(h, n: int):
+    infos = (lbm_run_info * n)()
+    st = load().lbm_batch_run(h, infos)
+    if st < 0 and st != ERR_NO_PERCOLATION:
+        raise LbmError("lbm_batch_run", st)
+    return st, list(infos)
+
+
+def lbm_batch_deff(h, i: int):
+    v = c_double()
+    st = load().lbm_batch_deff(h, i, ctypes.byref(v))
+    if st < 0 and st != ERR_NO_PERCOLATION:
+        raise LbmError("lbm_batch_deff", st)
+    return st, v.value
+
+
+def lbm_batch_reaction_rate(h, i: int):
+    r, j = c_double(), c_double()
+    st = _check("lbm_batch_reaction_rate", load().lbm_batch_reaction_rate(h, i, ctypes.byref(r), ctypes.byref(j)))
+    return st, r.value, j.value
+
+
+def lbm_batch_get_info(h, i: int) -> lbm_info:
+    o = lbm_info()
+    _check("lbm_batch_get_info", load().lbm_batch_get_info(h, i, ctypes.byref(o)))
+    return o
+
+
+def lbm_batch_destroy(h):
+    if h:
+        load().lbm_batch_destroy(h)
+
+
+# ---------------------------------------------------------------- torch plumbing
+
+class Solver:
+    """One structure: a workspace tensor and a stream from torch, the rest in HIP."""
+
+    def __init__(self, phase: np.ndarray, params: lbm_params | None = None, voxel_m: float = 2e-9,
+                 device: str = "cuda", stream=None, **overrides):
+        import torch
+
+        require_gpu()
+        self.params = params if params is not None else lbm_params_default()
+        for k, v in overrides.items():
+            setattr(self.params, k, v)
+        self.h = lbm_create(phase, self.params, voxel_m)
+        self.info = lbm_get_info(self.h)
+        self.nbytes = lbm_workspace_bytes(self.h)
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        self.ws = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        self.ws_ptr = (base + 255) // 256 * 256
+        torch.cuda.synchronize(self.device)
+        with torch.cuda.device(self.device):
+            lbm_bind(self.h, self.ws_ptr, self.nbytes, self.stream.cuda_stream)
+
+    @property
+    def shape(self):
+        return (self.info.nz, self.info.ny, self.info.nx)
+
+    @property
+    def N(self):
+        return self.info.nx * self.info.ny * self.info.nz
+
+    def _sync_in(self, t):
+        # work queued by torch on its current stream must finish before the solver's stream reads t
+        import torch
+
+        torch.cuda.current_stream(self.device).synchronize()
+        return t
+
+    def set_initial_concentration(self, c=None):
+        import torch
+
+        if c is None:
+            return lbm_set_initial_concentration(self.h, None)
+        c = torch.as_tensor(c, dtype=torch.float32, device=self.device).contiguous()
+        assert c.numel() == self.N
+        self._sync_in(c)
+        st = lbm_set_initial_concentration(self.h, c.data_ptr())
+        self.stream.synchronize()
+        return st
+
+    def set_populations(self, f):
+        import torch
+
+        f = torch.as_tensor(f, dtype=torch.float32, device=self.device).contiguous()
+        assert f.numel() == 7 * self.N
+        self._sync_in(f)
+        st = lbm_set_populations(self.h, f.data_ptr())
+        self.stream.synchronize()
+        return st
+
+    def populations(self):
+        import torch
+
+        out = torch.empty((7,) + self.shape, dtype=torch.float32, device=self.device)
+        self._sync_in(out)
+        lbm_get_populations(self.h, out.data_ptr())
+        return out
+
+    def concentration(self):
+        import torch
+
+        out = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+        self._sync_in(out)
+        lbm_concentration(self.h, out.data_ptr())
+        return out
+
+    def step(self, n=1):
+        return lbm_step(self.h, n)
+
+    def measure(self):
+        return lbm_measure(self.h)
+
+    def run_to_steady(self):
+        return lbm_run_to_steady(self.h)
+
+    def deff(self):
+        return lbm_deff(self.h)
+
+    def reaction_rate(self):
+        return lbm_reaction_rate(self.h)
+
+    def host_fields(self):
+        return lbm_get_host_fields(self.h)
+
+    def close(self):
+        lbm_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lbm_destroy(self.h)
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many structures solved together (one launch per step over all live instances)."""
+
+    def __init__(self, phases, params_list, voxel_m: float = 2e-9, device: str = "cuda", stream=None):
+        import torch
+
+        require_gpu()
+        self.n = len(phases)
+        self.h = lbm_batch_create(phases, params_list, voxel_m)
+        self.nbytes = lbm_batch_workspace_bytes(self.h)
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        self.ws = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
+        self.ws_ptr = (self.ws.data_ptr() + 255) // 256 * 256
+        torch.cuda.synchronize(self.device)
+        with torch.cuda.device(self.device):
+            lbm_batch_bind(self.h, self.ws_ptr, self.nbytes, self.stream.cuda_stream)
+
+    def set_tiling(self, spw, waves, xcd):
+        return lbm_batch_set_tiling(self.h, spw, waves, xcd)
+
+    def tiling(self):
+        return lbm_batch_get_tiling(self.h)
+
+    def autotune(self, steps_per_trial=20):
+        return lbm_batch_autotune(self.h, steps_per_trial)
+
+    def run(self):
+        return lbm_batch_run(self.h, self.n)
+
+    def deff(self, i):
+        return lbm_batch_deff(self.h, i)
+
+    def reaction_rate(self, i):
+        return lbm_batch_reaction_rate(self.h, i)
+
+    def info(self, i):
+        return lbm_batch_get_info(self.h, i)
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lbm_batch_destroy(self.h)
+        except Exception:
+            pass

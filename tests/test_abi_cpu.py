@@ -1,0 +1,143 @@
+"""C ABI on the CPU: the library loads, exports every declared symbol, and its host
+preprocessing matches the oracle bit for bit (no device call is made here)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import structgen as sg
+from oracle import lbm as O
+from paper_1410_1914_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared(header):
+    text = open(os.path.join(ROOT, "include", header)).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_\w+|unet_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = lbm.load()
+    names = _declared("lbm.h")
+    assert len(names) >= 25
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(lbm.SIGNATURES)
+
+
+def test_params_default_and_status_strings():
+    p = lbm.lbm_params_default()
+    assert p.struct_size == 200 or p.struct_size == __import__("ctypes").sizeof(lbm.lbm_params)
+    assert p.w0 == 0.25 and p.tau_ref == 1.0 and p.check_every % 2 == 0
+    for st in (0, 1, -1, -2, -3, -4, -5, -6, -7, -8, -9):
+        assert lbm.lbm_status_string(st)
+    assert lbm.lbm_status_string(12345) == "unknown status"
+
+
+CASES = [
+    ("pt", 1, (9, 10, 70), dict(knudsen=1)),
+    ("pt", 4, (8, 6, 130), dict(knudsen=1, d_ionomer_rel=0.05)),
+    ("pt", 8, (5, 6, 10), dict(knudsen=0)),
+    ("npmc", 2, (12, 12, 65), dict(knudsen=1, voxel_m=1e-9)),
+    ("two", 3, (16, 16, 32), dict(knudsen=0, tau_ref=0.8)),
+]
+
+
+def _phase(kind, seed, shape):
+    if kind == "pt":
+        return sg.pt_cl(seed, shape=shape)
+    if kind == "npmc":
+        return sg.npmc_cl(seed, shape=shape, meso_d=(3, 6))
+    return sg.two_phase(seed, shape=shape)
+
+
+@pytest.mark.parametrize("kind,seed,shape,kw", CASES)
+@pytest.mark.parametrize("mode", [lbm.MODE_DEFF, lbm.MODE_REACT, lbm.MODE_PROTON])
+def test_host_preprocessing_matches_oracle(kind, seed, shape, kw, mode):
+    ph = _phase(kind, seed, shape)
+    voxel = kw.get("voxel_m", 2e-9)
+    cat = (1 << lbm.PT) | (1 << lbm.CARBON) if kind == "npmc" else (1 << lbm.PT)
+    p = lbm.lbm_params_default(mode=mode, k_lat=0.05, catalyst_phases=cat,
+                               **{k: v for k, v in kw.items() if k != "voxel_m"})
+    h = lbm.lbm_create(ph, p, voxel)
+    try:
+        info = lbm.lbm_get_info(h)
+        act, ncat, om = lbm.lbm_get_host_fields(h)
+    finally:
+        lbm.lbm_destroy(h)
+    op = O.Params(mode=mode, knudsen=bool(kw.get("knudsen")), voxel_m=voxel, k_lat=0.05, catalyst_phases=cat,
+                  tau_ref=kw.get("tau_ref", 1.0), d_ionomer_rel=kw.get("d_ionomer_rel", 1e-3))
+    prob = O.prepare(ph, op)
+    assert (info.nz, info.ny, info.nx) == prob.active.shape
+    assert np.array_equal(act.astype(bool), prob.active)          # index work: bit exact
+    assert np.array_equal(ncat.astype(np.int64), prob.n_cat)
+    assert info.n_active == int(prob.active.sum())
+    assert bool(info.percolates) == prob.percolates
+    assert info.d_ref == pytest.approx(prob.D_ref, rel=1e-15)
+    assert info.d0 == pytest.approx(prob.D0, rel=1e-15)
+    assert info.d0_lat == pytest.approx(O.d0_lattice(prob), rel=1e-14)
+    # relaxation rates: FP32 rounding of the FP64 value
+    assert np.array_equal(om, prob.omega.astype(np.float32))
+
+
+def test_pore_size_matches_oracle_on_knudsen_structure():
+    """The library's run-length chord scan and the oracle's per-voxel walk agree
+    (checked through 1/tau, which is a strictly monotone function of d_p here)."""
+    ph = sg.npmc_cl(5, shape=(20, 18, 40), meso_d=(4, 8))
+    p = lbm.lbm_params_default(knudsen=1, d_ionomer_rel=1e-3)
+    h = lbm.lbm_create(ph, p, 1e-9)
+    _, _, om = lbm.lbm_get_host_fields(h)
+    lbm.lbm_destroy(h)
+    prob = O.prepare(ph, O.Params(knudsen=True, voxel_m=1e-9))
+    assert np.array_equal(om, prob.omega.astype(np.float32))
+
+
+def test_error_codes():
+    ph = np.zeros((4, 4, 8), np.uint8)
+    bad = ph.copy()
+    bad[0, 0, 0] = 7
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create(bad, lbm.lbm_params_default())
+    assert e.value.status == lbm.ERR_BAD_PHASE
+    for kw in (dict(tau_ref=0.5), dict(w0=0.0), dict(check_every=3), dict(k_lat=-1.0), dict(struct_size=4),
+               dict(mode=7)):
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.lbm_create(ph, lbm.lbm_params_default(**kw))
+        assert e.value.status == lbm.ERR_INVALID_ARG, kw
+    cat = np.zeros((4, 2, 8), np.uint8)
+    cat[:, 0, :] = lbm.PT  # the fluid row has Pt on both y sides: n = 2
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create(cat, lbm.lbm_params_default(mode=lbm.MODE_REACT, k_lat=0.6))  # k n = 1.2 >= 1
+    assert e.value.status == lbm.ERR_UNSTABLE
+    h = lbm.lbm_create(ph, lbm.lbm_params_default())
+    try:
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.lbm_step(h, 1)
+        assert e.value.status == lbm.ERR_UNBOUND
+        st, _ = lbm.lbm_deff(h)
+        assert st == lbm.ERR_UNBOUND or st == lbm.ERR_NO_PERCOLATION
+    except lbm.LbmError as err:
+        assert err.status == lbm.ERR_UNBOUND
+    finally:
+        lbm.lbm_destroy(h)
+    lbm.lbm_destroy(None)
+
+
+def test_no_percolation_flag():
+    ph = np.zeros((3, 3, 8), np.uint8)
+    ph[:, :, 4] = lbm.CARBON
+    h = lbm.lbm_create(ph, lbm.lbm_params_default())
+    assert lbm.lbm_get_info(h).percolates == 0
+    lbm.lbm_destroy(h)
+
+
+def test_segment_count_and_reservoir_plane():
+    ph = sg.pt_cl(2, shape=(4, 5, 130))
+    h = lbm.lbm_create(ph, lbm.lbm_params_default(mode=lbm.MODE_REACT, k_lat=0.01))
+    i = lbm.lbm_get_info(h)
+    assert (i.nx, i.nx_struct) == (131, 130)
+    assert i.n_segments == 3 * 5 * 4
+    lbm.lbm_destroy(h)

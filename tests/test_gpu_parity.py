@@ -1,0 +1,186 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances: a step is FP32 arithmetic on values of order 1 (shifted storage), so
+populations after a few steps agree to a few FP32 ulps of the largest value
+(absolute 2e-6 of the scale used here).  Steady-state outputs (D_eff/D0, sigma/
+sigma0, reaction rate) must agree with the oracle's exact fixed point to 1e-4
+relative, the target the method is held to."""
+import numpy as np
+import pytest
+
+import structgen as sg
+from oracle import lbm as O
+
+pytestmark = pytest.mark.gpu
+
+STEADY_RTOL = 1e-4
+
+
+def _oracle_params(mode, **kw):
+    p = O.Params(mode=mode)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def _lbm_params(hip, mode, **kw):
+    return hip.lbm_params_default(mode=mode, **kw)
+
+
+def _both(hip, ph, mode, voxel_m=2e-9, **kw):
+    """Oracle problem and HIP solver for the same structure and parameters."""
+    okw = dict(kw)
+    okw["knudsen"] = bool(okw.get("knudsen", 0))
+    prob = O.prepare(ph, _oracle_params(mode, voxel_m=voxel_m, **okw))
+    s = hip.Solver(ph, _lbm_params(hip, mode, **kw), voxel_m=voxel_m)
+    return prob, s
+
+
+def _random_pre(prob, seed):
+    """Seeded random pre-collision state on the active voxels (FP64)."""
+    rng = np.random.default_rng(seed)
+    f = rng.random((7, prob.N)) * 0.3
+    f *= prob.active.ravel()[None, :]
+    return np.ascontiguousarray(f)
+
+
+STEP_CASES = [
+    # (kind, seed, shape, mode, extra params)
+    ("pt", 1, (9, 10, 70), 0, dict(knudsen=1)),
+    ("pt", 1, (9, 10, 70), 1, dict(knudsen=1, k_lat=0.05, catalyst_phases=(1 << 2) | (1 << 1))),
+    ("pt", 4, (8, 7, 130), 1, dict(knudsen=0, k_lat=0.1)),
+    ("pt", 6, (6, 5, 64), 2, dict()),
+    ("two", 3, (16, 16, 32), 0, dict(tau_ref=0.8)),
+    ("pt", 9, (1, 1, 150), 0, dict(knudsen=1)),    # one row, periodic self-neighbours
+    ("pt", 10, (2, 1, 66), 1, dict(k_lat=0.02)),   # ragged tail of 2, ny = 1
+    ("npmc", 2, (12, 12, 65), 1, dict(knudsen=1, k_lat=0.01, catalyst_phases=(1 << 1) | (1 << 2))),
+]
+
+
+def _phase(kind, seed, shape):
+    if kind == "pt":
+        return sg.pt_cl(seed, shape=shape)
+    if kind == "ion":  # ionomer-rich structure whose ionomer percolates (proton problems)
+        return sg.pt_cl(seed, shape=shape, carbon=0.3, ionomer=0.4)
+    if kind == "npmc":
+        return sg.npmc_cl(seed, shape=shape, meso_d=(3, 6))
+    return sg.two_phase(seed, shape=shape)
+
+
+@pytest.mark.parametrize("kind,seed,shape,mode,kw", STEP_CASES)
+def test_steps_match_oracle(hip, kind, seed, shape, mode, kw):
+    """Random state, n fused stream-collide steps on the GPU vs n oracle steps."""
+    import torch
+
+    ph = _phase(kind, seed, shape)
+    voxel = 1e-9 if kind == "npmc" else 2e-9
+    prob, s = _both(hip, ph, mode, voxel_m=voxel, **kw)
+    f0 = _random_pre(prob, seed)
+    fs0 = O.collide(prob, f0)
+    s.set_populations(torch.from_numpy(fs0.astype(np.float32)).reshape((7,) + s.shape))
+    f = f0
+    for n in (1, 1, 3):
+        s.step(n)
+        for _ in range(n):
+            f = O.step(prob, f)
+        got = s.populations().cpu().numpy().reshape(7, -1)
+        want = O.collide(prob, f)
+        err = np.abs(got - want).max()
+        assert err < 2e-6, (n, err)
+
+
+@pytest.mark.parametrize("kind,seed,shape,mode,kw", STEP_CASES[:5])
+def test_measure_matches_oracle(hip, kind, seed, shape, mode, kw):
+    """FP64 reductions of a random state: fluxes, sink and mass."""
+    import torch
+
+    ph = _phase(kind, seed, shape)
+    prob, s = _both(hip, ph, mode, **kw)
+    f0 = _random_pre(prob, seed + 100)
+    s.set_populations(torch.from_numpy(O.collide(prob, f0).astype(np.float32)).reshape((7,) + s.shape))
+    got = s.measure()
+    want = O.fluxes(prob, f0)
+    scale = max(1.0, abs(want.j_in), abs(want.rate))
+    assert got.j_in == pytest.approx(want.j_in, abs=1e-6 * scale)
+    assert got.j_out == pytest.approx(want.j_out, abs=1e-6 * scale)
+    assert got.j_vol == pytest.approx(want.j_vol, abs=1e-6 * scale)
+    assert got.rate == pytest.approx(want.rate, abs=1e-6 * scale)
+    assert got.mass == pytest.approx(want.mass, rel=1e-6)
+
+
+def test_concentration_roundtrip(hip):
+    import torch
+
+    ph = sg.pt_cl(3, shape=(6, 7, 70))
+    prob, s = _both(hip, ph, 1, knudsen=1, k_lat=0.05)
+    rng = np.random.default_rng(0)
+    C = rng.random(s.shape).astype(np.float32)
+    s.set_initial_concentration(torch.from_numpy(C))
+    got = s.concentration().cpu().numpy()
+    assert np.allclose(got[prob.active], C[prob.active], rtol=2e-6, atol=1e-7)
+    assert np.all(got[~prob.active] == 0)
+    # the equilibrium populations are those of the oracle's equilibrium after one collision
+    want = O.collide(prob, O.equilibrium(prob, C.astype(np.float64)))
+    assert np.abs(s.populations().cpu().numpy().reshape(7, -1) - want).max() < 1e-6
+
+
+# ------------------------------------------------------------------ steady state
+
+STEADY_CASES = [
+    ("two", 1, (32, 32, 32), 0, dict()),                       # the 32^3 two-phase workload, tau = 1
+    ("two", 2, (32, 32, 32), 0, dict(tau_ref=0.7)),
+    ("pt", 1, (10, 12, 70), 0, dict(knudsen=1)),
+    ("pt", 1, (10, 12, 70), 1, dict(knudsen=1, k_lat=0.01)),
+    ("pt", 8, (8, 9, 66), 1, dict(k_lat=0.1)),
+    ("ion", 5, (8, 9, 66), 2, dict()),
+    ("ion", 12, (8, 9, 66), 2, dict(tau_ref=0.8)),
+]
+
+
+@pytest.mark.parametrize("kind,seed,shape,mode,kw", STEADY_CASES)
+def test_steady_state_matches_oracle(hip, kind, seed, shape, mode, kw):
+    ph = _phase(kind, seed, shape)
+    prob, s = _both(hip, ph, mode, check_every=200, **kw)
+    assert prob.percolates
+    ref = O.solve_fixed_point(prob)
+    st, info = s.run_to_steady()
+    assert st == 0, (st, info.as_dict())
+    if mode == O.MODE_REACT:
+        _, rate, jin = s.reaction_rate()
+        assert rate == pytest.approx(ref.rate, rel=STEADY_RTOL)
+        assert jin == pytest.approx(ref.fluxes.j_in, rel=10 * STEADY_RTOL)
+    else:
+        _, d = s.deff()
+        assert d == pytest.approx(ref.deff, rel=STEADY_RTOL)
+    C = s.concentration().cpu().numpy()
+    Cref = O.concentration(prob, ref.f)
+    assert np.abs(C - Cref).max() < 1e-3 * max(1.0, np.abs(Cref).max())
+
+
+def test_empty_box_and_no_percolation(hip):
+    ph = np.zeros((4, 5, 70), np.uint8)
+    s = hip.Solver(ph, hip.lbm_params_default(tau_ref=0.9, check_every=200))
+    st, _ = s.run_to_steady()
+    assert st == 0
+    assert s.deff()[1] == pytest.approx(1.0, rel=STEADY_RTOL)
+    ph[:, :, 30] = O.CARBON
+    s2 = hip.Solver(ph, hip.lbm_params_default())
+    st, _ = s2.run_to_steady()
+    assert st == hip.ERR_NO_PERCOLATION
+    st, d = s2.deff()
+    assert st == hip.ERR_NO_PERCOLATION and d == 0.0
+
+
+def test_batch_matches_single(hip):
+    """The batched engine gives each instance the single-solver answer."""
+    shapes = [(8, 9, 66), (6, 6, 40), (10, 10, 70)]
+    phases = [sg.pt_cl(20 + i, shape=sh) for i, sh in enumerate(shapes)]
+    ks = [0.1, 0.01, 0.03]
+    params = [hip.lbm_params_default(mode=1, k_lat=k, check_every=200) for k in ks]
+    b = hip.Batch(phases, params)
+    st, infos = b.run()
+    assert st == 0
+    for i in range(3):
+        prob = O.prepare(phases[i], O.Params(mode=1, k_lat=ks[i]))
+        ref = O.solve_fixed_point(prob)
+        assert b.reaction_rate(i)[1] == pytest.approx(ref.rate, rel=STEADY_RTOL)
