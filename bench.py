@@ -1,0 +1,264 @@
+#!/usr/bin/env python3
+"""Benchmark of the D3Q7 reactive-diffusion LBM on one MI355X.
+
+Headline (``value``): MLUPS, millions of fluid-voxel updates per second, of the
+steady-state loop on the 256^3 non-precious-metal catalyst layer at 1 nm (carbon
+0.45 with micro- and mesopores carved inside, ionomer 0.15, pores 0.40; Knudsen
+diffusivity in the pores; every carbon face reactive, k = 1e-4 per face; reactive
+problem with the inlet reservoir plane).  One bench step is one check window of
+the solver: ``--lbm-steps`` fused stream-collide steps (a captured HIP graph),
+the FP64 reductions and the host stop-rule evaluation.  Inputs are resident in
+HBM before timing starts.
+
+Also reported on the same JSON line:
+  * roofline: algorithmic bytes per stream-collide launch / its mean duration
+    (HIP events on the solver stream), against the 8 TB/s HBM peak;
+  * cpu_baseline: the FP64 oracle's step rate on a slab of the same structure;
+  * solves: solves/s to D_eff on the 32^3 two-phase workload (seeds 1..10),
+    sequential single solves vs one batched solve, with the error against the
+    stored oracle values;
+  * warm_start: learned warm start vs cold start, when the trained network exists.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20, help="timed bench steps (check windows)")
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--lbm-steps", type=int, default=500, help="LBM steps per bench step")
+    ap.add_argument("--n", type=int, default=256, help="cube edge of the headline structure")
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-solves", action="store_true", help="skip the 32^3 solves/s legs")
+    ap.add_argument("--no-warm", action="store_true", help="skip the warm-start leg")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU time budget of the oracle sample")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_1410_1914_amd", "csrc", "kernels.hip"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(info, knudsen: bool, react: bool) -> float:
+    """Bytes one stream-collide launch must move: 7 FP32 reads + 7 FP32 writes per
+    fluid voxel (+4 for its FP32 1/tau with Knudsen), and per 64-voxel segment its
+    fluid mask (8) and prefix (4), plus the reactive and catalyst masks (16) when
+    reacting or the ionomer mask (8) when 1/tau comes from the phase."""
+    per_fluid = 56.0 + (4.0 if knudsen else 0.0)
+    per_seg = 12.0 + (16.0 if react else 0.0) + (0.0 if knudsen else 8.0)
+    return info.n_active * per_fluid + info.n_segments * per_seg
+
+
+def traffic_from_profiles(kernel_sha: str, workload: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were taken
+    on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    e = d.get(workload)
+    if not e or e.get("kernel_sha") != kernel_sha:
+        return None
+    return e.get("bytes_per_launch")
+
+
+def headline(args, lbm, structgen):
+    import torch
+
+    n = args.n
+    t = time.time()
+    ph = structgen.npmc_cl(args.seed, n=n)
+    t_gen = time.time() - t
+    p = lbm.lbm_params_default(mode=lbm.MODE_REACT, knudsen=1, k_lat=1e-4,
+                               catalyst_phases=(1 << lbm.CARBON) | (1 << lbm.PT),
+                               check_every=args.lbm_steps, max_steps=1 << 60)
+    t = time.time()
+    s = lbm.Solver(ph, p, voxel_m=1e-9)
+    t_prep = time.time() - t
+    info = s.info
+    log(f"[bench] {n}^3 NPMC: generated in {t_gen:.1f}s, preprocessed+bound in {t_prep:.1f}s, "
+        f"{info.n_active} fluid voxels, {info.n_segments} segments")
+    tune_ms = s.autotune(10)
+    tiling = s.tiling()
+    log(f"[bench] autotuned tiling (segments/wave, waves/workgroup, xcd) = {tiling}: {tune_ms*1e3:.1f} us/step")
+    _, r0 = s.advance(0)
+    for _ in range(args.warmup):
+        _, r0 = s.advance(args.lbm_steps)
+    torch.cuda.synchronize()
+    ms0, l0 = r0.kernel_ms, r0.kernel_launches
+    t0 = time.perf_counter()
+    r = r0
+    for _ in range(args.steps):
+        _, r = s.advance(args.lbm_steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launches = r.kernel_launches - l0
+    kms = r.kernel_ms - ms0
+    updates = info.n_active * launches
+    mlups = updates / wall / 1e6
+    per_launch_s = kms / 1e3 / launches
+    alg = algorithmic_bytes(info, knudsen=True, react=True)
+    achieved = alg / per_launch_s / 1e9
+    log(f"[bench] {launches} LBM steps in {wall:.3f}s: {mlups:.0f} MLUPS; kernel mean {per_launch_s*1e6:.1f} us, "
+        f"{achieved:.0f} GB/s algorithmic")
+    workload = f"npmc_cl_{n}^3_react_knudsen"
+    sha = kernel_source_hash()
+    tb = traffic_from_profiles(sha, workload)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": (round(tb / per_launch_s / 1e9, 1) if tb else None),
+            "kernel": f"k_step<{tiling[1]},{tiling[0]},true,true> (fused pull stream-collide, Knudsen, reactive)",
+            "tiling": {"segs_per_wave": tiling[0], "waves_per_block": tiling[1], "xcd_remap": tiling[2]},
+            "alg_bytes_per_launch": int(alg), "mean_launch_us": round(per_launch_s * 1e6, 2),
+            "kernel_source_sha": sha}
+    res = {"mlups": mlups, "ms_per_step": 1e3 * wall / args.steps, "roofline": roof, "workload": workload,
+           "n_active": info.n_active, "n_voxels": n ** 3, "prep_s": round(t_prep, 2), "gen_s": round(t_gen, 2),
+           "kernel_mlups": info.n_active / per_launch_s / 1e6,
+           "rate_per_area_after": r.rate, "steps_taken": r.steps}
+    return res, ph
+
+
+def cpu_baseline(args, ph, structgen):
+    """Oracle (plain FP64 C, OpenMP) step rate on a slab of the same structure."""
+    import numpy as np
+    from oracle import lbm as O
+
+    slab = np.ascontiguousarray(ph[:, :, :64])
+    prob = O.prepare(slab, O.Params(mode=O.MODE_REACT, knudsen=True, voxel_m=1e-9, k_lat=1e-4,
+                                    catalyst_phases=(1 << O.CARBON) | (1 << O.PT)))
+    f = O.equilibrium(prob, 0.0)
+    st = O.Stepper(prob)
+    g = np.empty_like(f)
+    st.step(f, g)  # first touch
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        st.step(f, g)
+        f, g = g, f
+        n += 1
+        if time.perf_counter() - t0 > args.cpu_seconds:
+            break
+    dt = time.perf_counter() - t0
+    act = int(prob.active.sum())
+    v = act * n / dt / 1e6
+    return {"value": round(v, 2), "unit": "MLUPS", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"{n} FP64 steps of the oracle on the first 64 x-planes of the same structure "
+                      f"({slab.shape[2]}x{slab.shape[1]}x{slab.shape[0]}, {act} fluid voxels)"}
+
+
+def solves_leg(lbm, structgen):
+    """Solves/s to D_eff on the 32^3 two-phase workload, single vs batched."""
+    import torch
+
+    with open(os.path.join(ROOT, "tests", "golden", "oracle_two_phase_32.json")) as fh:
+        gold = {c["seed"]: c["deff"] for c in json.load(fh)["cases"]}
+    seeds = sorted(gold)
+    phases = [structgen.two_phase(sd, n=32) for sd in seeds]
+    mk = lambda: lbm.lbm_params_default(check_every=200)  # noqa: E731
+    # sequential single solves (each a fresh solver: preprocessing + bind + solve)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    errs, steps = [], []
+    for sd, ph in zip(seeds, phases):
+        s = lbm.Solver(ph, mk())
+        st, r = s.run_to_steady()
+        errs.append(abs(s.deff()[1] / gold[sd] - 1))
+        steps.append(r.steps)
+        s.close()
+    t_single = time.perf_counter() - t0
+    # one batched solve of the same structures
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = lbm.Batch(phases, [mk() for _ in phases])
+    b.autotune(20)
+    st, infos = b.run()
+    berrs = [abs(b.deff(i)[1] / gold[sd] - 1) for i, sd in enumerate(seeds)]
+    t_batch = time.perf_counter() - t0
+    return {"workload": "two-phase QSGS 32^3, seeds 1..10, tau 1, D_eff",
+            "single_solves_per_s": round(len(seeds) / t_single, 2),
+            "batched_solves_per_s": round(len(seeds) / t_batch, 2),
+            "batched_speedup": round(t_single / t_batch, 2),
+            "max_rel_err_single": max(errs), "max_rel_err_batched": max(berrs),
+            "mean_steps": int(sum(steps) / len(steps)), "tiling": list(b.tiling())}
+
+
+def warm_leg():
+    try:
+        from paper_1410_1914_amd import warmstart
+    except ImportError:
+        return None
+    if not hasattr(warmstart, "bench_warm_vs_cold"):
+        return None
+    return warmstart.bench_warm_vs_cold()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver has no multi-GPU path.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch  # noqa: F401
+
+    import structgen
+    from paper_1410_1914_amd import lbm
+
+    lbm.require_gpu()
+    head, ph = headline(args, lbm, structgen)
+    out = {
+        "metric": "D3Q7 MLUPS (% HBM peak); solves/s to D_eff +-1e-4; warm-start vs cold speedup",
+        "value": round(head["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 storage, f64 arithmetic and reductions",
+        "data": "synthetic (seeded QSGS structure)",
+        "config": {"workload": head["workload"], "edge": args.n, "voxel_nm": 1.0, "lbm_steps_per_step": args.lbm_steps,
+                   "fluid_voxels": head["n_active"], "k_lat": 1e-4, "parallelism": "single GPU"},
+        "roofline": head["roofline"],
+        "kernel_mlups": round(head["kernel_mlups"], 1),
+        "prep_s": head["prep_s"],
+    }
+    if not args.no_cpu:
+        log("[bench] CPU oracle baseline ...")
+        out["cpu_baseline"] = cpu_baseline(args, ph, structgen)
+    del ph
+    if not args.no_solves:
+        log("[bench] 32^3 solves/s legs ...")
+        out["solves"] = solves_leg(lbm, structgen)
+    if not args.no_warm:
+        w = warm_leg()
+        if w is not None:
+            out["warm_start"] = w
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -106,6 +106,9 @@ typedef struct {
     double rate;        /* total sink sum k n C, per unit cross-section area      */
     double mass;        /* total sum of C over simulated voxels                   */
     double est_error;   /* estimated remaining relative error of the output       */
+    double kernel_ms;   /* HIP-event time of the stream-collide launches made by
+                           the steady-state loop since the last initialisation    */
+    int64_t kernel_launches; /* stream-collide launches timed in kernel_ms        */
     int32_t status;     /* LBM_OK, LBM_NOT_CONVERGED or an error                  */
     int32_t checks;     /* number of convergence checks made                      */
 } lbm_run_info;
@@ -178,6 +181,20 @@ int lbm_measure(lbm_solver *s, lbm_run_info *info);
  * flux balance are all below their tolerances, or after max_steps.  Returns LBM_OK, LBM_NOT_CONVERGED,
  * LBM_ERR_DIVERGED or LBM_ERR_NO_PERCOLATION (D_eff problems without a path). */
 int lbm_run_to_steady(lbm_solver *s, lbm_run_info *info);
+
+/* Tiling of the stream-collide launch: segments per wave (1, 2, 4), waves per
+ * workgroup (1, 2, 4, 8), XCD-aware workgroup order (0/1).  lbm_autotune times
+ * every tiling for steps_per_trial steps on the live state (the trial steps are
+ * ordinary solver steps) and keeps the fastest; ms_best receives its time per step. */
+int lbm_set_tiling(lbm_solver *s, int32_t segs_per_wave, int32_t waves_per_block, int32_t xcd_remap);
+int lbm_get_tiling(const lbm_solver *s, int32_t *segs_per_wave, int32_t *waves_per_block, int32_t *xcd_remap);
+int lbm_autotune(lbm_solver *s, int32_t steps_per_trial, double *ms_best);
+
+/* The loop of lbm_run_to_steady with a budget: at most max_new_steps further
+ * steps (whole windows of K steps; fewer than K steps of budget does nothing).
+ * Returns LBM_OK once converged, LBM_NOT_CONVERGED while the budget ran out
+ * first (call again to continue), or an error. */
+int lbm_advance(lbm_solver *s, int64_t max_new_steps, lbm_run_info *info);
 
 /* D_eff/D0 (LBM_MODE_DEFF) or sigma_eff/sigma (LBM_MODE_PROTON) from the volume
  * averaged x flux of the last measurement, Eq. (19) with L = nx:

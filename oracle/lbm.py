@@ -72,6 +72,8 @@ def _load():
     lib.orc_assemble.restype = ctypes.c_int64
     lib.orc_chords.argtypes = [ctypes.c_int] * 3 + [u8, dp]
     lib.orc_flood.argtypes = [ctypes.c_int] * 3 + [u8, u8, u8]
+    lib.orc_num_threads.argtypes = []
+    lib.orc_num_threads.restype = ctypes.c_int
     for fn in (lib.orc_collide, lib.orc_stream, lib.orc_step, lib.orc_concentration,
                lib.orc_fluxes, lib.orc_chords, lib.orc_flood):
         fn.restype = None
@@ -88,6 +90,11 @@ class _Grid(ctypes.Structure):
         ("omega", ctypes.POINTER(ctypes.c_double)),
         ("kn", ctypes.POINTER(ctypes.c_double)),
     ]
+
+
+def num_threads() -> int:
+    """Threads the oracle's parallel loops use."""
+    return int(_load().orc_num_threads())
 
 
 def _p(a, ct):

@@ -23,9 +23,21 @@
  *   kn[v]      k * n(v), the first-order sink coefficient (Eqs. 17b, 18a)
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* threads the parallel loops below use (1 without OpenMP) */
+int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 static const int CX[7] = {0, 1, -1, 0, 0, 0, 0};
 static const int CY[7] = {0, 0, 0, 1, -1, 0, 0};

@@ -75,17 +75,22 @@ struct Engine {
     int cur = 0;
 
     int waves = 4, spw = 1, xcd = 1;
-    int step_nblk = 0, meas_nblk = 0, conv_nblk = 0;
+    int step_nblk = 0, step_nent = 0, meas_nblk = 0, conv_nblk = 0;
     std::vector<int> live;
     std::vector<RunState> rs;
 
     hipGraphExec_t gexec = nullptr;
     int g_cur = -1, g_nblk = -1;
     bool g_valid = false;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;  // bracket the step launches of a window
+    bool ev_pending = false;
+    int64_t ev_launches = 0;
 
     ~Engine() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (res_host) (void)hipHostFree(res_host);
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
     }
 
     template <typename T>
@@ -106,7 +111,7 @@ struct Engine {
             dense += (int64_t)P[i].nx * P[i].ny * P[i].nz;
         }
         stride = (int64_t)align_up((size_t)std::max<int64_t>(nf_total, 1), 64);
-        cap_sblk = nseg_total + ninst;
+        cap_sblk = nseg_total;
         cap_cblk = nseg_total / 4 + ninst + 1;
         cap_mblk = (int64_t)ninst * kMeasMaxBlocks;
         size_t o = 0;
@@ -126,7 +131,7 @@ struct Engine {
         off_pre = take(sizeof(uint32_t) * nseg_total);
         off_inst = take(sizeof(InstDev) * ninst);
         off_dbase = take(sizeof(int64_t) * ninst);
-        off_sblk = take(sizeof(int2) * cap_sblk);
+        off_sblk = take(sizeof(SegEntry) * cap_sblk);
         off_cblk = take(sizeof(int2) * cap_cblk);
         off_mblk = take(sizeof(int4) * cap_mblk);
         off_rng = take(sizeof(int2) * ninst);
@@ -158,14 +163,20 @@ struct Engine {
     }
 
     hipError_t upload_tables() {
-        // step table over live instances
-        std::vector<int2> sb;
-        const int per = waves * spw;
+        // step table: the segments holding fluid of every live instance, in grid order
+        std::vector<SegEntry> sb;
         for (int i : live) {
-            const int64_t nb = (P[i].nseg + per - 1) / per;
-            for (int64_t b = 0; b < nb; ++b) sb.push_back(make_int2(i, (int)(b * per)));
+            const Prepared &p = P[i];
+            for (int64_t g = 0; g < p.nseg; ++g) {
+                if (!p.m_fluid[g]) continue;
+                const int s = (int)(g % p.nsx);
+                const int64_t row = g / p.nsx;
+                sb.push_back(SegEntry{(uint16_t)s, (uint16_t)(row % p.ny), (uint16_t)(row / p.ny), (uint16_t)i});
+            }
         }
-        step_nblk = (int)sb.size();
+        step_nent = (int)sb.size();
+        const int per = waves * spw;
+        step_nblk = (step_nent + per - 1) / per;
         // measure table and per-instance partial ranges
         std::vector<int4> mb;
         std::vector<int2> rg(ninst, make_int2(0, 0));
@@ -177,7 +188,8 @@ struct Engine {
         }
         meas_nblk = (int)mb.size();
         hipError_t e = hipSuccess;
-        if (!sb.empty()) e = hipMemcpyAsync(at<int2>(off_sblk), sb.data(), sizeof(int2) * sb.size(), hipMemcpyHostToDevice, st);
+        if (!sb.empty())
+            e = hipMemcpyAsync(at<SegEntry>(off_sblk), sb.data(), sizeof(SegEntry) * sb.size(), hipMemcpyHostToDevice, st);
         if (e == hipSuccess && !mb.empty())
             e = hipMemcpyAsync(at<int4>(off_mblk), mb.data(), sizeof(int4) * mb.size(), hipMemcpyHostToDevice, st);
         if (e == hipSuccess) e = hipMemcpyAsync(at<int2>(off_rng), rg.data(), sizeof(int2) * ninst, hipMemcpyHostToDevice, st);
@@ -201,6 +213,8 @@ struct Engine {
             e = note(hipHostMalloc((void **)&res_host, sizeof(double) * NQ * ninst, hipHostMallocDefault), "hipHostMalloc");
             if (e != hipSuccess) return e;
         }
+        if (!ev0 && (e = note(hipEventCreate(&ev0), "hipEventCreate")) != hipSuccess) return e;
+        if (!ev1 && (e = note(hipEventCreate(&ev1), "hipEventCreate")) != hipSuccess) return e;
         f[0] = at<float>(off_f0);
         f[1] = at<float>(off_f1);
         csnap = at<float>(off_snap);
@@ -254,6 +268,7 @@ struct Engine {
     hipError_t init(const float *c_dense) {
         cur = 0;
         rs.assign(ninst, RunState{});
+        for (auto &r : rs) r.info.status = LBM_NOT_CONVERGED;
         live.clear();
         for (int i = 0; i < ninst; ++i) live.push_back(i);
         hipError_t e = upload_tables();
@@ -276,7 +291,8 @@ struct Engine {
         s.spw = spw;
         s.xcd = xcd;
         s.nblk = step_nblk;
-        s.blk = at<int2>(off_sblk);
+        s.nent = step_nent;
+        s.seg = at<SegEntry>(off_sblk);
         return s;
     }
 
@@ -339,11 +355,15 @@ struct Engine {
             g_cur = cur;
             g_nblk = step_nblk;
         }
-        for (int64_t r = 0; r < reps; ++r) {
-            hipError_t e = note(hipGraphLaunch(gexec, st), "hipGraphLaunch");
-            if (e != hipSuccess) return e;
+        hipError_t e = note(hipEventRecord(ev0, st), "hipEventRecord");
+        for (int64_t r = 0; r < reps && e == hipSuccess; ++r) {
+            e = note(hipGraphLaunch(gexec, st), "hipGraphLaunch");
             if (K0 & 1) cur ^= 1;
         }
+        if (e == hipSuccess) e = note(hipEventRecord(ev1, st), "hipEventRecord");
+        if (e != hipSuccess) return e;
+        ev_pending = true;
+        ev_launches = (int64_t)K0 * reps;
         if (K0 & 1) g_valid = false;  // the next window starts from the other lattice
         return measure_enqueue(1);
     }
@@ -424,9 +444,13 @@ struct Engine {
         return info.steps >= pp.max_steps;
     }
 
-    int run(lbm_run_info *out) {
+    // The steady-state loop.  budget caps the number of new steps (windows are
+    // shortened to fit); instances still running when it is spent report
+    // LBM_NOT_CONVERGED and can be resumed by another call.
+    int run(lbm_run_info *out, int64_t budget = std::numeric_limits<int64_t>::max()) {
         if (!bound) return LBM_ERR_UNBOUND;
         const int K = check_every;
+        int64_t spent = 0;
         // instances without a percolating path are finished before the first step
         std::vector<int> still;
         for (int i : live) {
@@ -444,8 +468,20 @@ struct Engine {
         }
         int64_t reps = 1;  // window = reps * K steps; doubled while every live instance is slow
         while (!live.empty()) {
+            const int64_t room = (budget - spent) / K;
+            if (room < 1) break;
+            reps = std::min(reps, room);
             if (window(K, reps) != hipSuccess) return LBM_ERR_HIP;
+            spent += (int64_t)K * reps;
             if (read_results() != hipSuccess) return LBM_ERR_HIP;
+            float win_ms = 0.f;
+            if (ev_pending && hipEventElapsedTime(&win_ms, ev0, ev1) == hipSuccess) {
+                for (int i : live) {
+                    rs[i].info.kernel_ms += win_ms;
+                    rs[i].info.kernel_launches += ev_launches;
+                }
+            }
+            ev_pending = false;
             std::vector<int> keep;
             bool all_slow = true;
             for (int i : live) {
@@ -530,7 +566,7 @@ int hip_status_at(hipError_t e, const char *where) {
 
 int make_engine(int n, const lbm_grid *grids, const uint8_t *const *phases, const lbm_params *params,
                 std::unique_ptr<Engine> &out) {
-    if (n <= 0 || !grids || !phases || !params) return LBM_ERR_INVALID_ARG;
+    if (n <= 0 || n > 65535 || !grids || !phases || !params) return LBM_ERR_INVALID_ARG;
     auto E = std::make_unique<Engine>();
     E->ninst = n;
     E->P.resize(n);
@@ -546,6 +582,7 @@ int make_engine(int n, const lbm_grid *grids, const uint8_t *const *phases, cons
     E->react = E->mode == LBM_MODE_REACT;
     E->check_every = params[0].check_every;
     E->layout();
+    if (E->nseg_total > (int64_t)INT32_MAX) return LBM_ERR_INVALID_ARG;
     E->rs.assign(n, RunState{});
     out = std::move(E);
     return LBM_OK;
@@ -716,6 +753,21 @@ int lbm_run_to_steady(lbm_solver *s, lbm_run_info *info) {
     LBM_GUARD_END
 }
 
+int lbm_advance(lbm_solver *s, int64_t max_new_steps, lbm_run_info *info) {
+    LBM_GUARD_BEGIN
+    if (!s || max_new_steps < 0) return LBM_ERR_INVALID_ARG;
+    cl::DeviceGuard dg(s->E->device);
+    cl::Engine &E = *s->E;
+    if (!E.bound) return LBM_ERR_UNBOUND;
+    E.rs[0].done = 0;
+    if (E.all_live() != hipSuccess) return LBM_ERR_HIP;
+    lbm_run_info tmp{};
+    const int st = E.run(&tmp, max_new_steps);
+    if (info) *info = tmp;
+    return st < 0 ? st : tmp.status;
+    LBM_GUARD_END
+}
+
 int lbm_deff(const lbm_solver *s, double *out) {
     if (!s || !out) return LBM_ERR_INVALID_ARG;
     return s->E->deff(0, out);
@@ -789,11 +841,9 @@ int lbm_batch_bind(lbm_batch *b, void *ws, size_t bytes, void *stream) {
     LBM_GUARD_END
 }
 
-int lbm_batch_set_tiling(lbm_batch *b, int32_t spw, int32_t waves, int32_t xcd) {
-    if (!b) return LBM_ERR_INVALID_ARG;
+static int set_tiling(cl::Engine &E, int32_t spw, int32_t waves, int32_t xcd) {
     if (!(spw == 1 || spw == 2 || spw == 4) || !(waves == 1 || waves == 2 || waves == 4 || waves == 8))
         return LBM_ERR_INVALID_ARG;
-    cl::Engine &E = *b->E;
     E.spw = spw;
     E.waves = waves;
     E.xcd = xcd ? 1 : 0;
@@ -804,18 +854,17 @@ int lbm_batch_set_tiling(lbm_batch *b, int32_t spw, int32_t waves, int32_t xcd) 
     return LBM_OK;
 }
 
-int lbm_batch_get_tiling(const lbm_batch *b, int32_t *spw, int32_t *waves, int32_t *xcd) {
-    if (!b) return LBM_ERR_INVALID_ARG;
-    if (spw) *spw = b->E->spw;
-    if (waves) *waves = b->E->waves;
-    if (xcd) *xcd = b->E->xcd;
+static int get_tiling(const cl::Engine &E, int32_t *spw, int32_t *waves, int32_t *xcd) {
+    if (spw) *spw = E.spw;
+    if (waves) *waves = E.waves;
+    if (xcd) *xcd = E.xcd;
     return LBM_OK;
 }
 
-int lbm_batch_autotune(lbm_batch *b, int32_t steps_per_trial, double *ms_best) {
+static int autotune(cl::Engine &E, int32_t steps_per_trial, double *ms_best) {
     LBM_GUARD_BEGIN
-    if (!b || steps_per_trial < 2) return LBM_ERR_INVALID_ARG;
-    cl::Engine &E = *b->E;
+    if (steps_per_trial < 2) return LBM_ERR_INVALID_ARG;
+    if (E.bound && E.all_live() != hipSuccess) return LBM_ERR_HIP;
     if (!E.bound) return LBM_ERR_UNBOUND;
     cl::DeviceGuard dg(E.device);
     if (steps_per_trial & 1) ++steps_per_trial;  // even: the state stays in its lattice
@@ -862,6 +911,30 @@ int lbm_batch_autotune(lbm_batch *b, int32_t steps_per_trial, double *ms_best) {
     if (ms_best) *ms_best = best;
     return cl::hip_status(e);
     LBM_GUARD_END
+}
+
+int lbm_batch_set_tiling(lbm_batch *b, int32_t spw, int32_t waves, int32_t xcd) {
+    return b ? set_tiling(*b->E, spw, waves, xcd) : LBM_ERR_INVALID_ARG;
+}
+
+int lbm_batch_get_tiling(const lbm_batch *b, int32_t *spw, int32_t *waves, int32_t *xcd) {
+    return b ? get_tiling(*b->E, spw, waves, xcd) : LBM_ERR_INVALID_ARG;
+}
+
+int lbm_batch_autotune(lbm_batch *b, int32_t steps_per_trial, double *ms_best) {
+    return b ? autotune(*b->E, steps_per_trial, ms_best) : LBM_ERR_INVALID_ARG;
+}
+
+int lbm_set_tiling(lbm_solver *s, int32_t spw, int32_t waves, int32_t xcd) {
+    return s ? set_tiling(*s->E, spw, waves, xcd) : LBM_ERR_INVALID_ARG;
+}
+
+int lbm_get_tiling(const lbm_solver *s, int32_t *spw, int32_t *waves, int32_t *xcd) {
+    return s ? get_tiling(*s->E, spw, waves, xcd) : LBM_ERR_INVALID_ARG;
+}
+
+int lbm_autotune(lbm_solver *s, int32_t steps_per_trial, double *ms_best) {
+    return s ? autotune(*s->E, steps_per_trial, ms_best) : LBM_ERR_INVALID_ARG;
 }
 
 int lbm_batch_run(lbm_batch *b, lbm_run_info *infos) {

@@ -35,12 +35,18 @@ struct Lattice {
 // Quantities reduced per instance, in this order.
 enum { Q_JIN = 0, Q_JOUT, Q_JINT, Q_RATE, Q_MASS, Q_DCMAX, Q_CMAX, Q_BAD, NQ };
 
+// One entry per row segment that holds fluid: its position in its instance.
+struct SegEntry {
+    uint16_t s, y, z, inst;
+};
+
 struct StepLaunch {
     int32_t waves;        // waves per workgroup: 1, 2, 4, 8
     int32_t spw;          // segments per wave: 1, 2, 4
     int32_t xcd;          // XCD-aware block order
     int32_t nblk;         // workgroups
-    const int2 *blk;      // per workgroup: {instance, first local segment}
+    int32_t nent;         // entries of the segment table
+    const SegEntry *seg;  // segments with fluid, in grid order
 };
 
 struct MeasureLaunch {

@@ -62,6 +62,21 @@ __device__ __forceinline__ Seg locate(const InstDev &I, int64_t sl) {
     return q;
 }
 
+// segment of a table entry: global index and periodic neighbour rows, no division
+__device__ __forceinline__ Seg locate_entry(const InstDev &I, SegEntry e) {
+    Seg q;
+    q.s = e.s;
+    q.y = e.y;
+    q.z = e.z;
+    const int64_t rs = I.nsx, ps = (int64_t)I.ny * I.nsx;
+    q.g = I.seg_base + (int64_t)q.z * ps + (int64_t)q.y * rs + q.s;
+    q.gym = q.g + (q.y == 0 ? (int64_t)(I.ny - 1) * rs : -rs);
+    q.gyp = q.g + (q.y == I.ny - 1 ? -(int64_t)(I.ny - 1) * rs : rs);
+    q.gzm = q.g + (q.z == 0 ? (int64_t)(I.nz - 1) * ps : -ps);
+    q.gzp = q.g + (q.z == I.nz - 1 ? -(int64_t)(I.nz - 1) * ps : ps);
+    return q;
+}
+
 // catalyst face neighbours of the lane's voxel (Eq. 18a): x bounded, y/z periodic
 __device__ __forceinline__ int catalyst_count(const Lattice &L, const Seg &q, int nsx, int lane) {
     const uint64_t c = L.m_cat[q.g];
@@ -75,9 +90,8 @@ __device__ __forceinline__ int catalyst_count(const Lattice &L, const Seg &q, in
 
 // One fused pull stream + collide for the fluid lanes of one row segment.
 template <bool KNUDSEN, bool REACT>
-__device__ __forceinline__ void step_segment(const Lattice &L, const InstDev &I, int64_t sl, int lane,
+__device__ __forceinline__ void step_segment(const Lattice &L, const InstDev &I, const Seg &q, int lane,
                                              const float *__restrict__ fin, float *__restrict__ fout) {
-    const Seg q = locate(I, sl);
     const uint64_t m = L.m_fluid[q.g];
     if (m == 0ull) return;
     const uint64_t mp = q.s > 0 ? L.m_fluid[q.g - 1] : 0ull;
@@ -141,17 +155,19 @@ __device__ __forceinline__ void step_segment(const Lattice &L, const InstDev &I,
 }
 
 template <int WAVES, int SPW, bool KNUDSEN, bool REACT>
-__global__ __launch_bounds__(WAVES * 64) void k_step(Lattice L, const int2 *__restrict__ blk, int nblk, int remap,
-                                                    const float *__restrict__ fin, float *__restrict__ fout) {
+__global__ __launch_bounds__(WAVES * 64) void k_step(Lattice L, const SegEntry *__restrict__ seg, int nent, int nblk,
+                                                    int remap, const float *__restrict__ fin, float *__restrict__ fout) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int b = logical_block(blockIdx.x, nblk, remap);
-    const int2 t = blk[b];
-    const InstDev &I = L.inst[t.x];
 #pragma unroll
     for (int k = 0; k < SPW; ++k) {
-        const int64_t sl = (int64_t)t.y + (int64_t)wave * SPW + k;
-        if (sl < I.nseg) step_segment<KNUDSEN, REACT>(L, I, sl, lane, fin, fout);
+        const int idx = (b * WAVES + wave) * SPW + k;
+        if (idx < nent) {
+            const SegEntry e = seg[idx];
+            const InstDev &I = L.inst[e.inst];
+            step_segment<KNUDSEN, REACT>(L, I, locate_entry(I, e), lane, fin, fout);
+        }
     }
 }
 
@@ -325,13 +341,13 @@ hipError_t launch_step_t(const Lattice &L, const StepLaunch &S, bool kn, bool re
     const dim3 grid(S.nblk), block(W * 64);
     (void)hipGetLastError();  // drop a stale error (e.g. hipErrorNotReady from an event query)
     if (kn && re) {
-        hipLaunchKernelGGL((k_step<W, SPW, true, true>), grid, block, 0, st, L, S.blk, S.nblk, S.xcd, fin, fout);
+        hipLaunchKernelGGL((k_step<W, SPW, true, true>), grid, block, 0, st, L, S.seg, S.nent, S.nblk, S.xcd, fin, fout);
     } else if (kn) {
-        hipLaunchKernelGGL((k_step<W, SPW, true, false>), grid, block, 0, st, L, S.blk, S.nblk, S.xcd, fin, fout);
+        hipLaunchKernelGGL((k_step<W, SPW, true, false>), grid, block, 0, st, L, S.seg, S.nent, S.nblk, S.xcd, fin, fout);
     } else if (re) {
-        hipLaunchKernelGGL((k_step<W, SPW, false, true>), grid, block, 0, st, L, S.blk, S.nblk, S.xcd, fin, fout);
+        hipLaunchKernelGGL((k_step<W, SPW, false, true>), grid, block, 0, st, L, S.seg, S.nent, S.nblk, S.xcd, fin, fout);
     } else {
-        hipLaunchKernelGGL((k_step<W, SPW, false, false>), grid, block, 0, st, L, S.blk, S.nblk, S.xcd, fin, fout);
+        hipLaunchKernelGGL((k_step<W, SPW, false, false>), grid, block, 0, st, L, S.seg, S.nent, S.nblk, S.xcd, fin, fout);
     }
     return hipGetLastError();
 }

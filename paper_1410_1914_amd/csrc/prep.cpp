@@ -120,7 +120,8 @@ int prepare(const lbm_grid &g, const uint8_t *phase, const lbm_params &p, Prepar
     if (p.knudsen && !(g.voxel_m > 0.0 && p.T_K > 0.0 && p.M_kg_mol > 0.0)) return LBM_ERR_INVALID_ARG;
     if (p.mode != LBM_MODE_PROTON && !(p.T_K > 0.0 && p.p_atm > 0.0 && p.d_ionomer_rel > 0.0))
         return LBM_ERR_INVALID_ARG;
-    if ((int64_t)g.nx + 1 > (int64_t)1 << 30) return LBM_ERR_INVALID_ARG;
+    // the segment table packs row segment, y and z in 16 bits each
+    if ((int64_t)g.nx + 1 > (int64_t)kSeg * 65535 || g.ny > 65535 || g.nz > 65535) return LBM_ERR_INVALID_ARG;
     const int64_t Ns = (int64_t)g.nx * g.ny * g.nz;
     for (int64_t v = 0; v < Ns; ++v)
         if (phase[v] > LBM_IONOMER) return LBM_ERR_BAD_PHASE;

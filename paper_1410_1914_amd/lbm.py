@@ -47,6 +47,7 @@ class lbm_params(ctypes.Structure):
 class lbm_run_info(ctypes.Structure):
     _fields_ = [("steps", c_int64), ("residual", c_double), ("j_in", c_double), ("j_out", c_double),
                 ("j_vol", c_double), ("rate", c_double), ("mass", c_double), ("est_error", c_double),
+                ("kernel_ms", c_double), ("kernel_launches", c_int64),
                 ("status", c_int32), ("checks", c_int32)]
 
     def as_dict(self):
@@ -85,6 +86,10 @@ SIGNATURES = {
     "lbm_step": ([_P, c_int64], c_int32),
     "lbm_measure": ([_P, ctypes.POINTER(lbm_run_info)], c_int32),
     "lbm_run_to_steady": ([_P, ctypes.POINTER(lbm_run_info)], c_int32),
+    "lbm_advance": ([_P, c_int64, ctypes.POINTER(lbm_run_info)], c_int32),
+    "lbm_set_tiling": ([_P, c_int32, c_int32, c_int32], c_int32),
+    "lbm_get_tiling": ([_P, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32), ctypes.POINTER(c_int32)], c_int32),
+    "lbm_autotune": ([_P, c_int32, ctypes.POINTER(c_double)], c_int32),
     "lbm_deff": ([_P, ctypes.POINTER(c_double)], c_int32),
     "lbm_reaction_rate": ([_P, ctypes.POINTER(c_double), ctypes.POINTER(c_double)], c_int32),
     "lbm_concentration": ([_P, _P], c_int32),
@@ -226,6 +231,30 @@ def lbm_run_to_steady(h):
     if st < 0 and st != ERR_NO_PERCOLATION:
         raise LbmError("lbm_run_to_steady", st)
     return st, r
+
+
+def lbm_advance(h, max_new_steps: int):
+    r = lbm_run_info()
+    st = load().lbm_advance(h, max_new_steps, ctypes.byref(r))
+    if st < 0 and st != ERR_NO_PERCOLATION:
+        raise LbmError("lbm_advance", st)
+    return st, r
+
+
+def lbm_set_tiling(h, segs_per_wave, waves_per_block, xcd_remap):
+    return _check("lbm_set_tiling", load().lbm_set_tiling(h, segs_per_wave, waves_per_block, xcd_remap))
+
+
+def lbm_get_tiling(h):
+    a, b, c = c_int32(), c_int32(), c_int32()
+    _check("lbm_get_tiling", load().lbm_get_tiling(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def lbm_autotune(h, steps_per_trial: int = 20):
+    ms = c_double()
+    _check("lbm_autotune", load().lbm_autotune(h, steps_per_trial, ctypes.byref(ms)))
+    return ms.value
 
 
 def lbm_deff(h):
@@ -411,6 +440,18 @@ class Solver:
 
     def run_to_steady(self):
         return lbm_run_to_steady(self.h)
+
+    def advance(self, max_new_steps):
+        return lbm_advance(self.h, max_new_steps)
+
+    def set_tiling(self, spw, waves, xcd):
+        return lbm_set_tiling(self.h, spw, waves, xcd)
+
+    def tiling(self):
+        return lbm_get_tiling(self.h)
+
+    def autotune(self, steps_per_trial=20):
+        return lbm_autotune(self.h, steps_per_trial)
 
     def deff(self):
         return lbm_deff(self.h)
