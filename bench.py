@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--no-solves", action="store_true", help="skip the 32^3 solves/s legs")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-start leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU time budget of the oracle sample")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default tiling (no autotuning)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy three times (calibrates HBM byte counters) and exit")
     return ap.parse_args()
 
 
@@ -60,14 +63,27 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(info, knudsen: bool, react: bool) -> float:
+def algorithmic_bytes(info, knudsen: bool, n_listed: int) -> float:
     """Bytes one stream-collide launch must move: 7 FP32 reads + 7 FP32 writes per
-    fluid voxel (+4 for its FP32 1/tau with Knudsen), and per 64-voxel segment its
-    fluid mask (8) and prefix (4), plus the reactive and catalyst masks (16) when
-    reacting or the ionomer mask (8) when 1/tau comes from the phase."""
+    fluid voxel (+4 for its FP32 1/tau with Knudsen), and per listed 64-voxel
+    segment its 120-byte record and 4-byte list entry."""
     per_fluid = 56.0 + (4.0 if knudsen else 0.0)
-    per_seg = 12.0 + (16.0 if react else 0.0) + (0.0 if knudsen else 8.0)
-    return info.n_active * per_fluid + info.n_segments * per_seg
+    return info.n_active * per_fluid + n_listed * 124.0
+
+
+def ph_listed(ph, n):
+    """Number of 64-voxel row segments holding at least one simulated voxel (the
+    reactive problem prepends one pore plane, so every row's first segment counts)."""
+    import numpy as np
+
+    nz, ny, nx = ph.shape
+    nxs = nx + 1
+    nsx = (nxs + 63) // 64
+    transport = np.isin(ph, (0, 3))
+    pad = np.zeros((nz, ny, nsx * 64), bool)
+    pad[:, :, 0] = True
+    pad[:, :, 1:nx + 1] = transport
+    return int(pad.reshape(nz, ny, nsx, 64).any(axis=3).sum())
 
 
 def traffic_from_profiles(kernel_sha: str, workload: str):
@@ -100,7 +116,7 @@ def headline(args, lbm, structgen):
     info = s.info
     log(f"[bench] {n}^3 NPMC: generated in {t_gen:.1f}s, preprocessed+bound in {t_prep:.1f}s, "
         f"{info.n_active} fluid voxels, {info.n_segments} segments")
-    tune_ms = s.autotune(10)
+    tune_ms = s.autotune(10) if not args.no_tune else float("nan")
     tiling = s.tiling()
     log(f"[bench] autotuned tiling (segments/wave, waves/workgroup, xcd) = {tiling}: {tune_ms*1e3:.1f} us/step")
     _, r0 = s.advance(0)
@@ -119,7 +135,7 @@ def headline(args, lbm, structgen):
     updates = info.n_active * launches
     mlups = updates / wall / 1e6
     per_launch_s = kms / 1e3 / launches
-    alg = algorithmic_bytes(info, knudsen=True, react=True)
+    alg = algorithmic_bytes(info, knudsen=True, n_listed=int((ph_listed(ph, n))))
     achieved = alg / per_launch_s / 1e9
     log(f"[bench] {launches} LBM steps in {wall:.3f}s: {mlups:.0f} MLUPS; kernel mean {per_launch_s*1e6:.1f} us, "
         f"{achieved:.0f} GB/s algorithmic")
@@ -221,6 +237,15 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     import torch  # noqa: F401
+
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_each_way": src.numel() * 4, "copies": 3}))
+        return
 
     import structgen
     from paper_1410_1914_amd import lbm

@@ -59,9 +59,8 @@ struct Engine {
 
     // workspace
     size_t ws_need = 0;
-    size_t off_f0 = 0, off_f1 = 0, off_om = 0, off_snap = 0, off_mf = 0, off_mi = 0, off_mr = 0, off_mc = 0,
-           off_pre = 0, off_inst = 0, off_dbase = 0, off_sblk = 0, off_cblk = 0, off_mblk = 0, off_rng = 0,
-           off_part = 0, off_res = 0;
+    size_t off_f0 = 0, off_f1 = 0, off_om = 0, off_snap = 0, off_rec = 0, off_inst = 0, off_dbase = 0, off_sblk = 0,
+           off_cblk = 0, off_mblk = 0, off_rng = 0, off_part = 0, off_res = 0;
     int64_t cap_sblk = 0, cap_cblk = 0, cap_mblk = 0;
 
     bool bound = false;
@@ -124,14 +123,10 @@ struct Engine {
         off_f1 = take(sizeof(float) * 7 * stride);
         off_om = knudsen ? take(sizeof(float) * stride) : 0;
         off_snap = take(sizeof(float) * stride);
-        off_mf = take(sizeof(uint64_t) * nseg_total);
-        off_mi = take(sizeof(uint64_t) * nseg_total);
-        off_mr = take(sizeof(uint64_t) * nseg_total);
-        off_mc = take(sizeof(uint64_t) * nseg_total);
-        off_pre = take(sizeof(uint32_t) * nseg_total);
+        off_rec = take(sizeof(SegRec) * nseg_total);
         off_inst = take(sizeof(InstDev) * ninst);
         off_dbase = take(sizeof(int64_t) * ninst);
-        off_sblk = take(sizeof(SegEntry) * cap_sblk);
+        off_sblk = take(sizeof(uint32_t) * cap_sblk);
         off_cblk = take(sizeof(int2) * cap_cblk);
         off_mblk = take(sizeof(int4) * cap_mblk);
         off_rng = take(sizeof(int2) * ninst);
@@ -163,16 +158,12 @@ struct Engine {
     }
 
     hipError_t upload_tables() {
-        // step table: the segments holding fluid of every live instance, in grid order
-        std::vector<SegEntry> sb;
+        // step list: the segments holding fluid of every live instance, in grid order
+        std::vector<uint32_t> sb;
         for (int i : live) {
             const Prepared &p = P[i];
-            for (int64_t g = 0; g < p.nseg; ++g) {
-                if (!p.m_fluid[g]) continue;
-                const int s = (int)(g % p.nsx);
-                const int64_t row = g / p.nsx;
-                sb.push_back(SegEntry{(uint16_t)s, (uint16_t)(row % p.ny), (uint16_t)(row / p.ny), (uint16_t)i});
-            }
+            for (int64_t g = 0; g < p.nseg; ++g)
+                if (p.m_fluid[g]) sb.push_back((uint32_t)(seg_base[i] + g));
         }
         step_nent = (int)sb.size();
         const int per = waves * spw;
@@ -189,13 +180,55 @@ struct Engine {
         meas_nblk = (int)mb.size();
         hipError_t e = hipSuccess;
         if (!sb.empty())
-            e = hipMemcpyAsync(at<SegEntry>(off_sblk), sb.data(), sizeof(SegEntry) * sb.size(), hipMemcpyHostToDevice, st);
+            e = hipMemcpyAsync(at<uint32_t>(off_sblk), sb.data(), sizeof(uint32_t) * sb.size(), hipMemcpyHostToDevice, st);
         if (e == hipSuccess && !mb.empty())
             e = hipMemcpyAsync(at<int4>(off_mblk), mb.data(), sizeof(int4) * mb.size(), hipMemcpyHostToDevice, st);
         if (e == hipSuccess) e = hipMemcpyAsync(at<int2>(off_rng), rg.data(), sizeof(int2) * ninst, hipMemcpyHostToDevice, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);  // host vectors go out of scope
         g_valid = false;
         return e;
+    }
+
+    // Segment records of instance i (see SegRec): masks and compact prefixes of the
+    // segment and of its four neighbour rows, and the reaction bit planes.
+    void build_records(int i, SegRec *out) const {
+        const Prepared &p = P[i];
+        const int nsx = p.nsx, ny = p.ny, nz = p.nz;
+        const int64_t rs = nsx, ps = (int64_t)ny * nsx;
+        for (int64_t g = 0; g < p.nseg; ++g) {
+            SegRec r{};
+            const int s = (int)(g % nsx);
+            const int64_t row = g / nsx;
+            const int y = (int)(row % ny), z = (int)(row / ny);
+            const uint64_t m = p.m_fluid[g];
+            const uint64_t mp = s > 0 ? p.m_fluid[g - 1] : 0ull;
+            const uint64_t mn = s + 1 < nsx ? p.m_fluid[g + 1] : 0ull;
+            const int64_t gn[4] = {g + (y == 0 ? (int64_t)(ny - 1) * rs : -rs), g + (y == ny - 1 ? -(int64_t)(ny - 1) * rs : rs),
+                                   g + (z == 0 ? (int64_t)(nz - 1) * ps : -ps), g + (z == nz - 1 ? -(int64_t)(nz - 1) * ps : ps)};
+            r.m = m;
+            r.left = (m << 1) | (mp >> 63);
+            r.right = (m >> 1) | (mn << 63);
+            for (int k = 0; k < 4; ++k) {
+                r.nb[k] = p.m_fluid[gn[k]];
+                r.pnb[k] = (uint32_t)(fluid_base[i] + p.prefix[gn[k]]);
+            }
+            r.ion = p.m_ion[g];
+            const uint64_t mr = p.m_react[g];
+            const int64_t v0 = row * p.nx + (int64_t)s * kSeg;
+            for (int l = 0; l < kSeg && s * kSeg + l < p.nx; ++l) {
+                if (!((mr >> l) & 1ull)) continue;
+                const int n = p.n_cat[v0 + l];
+                if (n & 1) r.n0 |= 1ull << l;
+                if (n & 2) r.n1 |= 1ull << l;
+                if (n & 4) r.n2 |= 1ull << l;
+            }
+            r.pre = (uint32_t)(fluid_base[i] + p.prefix[g]);
+            r.s = (uint16_t)s;
+            r.y = (uint16_t)y;
+            r.z = (uint16_t)z;
+            r.inst = (uint16_t)i;
+            out[g] = r;
+        }
     }
 
     hipError_t bind(void *mem, size_t bytes, hipStream_t stream) {
@@ -218,41 +251,27 @@ struct Engine {
         f[0] = at<float>(off_f0);
         f[1] = at<float>(off_f1);
         csnap = at<float>(off_snap);
-        L.m_fluid = at<uint64_t>(off_mf);
-        L.m_ion = at<uint64_t>(off_mi);
-        L.m_react = at<uint64_t>(off_mr);
-        L.m_cat = at<uint64_t>(off_mc);
-        L.prefix = at<uint32_t>(off_pre);
+        L.rec = at<SegRec>(off_rec);
         L.omega = knudsen ? at<float>(off_om) : nullptr;
         L.inst = at<InstDev>(off_inst);
-        L.stride = stride;
+        L.stride = (uint32_t)stride;
         // metadata (host staging, then one synchronisation)
-        std::vector<uint64_t> mf(nseg_total), mi(nseg_total), mr(nseg_total), mc(nseg_total);
-        std::vector<uint32_t> pre(nseg_total);
+        std::vector<SegRec> rec(nseg_total);
         std::vector<float> om(knudsen ? nf_total : 0);
         std::vector<InstDev> id(ninst);
         std::vector<int2> cb;
         for (int i = 0; i < ninst; ++i) {
+            build_records(i, rec.data() + seg_base[i]);
             const Prepared &p = P[i];
-            std::copy(p.m_fluid.begin(), p.m_fluid.end(), mf.begin() + seg_base[i]);
-            std::copy(p.m_ion.begin(), p.m_ion.end(), mi.begin() + seg_base[i]);
-            std::copy(p.m_react.begin(), p.m_react.end(), mr.begin() + seg_base[i]);
-            std::copy(p.m_cat.begin(), p.m_cat.end(), mc.begin() + seg_base[i]);
-            for (int64_t s = 0; s < p.nseg; ++s) pre[seg_base[i] + s] = (uint32_t)(p.prefix[s] + fluid_base[i]);
             if (knudsen) std::copy(p.omega_c.begin(), p.omega_c.end(), om.begin() + fluid_base[i]);
             id[i] = inst_dev(i);
             for (int64_t b = 0; b < (p.nseg + 3) / 4; ++b) cb.push_back(make_int2(i, (int)(b * 4)));
         }
         conv_nblk = (int)cb.size();
-        if (nf_total > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
         auto up = [&](size_t off, const void *src, size_t n) {
             return note(n ? hipMemcpyAsync(ws + off, src, n, hipMemcpyHostToDevice, st) : hipSuccess, "upload");
         };
-        if ((e = up(off_mf, mf.data(), 8 * mf.size())) != hipSuccess) return e;
-        if ((e = up(off_mi, mi.data(), 8 * mi.size())) != hipSuccess) return e;
-        if ((e = up(off_mr, mr.data(), 8 * mr.size())) != hipSuccess) return e;
-        if ((e = up(off_mc, mc.data(), 8 * mc.size())) != hipSuccess) return e;
-        if ((e = up(off_pre, pre.data(), 4 * pre.size())) != hipSuccess) return e;
+        if ((e = up(off_rec, rec.data(), sizeof(SegRec) * rec.size())) != hipSuccess) return e;
         if (knudsen && (e = up(off_om, om.data(), 4 * om.size())) != hipSuccess) return e;
         if ((e = up(off_inst, id.data(), sizeof(InstDev) * id.size())) != hipSuccess) return e;
         if ((e = up(off_dbase, dense_base.data(), 8 * dense_base.size())) != hipSuccess) return e;
@@ -292,7 +311,8 @@ struct Engine {
         s.xcd = xcd;
         s.nblk = step_nblk;
         s.nent = step_nent;
-        s.seg = at<SegEntry>(off_sblk);
+        s.list = at<uint32_t>(off_sblk);
+        s.single = ninst == 1 ? 1 : 0;
         return s;
     }
 
@@ -582,7 +602,8 @@ int make_engine(int n, const lbm_grid *grids, const uint8_t *const *phases, cons
     E->react = E->mode == LBM_MODE_REACT;
     E->check_every = params[0].check_every;
     E->layout();
-    if (E->nseg_total > (int64_t)INT32_MAX) return LBM_ERR_INVALID_ARG;
+    // segment indices are 32-bit; population byte offsets are 32-bit (buffer resources)
+    if (E->nseg_total > (int64_t)INT32_MAX || 28 * E->stride >= ((int64_t)1 << 32) - 64) return LBM_ERR_INVALID_ARG;
     E->rs.assign(n, RunState{});
     out = std::move(E);
     return LBM_OK;

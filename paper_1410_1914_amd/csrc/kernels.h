@@ -23,38 +23,48 @@ struct alignas(64) InstDev {
     float om_pore, om_ion;    // relaxation rates when not stored per voxel
 };
 
-// Device views of the workspace.
-struct Lattice {
-    const uint64_t *m_fluid, *m_ion, *m_react, *m_cat;  // per segment bitmasks
-    const uint32_t *prefix;   // global compact index of the first fluid voxel of a segment
-    const float *omega;       // per fluid voxel 1/tau (Knudsen problems), else null
-    const InstDev *inst;
-    int64_t stride;           // elements per population array
+// Everything a wave needs to update one 64-voxel row segment (one bit per lane).
+// Built once on the host; the stream-collide kernel reads it with a few scalar
+// loads instead of recomputing neighbour rows and bit shifts per step.
+struct SegRec {
+    uint64_t m;              // lanes that are simulated (fluid)
+    uint64_t left, right;    // lanes whose x-1 / x+1 neighbour is fluid (x faces excluded)
+    uint64_t nb[4];          // fluid masks of the rows y-1, y+1, z-1, z+1 over the same x range
+    uint64_t ion;            // ionomer lanes (relaxation rate from the phase)
+    uint64_t n0, n1, n2;     // bit planes of n, the catalyst face-neighbour count, of reacting lanes
+    uint32_t pre;            // global compact index of the first fluid lane
+    uint32_t pnb[4];         // the same for the four neighbour rows
+    uint16_t s, y, z, inst;  // segment position: x0 = 64 s, row y, plane z; its instance
+    uint32_t pad;
 };
+static_assert(sizeof(SegRec) == 120, "SegRec layout");
 
 // Quantities reduced per instance, in this order.
 enum { Q_JIN = 0, Q_JOUT, Q_JINT, Q_RATE, Q_MASS, Q_DCMAX, Q_CMAX, Q_BAD, NQ };
 
-// One entry per row segment that holds fluid: its position in its instance.
-struct SegEntry {
-    uint16_t s, y, z, inst;
+struct Lattice {
+    const SegRec *rec;        // per segment of every instance
+    const float *omega;       // per fluid voxel 1/tau (Knudsen problems), else null
+    const InstDev *inst;
+    uint32_t stride;          // elements per population array (7 * stride * 4 < 2^32)
 };
 
 struct StepLaunch {
-    int32_t waves;        // waves per workgroup: 1, 2, 4, 8
-    int32_t spw;          // segments per wave: 1, 2, 4
-    int32_t xcd;          // XCD-aware block order
-    int32_t nblk;         // workgroups
-    int32_t nent;         // entries of the segment table
-    const SegEntry *seg;  // segments with fluid, in grid order
+    int32_t waves;            // waves per workgroup: 1, 2, 4, 8
+    int32_t spw;              // segments per wave: 1, 2, 4
+    int32_t xcd;              // XCD-aware block order
+    int32_t nblk;             // workgroups
+    int32_t nent;             // entries of the list
+    const uint32_t *list;     // segments with fluid of the live instances, in grid order
+    int32_t single;           // 1: one instance (its constants load without waiting for the record)
 };
 
 struct MeasureLaunch {
     int32_t nblk;
-    const int4 *blk;      // per workgroup: {instance, block within instance, blocks of instance, partial slot}
-    double *partial;      // [nblk][NQ]
+    const int4 *blk;          // per workgroup: {instance, block within instance, blocks of instance, partial slot}
+    double *partial;          // [nblk][NQ]
     int32_t update_snap;
-    float *csnap;         // per fluid voxel concentration snapshot
+    float *csnap;             // per fluid voxel concentration snapshot
 };
 
 hipError_t launch_step(const Lattice &L, const StepLaunch &S, bool knudsen, bool react, const float *fin,
@@ -63,8 +73,8 @@ hipError_t launch_measure(const Lattice &L, const MeasureLaunch &M, bool react, 
 // results[i*NQ + q] from partials of blocks [base_i, base_i + count_i): ranges[i] = {base, count}
 hipError_t launch_finish(const double *partial, const int2 *ranges, int32_t ninst, double *results, hipStream_t st);
 
-// dense <-> compact conversions over all segments of the listed instances
-// (blk as for the step kernel with waves = 4, spw = 1)
+// Dense <-> compact conversions over every segment of the instances in blk
+// (entries {instance, first local segment}, four segments per 256-thread block).
 hipError_t launch_init_eq(const Lattice &L, int32_t nblk, const int2 *blk, bool react, const float *c_dense,
                           const int64_t *dense_base, float *f, float *csnap, hipStream_t st);
 hipError_t launch_set_pop(const Lattice &L, int32_t nblk, const int2 *blk, const float *f_dense,

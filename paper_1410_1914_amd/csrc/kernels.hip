@@ -5,26 +5,45 @@
 // boundaries of Section 3.5 (Eqs. 19, 20a, 20b).
 //
 // Layout (one wave64 = one 64-voxel row segment = one 64-bit mask word):
-//   * m_fluid[seg] bit l is set when voxel (64 s + l, y, z) is simulated.
 //   * Fluid voxels are stored compactly in x-fastest order; the compact index of a
-//     fluid lane is prefix[seg] + mbcnt(m_fluid[seg]) (count of fluid lanes below it).
-//   * The compact index of the +-y / +-z neighbour is found the same way from the
-//     neighbour row's mask word and prefix, so no per-voxel neighbour table exists.
+//     fluid lane is pre + mbcnt(m) (the number of fluid lanes below it).
+//   * A segment record (SegRec) carries the masks and compact prefixes of the four
+//     neighbour rows, so the compact index of the +-y / +-z neighbour is the same
+//     mbcnt on that row's mask: no per-voxel neighbour table exists.
 //   * Populations are SoA: f[i * stride + j], i = rest, +x, -x, +y, -y, +z, -z, stored
 //     post-collision as g_i = f_i - w_i c_sh(x), c_sh the linear empty-box profile
 //     (a constant for the reactive problem).  The shift is exact; it keeps the stored
 //     values small so FP32 storage resolves the fluxes.
 //   * Arithmetic is FP64: the seven FP32 loads are summed exactly, and each stored
 //     value carries a single rounding, so rounding does not bias the mass balance.
+//   * Populations are read and written through buffer resources: 32-bit byte
+//     offsets, and the hardware range check turns any out-of-range access into a
+//     zero read or a dropped write.
 //
 // Every stored value is read exactly once per step (by the voxel it streams into,
 // or by its own voxel when bounced back), and every fluid voxel writes its seven
-// populations once: 56 bytes per fluid update plus the relaxation rate in Knudsen
-// problems.  Solid voxels cost nothing but their share of the mask words.
+// populations once: 56 bytes per fluid update, plus the relaxation rate in Knudsen
+// problems and the segment record (120 bytes per 64 voxels).
 #include "kernels.h"
 
 namespace cl {
 namespace {
+
+// dword 3 of a raw (untyped, unswizzled) buffer resource on the gfx9 family
+constexpr int kRawBuffer = 0x00020000;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, kRawBuffer);
+}
+
+// the b32 buffer builtins move raw 32-bit words: reinterpret, never convert
+__device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
+__device__ __forceinline__ void st(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 0);
+}
 
 __device__ __forceinline__ int mbcnt64(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -32,8 +51,16 @@ __device__ __forceinline__ int mbcnt64(uint64_t m) {
 
 __device__ __forceinline__ int bit(uint64_t m, int lane) { return (int)((m >> lane) & 1ull); }
 
+// Per-lane select by the lane's bit of a wave-uniform mask held in an SGPR pair:
+// one v_cndmask_b32 instead of a 64-bit shift, an and and a compare.
+__device__ __forceinline__ uint32_t lane_sel(uint64_t m, uint32_t if_set, uint32_t if_clear) {
+    uint32_t r;
+    asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(r) : "v"(if_clear), "v"(if_set), "s"(m));
+    return r;
+}
+
 // Workgroups are dealt to the 8 XCDs round robin; renumber them so that each XCD
-// works on one contiguous eighth of the grid (neighbour rows then share its L2).
+// works on one contiguous eighth of the list (neighbour rows then share its L2).
 __device__ __forceinline__ int logical_block(int b, int nblk, int remap) {
     if (!remap || nblk < 8) return b;
     const int q = nblk >> 3, r = nblk & 7;
@@ -41,132 +68,102 @@ __device__ __forceinline__ int logical_block(int b, int nblk, int remap) {
     return x * q + min(x, r) + (b >> 3);
 }
 
-struct Seg {
-    int64_t g;             // global segment
-    int s, y, z;
-    int64_t gym, gyp, gzm, gzp;
-};
-
-__device__ __forceinline__ Seg locate(const InstDev &I, int64_t sl) {
-    Seg q;
-    q.s = (int)(sl % I.nsx);
-    const int64_t row = sl / I.nsx;
-    q.y = (int)(row % I.ny);
-    q.z = (int)(row / I.ny);
-    q.g = I.seg_base + sl;
-    const int64_t rs = I.nsx, ps = (int64_t)I.ny * I.nsx;
-    q.gym = q.g + (q.y == 0 ? (int64_t)(I.ny - 1) * rs : -rs);
-    q.gyp = q.g + (q.y == I.ny - 1 ? -(int64_t)(I.ny - 1) * rs : rs);
-    q.gzm = q.g + (q.z == 0 ? (int64_t)(I.nz - 1) * ps : -ps);
-    q.gzp = q.g + (q.z == I.nz - 1 ? -(int64_t)(I.nz - 1) * ps : ps);
-    return q;
+// catalyst face-neighbour count of reacting lanes, from the record's bit planes
+__device__ __forceinline__ int react_n(const SegRec &R, int lane) {
+    return bit(R.n0, lane) + 2 * bit(R.n1, lane) + 4 * bit(R.n2, lane);
 }
 
-// segment of a table entry: global index and periodic neighbour rows, no division
-__device__ __forceinline__ Seg locate_entry(const InstDev &I, SegEntry e) {
-    Seg q;
-    q.s = e.s;
-    q.y = e.y;
-    q.z = e.z;
-    const int64_t rs = I.nsx, ps = (int64_t)I.ny * I.nsx;
-    q.g = I.seg_base + (int64_t)q.z * ps + (int64_t)q.y * rs + q.s;
-    q.gym = q.g + (q.y == 0 ? (int64_t)(I.ny - 1) * rs : -rs);
-    q.gyp = q.g + (q.y == I.ny - 1 ? -(int64_t)(I.ny - 1) * rs : rs);
-    q.gzm = q.g + (q.z == 0 ? (int64_t)(I.nz - 1) * ps : -ps);
-    q.gzp = q.g + (q.z == I.nz - 1 ? -(int64_t)(I.nz - 1) * ps : ps);
-    return q;
+// Byte offset past every buffer: a lane with nothing to do loads 0 from here.
+constexpr uint32_t kOutOfRange = 0xFFFFFFF0u;
+
+// Gather phase of one segment: the seven pulled populations (bounce-back reads the
+// voxel's own opposite one) and the relaxation rate, issued without waiting.
+template <bool KNUDSEN>
+__device__ __forceinline__ void gather(const SegRec &R, __amdgpu_buffer_rsrc_t rin, __amdgpu_buffer_rsrc_t rom,
+                                       uint32_t S4, int lane, bool act, float (&r)[8], uint32_t &j4) {
+    const uint32_t j = R.pre + (uint32_t)mbcnt64(R.m);
+    j4 = act ? 4u * j : kOutOfRange;
+    const uint32_t o1 = lane_sel(R.left, 1u * S4 + j4 - 4u, 2u * S4 + j4);
+    const uint32_t o2 = lane_sel(R.right, 2u * S4 + j4 + 4u, 1u * S4 + j4);
+    const uint32_t o3 = lane_sel(R.nb[0], 3u * S4 + 4u * (R.pnb[0] + (uint32_t)mbcnt64(R.nb[0])), 4u * S4 + j4);
+    const uint32_t o4 = lane_sel(R.nb[1], 4u * S4 + 4u * (R.pnb[1] + (uint32_t)mbcnt64(R.nb[1])), 3u * S4 + j4);
+    const uint32_t o5 = lane_sel(R.nb[2], 5u * S4 + 4u * (R.pnb[2] + (uint32_t)mbcnt64(R.nb[2])), 6u * S4 + j4);
+    const uint32_t o6 = lane_sel(R.nb[3], 6u * S4 + 4u * (R.pnb[3] + (uint32_t)mbcnt64(R.nb[3])), 5u * S4 + j4);
+    r[0] = ld(rin, j4, 0);
+    r[1] = ld(rin, act ? o1 : kOutOfRange, 0);
+    r[2] = ld(rin, act ? o2 : kOutOfRange, 0);
+    r[3] = ld(rin, act ? o3 : kOutOfRange, 0);
+    r[4] = ld(rin, act ? o4 : kOutOfRange, 0);
+    r[5] = ld(rin, act ? o5 : kOutOfRange, 0);
+    r[6] = ld(rin, act ? o6 : kOutOfRange, 0);
+    if (KNUDSEN) r[7] = ld(rom, j4, 0);
 }
 
-// catalyst face neighbours of the lane's voxel (Eq. 18a): x bounded, y/z periodic
-__device__ __forceinline__ int catalyst_count(const Lattice &L, const Seg &q, int nsx, int lane) {
-    const uint64_t c = L.m_cat[q.g];
-    const uint64_t cp = q.s > 0 ? L.m_cat[q.g - 1] : 0ull;
-    const uint64_t cn = q.s + 1 < nsx ? L.m_cat[q.g + 1] : 0ull;
-    const uint64_t cl = (c << 1) | (cp >> 63);
-    const uint64_t cr = (c >> 1) | (cn << 63);
-    return bit(cl, lane) + bit(cr, lane) + bit(L.m_cat[q.gym], lane) + bit(L.m_cat[q.gyp], lane) +
-           bit(L.m_cat[q.gzm], lane) + bit(L.m_cat[q.gzp], lane);
-}
-
-// One fused pull stream + collide for the fluid lanes of one row segment.
+// Collide phase of one segment: FP64 collision with the sink, seven FP32 stores.
 template <bool KNUDSEN, bool REACT>
-__device__ __forceinline__ void step_segment(const Lattice &L, const InstDev &I, const Seg &q, int lane,
-                                             const float *__restrict__ fin, float *__restrict__ fout) {
-    const uint64_t m = L.m_fluid[q.g];
-    if (m == 0ull) return;
-    const uint64_t mp = q.s > 0 ? L.m_fluid[q.g - 1] : 0ull;
-    const uint64_t mn = q.s + 1 < I.nsx ? L.m_fluid[q.g + 1] : 0ull;
-    const uint64_t mym = L.m_fluid[q.gym], myp = L.m_fluid[q.gyp];
-    const uint64_t mzm = L.m_fluid[q.gzm], mzp = L.m_fluid[q.gzp];
-    const uint32_t pre = L.prefix[q.g];
-    const uint32_t pym = L.prefix[q.gym], pyp = L.prefix[q.gyp];
-    const uint32_t pzm = L.prefix[q.gzm], pzp = L.prefix[q.gzp];
-    const uint64_t left = (m << 1) | (mp >> 63);   // bit l: voxel x-1 is fluid
-    const uint64_t right = (m >> 1) | (mn << 63);  // bit l: voxel x+1 is fluid
-    uint64_t mion = 0, mreact = 0;
-    if (!KNUDSEN) mion = L.m_ion[q.g];
-    if (REACT) mreact = L.m_react[q.g];
-    int ncat = 0;
-    if (REACT) ncat = catalyst_count(L, q, I.nsx, lane);
-
-    if (!bit(m, lane)) return;
-    const int64_t S = L.stride;
-    const int64_t j = (int64_t)pre + mbcnt64(m);
-    const int x = q.s * 64 + lane;
-
-    // pull the seven populations (bounce-back reads the voxel's own opposite one)
-    const bool fl = bit(left, lane), fr = bit(right, lane);
-    const int64_t a1 = fl ? 1 * S + j - 1 : 2 * S + j;
-    const int64_t a2 = fr ? 2 * S + j + 1 : 1 * S + j;
-    const int64_t a3 = bit(mym, lane) ? 3 * S + (int64_t)pym + mbcnt64(mym) : 4 * S + j;
-    const int64_t a4 = bit(myp, lane) ? 4 * S + (int64_t)pyp + mbcnt64(myp) : 3 * S + j;
-    const int64_t a5 = bit(mzm, lane) ? 5 * S + (int64_t)pzm + mbcnt64(mzm) : 6 * S + j;
-    const int64_t a6 = bit(mzp, lane) ? 6 * S + (int64_t)pzp + mbcnt64(mzp) : 5 * S + j;
-    const float r0 = fin[j], r1 = fin[a1], r2 = fin[a2], r3 = fin[a3], r4 = fin[a4], r5 = fin[a5], r6 = fin[a6];
-    const double p0 = r0, p3 = r3, p4 = r4, p5 = r5, p6 = r6;
-    // +-x: re-reference to this voxel's shift; x faces: anti-bounce-back Dirichlet at
-    // the inlet, Dirichlet (anti-bounce-back) or zero-gradient (bounce-back) outlet
-    double p1 = fl ? (double)r1 + I.pull_dx : (double)r1;
-    double p2 = fr ? (double)r2 - I.pull_dx : (double)r2;
-    if (x == 0) p1 = I.abb_in - (double)r1;
-    if (!REACT && x == I.nx - 1) p2 = I.abb_out - (double)r2;
-
-    const double Cs = ((p0 + p1) + (p2 + p3)) + ((p4 + p5) + p6);  // C - c_sh(x), exact
+__device__ __forceinline__ void collide_store(const SegRec &R, const InstDev &I, __amdgpu_buffer_rsrc_t rout,
+                                              uint32_t S4, int lane, const float (&r)[8], uint32_t j4) {
+    const int x = (int)R.s * 64 + lane;
     double om;
     if (KNUDSEN)
-        om = (double)L.omega[j];
+        om = (double)r[7];
     else
-        om = (double)(bit(mion, lane) ? I.om_ion : I.om_pore);
+        om = (double)__uint_as_float(lane_sel(R.ion, __float_as_uint(I.om_ion), __float_as_uint(I.om_pore)));
+    const double p0 = r[0], p3 = r[3], p4 = r[4], p5 = r[5], p6 = r[6];
+    // +-x: re-reference to this voxel's shift; x faces: anti-bounce-back Dirichlet at
+    // the inlet, Dirichlet (anti-bounce-back) or zero-gradient (bounce-back) outlet
+    double p1 = bit(R.left, lane) ? (double)r[1] + I.pull_dx : (double)r[1];
+    double p2 = bit(R.right, lane) ? (double)r[2] - I.pull_dx : (double)r[2];
+    if (x == 0) p1 = I.abb_in - (double)r[1];
+    if (!REACT && x == I.nx - 1) p2 = I.abb_out - (double)r[2];
+
+    const double Cs = ((p0 + p1) + (p2 + p3)) + ((p4 + p5) + p6);  // C - c_sh(x), exact
     double s0 = 0.0, s1 = 0.0;
     if (REACT) {
-        const double kn = bit(mreact, lane) ? I.k * (double)ncat : 0.0;
+        const double kn = I.k * (double)react_n(R, lane);
         const double sink = -kn * (Cs + (I.sh0 - I.slope * (double)x));
         s0 = I.w0 * sink;
         s1 = I.w1 * sink;
     }
     const double e0 = I.w0 * Cs, e1 = I.w1 * Cs;
-    fout[j] = (float)(fma(om, e0 - p0, p0) + s0);
-    fout[1 * S + j] = (float)(fma(om, e1 - p1, p1) + s1);
-    fout[2 * S + j] = (float)(fma(om, e1 - p2, p2) + s1);
-    fout[3 * S + j] = (float)(fma(om, e1 - p3, p3) + s1);
-    fout[4 * S + j] = (float)(fma(om, e1 - p4, p4) + s1);
-    fout[5 * S + j] = (float)(fma(om, e1 - p5, p5) + s1);
-    fout[6 * S + j] = (float)(fma(om, e1 - p6, p6) + s1);
+    st((float)(fma(om, e0 - p0, p0) + s0), rout, j4, 0);
+    st((float)(fma(om, e1 - p1, p1) + s1), rout, j4, 1u * S4);
+    st((float)(fma(om, e1 - p2, p2) + s1), rout, j4, 2u * S4);
+    st((float)(fma(om, e1 - p3, p3) + s1), rout, j4, 3u * S4);
+    st((float)(fma(om, e1 - p4, p4) + s1), rout, j4, 4u * S4);
+    st((float)(fma(om, e1 - p5, p5) + s1), rout, j4, 5u * S4);
+    st((float)(fma(om, e1 - p6, p6) + s1), rout, j4, 6u * S4);
 }
 
-template <int WAVES, int SPW, bool KNUDSEN, bool REACT>
-__global__ __launch_bounds__(WAVES * 64) void k_step(Lattice L, const SegEntry *__restrict__ seg, int nent, int nblk,
-                                                    int remap, const float *__restrict__ fin, float *__restrict__ fout) {
+// Fused pull stream + collide.  Each wave takes SPW consecutive list entries (row
+// segments holding fluid) and issues all their loads before any arithmetic, so a
+// wave keeps SPW x 8 loads in flight.
+template <int WAVES, int SPW, bool KNUDSEN, bool REACT, bool SINGLE>
+__global__ __launch_bounds__(WAVES * 64) void k_step(Lattice L, StepLaunch S, const float *__restrict__ fin,
+                                                    float *__restrict__ fout) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int b = logical_block(blockIdx.x, nblk, remap);
+    const int b = logical_block(blockIdx.x, S.nblk, S.xcd);
+    const uint32_t S4 = 4u * L.stride;
+    const __amdgpu_buffer_rsrc_t rin = rsrc(fin, 7u * S4), rout = rsrc(fout, 7u * S4);
+    const __amdgpu_buffer_rsrc_t rom = rsrc(L.omega, KNUDSEN ? S4 : 0u);
+    const int base = (b * WAVES + wave) * SPW;
+    const SegRec *R[SPW];
+    bool act[SPW];
+    float r[SPW][8];
+    uint32_t j4[SPW];
 #pragma unroll
     for (int k = 0; k < SPW; ++k) {
-        const int idx = (b * WAVES + wave) * SPW + k;
-        if (idx < nent) {
-            const SegEntry e = seg[idx];
-            const InstDev &I = L.inst[e.inst];
-            step_segment<KNUDSEN, REACT>(L, I, locate_entry(I, e), lane, fin, fout);
+        const bool valid = base + k < S.nent;  // wave-uniform
+        R[k] = &L.rec[S.list[valid ? base + k : 0]];
+        act[k] = valid && bit(R[k]->m, lane);
+        gather<KNUDSEN>(*R[k], rin, rom, S4, lane, act[k], r[k], j4[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < SPW; ++k) {
+        if (act[k]) {
+            const InstDev &I = L.inst[SINGLE ? 0 : R[k]->inst];
+            collide_store<KNUDSEN, REACT>(*R[k], I, rout, S4, lane, r[k], j4[k]);
         }
     }
 }
@@ -200,38 +197,28 @@ __global__ __launch_bounds__(kMeasWaves * 64) void k_measure(Lattice L, MeasureL
 #pragma unroll
     for (int i = 0; i < NQ; ++i) acc[i] = 0.0;
     for (int64_t sl = (int64_t)t.y * kMeasWaves + wave; sl < I.nseg; sl += (int64_t)t.z * kMeasWaves) {
-        const Seg q = locate(I, sl);
-        const uint64_t m = L.m_fluid[q.g];
+        const SegRec &R = L.rec[I.seg_base + sl];
+        const uint64_t m = R.m;
         if (m == 0ull) continue;
-        const uint64_t mn = q.s + 1 < I.nsx ? L.m_fluid[q.g + 1] : 0ull;
-        const uint64_t right = (m >> 1) | (mn << 63);
-        const uint32_t pre = L.prefix[q.g];
-        int ncat = 0;
-        uint64_t mreact = 0;
-        if (REACT) {
-            ncat = catalyst_count(L, q, I.nsx, lane);
-            mreact = L.m_react[q.g];
-        }
         if (!bit(m, lane)) continue;
-        const int64_t j = (int64_t)pre + mbcnt64(m);
-        const int x = q.s * 64 + lane;
+        const int64_t j = (int64_t)R.pre + mbcnt64(m);
+        const int x = (int)R.s * 64 + lane;
         double cs = 0.0;
 #pragma unroll
         for (int i = 0; i < 7; ++i) cs += (double)f[i * S + j];
-        const double kn = (REACT && bit(mreact, lane)) ? I.k * ncat : 0.0;
+        const double kn = REACT ? I.k * react_n(R, lane) : 0.0;
         const double C = (cs + (I.sh0 - I.slope * (double)x)) / (1.0 - kn);
         acc[Q_MASS] += C;
         acc[Q_RATE] += kn * C;
         if (x == 0) acc[Q_JIN] += I.abb_in - 2.0 * (double)f[2 * S + j];
         if (!REACT && x == I.nx - 1) acc[Q_JOUT] += 2.0 * (double)f[1 * S + j] - I.abb_out;
         // link flux f*_{+x}(x) - f*_{-x}(x+1); the shifts differ by w1 * slope
-        if (bit(right, lane)) acc[Q_JINT] += (double)f[1 * S + j] - (double)f[2 * S + j + 1] + I.pull_dx;
-        const float Cf = (float)C;
+        if (bit(R.right, lane)) acc[Q_JINT] += (double)f[1 * S + j] - (double)f[2 * S + j + 1] + I.pull_dx;
         const double dc = fabs(C - (double)M.csnap[j]);
         acc[Q_DCMAX] = fmax(acc[Q_DCMAX], dc);
         acc[Q_CMAX] = fmax(acc[Q_CMAX], fabs(C));
         if (!isfinite(C)) acc[Q_BAD] += 1.0;
-        if (M.update_snap) M.csnap[j] = Cf;
+        if (M.update_snap) M.csnap[j] = (float)C;
     }
     __shared__ double red[kMeasWaves][NQ];
 #pragma unroll
@@ -248,21 +235,30 @@ __global__ __launch_bounds__(kMeasWaves * 64) void k_measure(Lattice L, MeasureL
     }
 }
 
-__global__ void k_finish(const double *__restrict__ partial, const int2 *__restrict__ ranges, double *results) {
+// Per-instance totals of the reduction partials: 64 threads stride over the
+// instance's partial slots, then a fixed-order wave reduction (deterministic).
+__global__ __launch_bounds__(64) void k_finish(const double *__restrict__ partial, const int2 *__restrict__ ranges,
+                                               double *results) {
     const int inst = blockIdx.x;
-    const int i = threadIdx.x;
-    if (i >= NQ) return;
+    const int lane = threadIdx.x;
     const int2 r = ranges[inst];
-    double v = 0.0;
-    for (int b = 0; b < r.y; ++b) {
-        const double p = partial[(int64_t)(r.x + b) * NQ + i];
-        v = (i == Q_DCMAX || i == Q_CMAX) ? fmax(v, p) : v + p;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        const bool mx = (i == Q_DCMAX || i == Q_CMAX);
+        double v = 0.0;
+        for (int b = lane; b < r.y; b += 64) {
+            const double p = partial[(int64_t)(r.x + b) * NQ + i];
+            v = mx ? fmax(v, p) : v + p;
+        }
+        v = mx ? wave_max(v) : wave_sum(v);
+        if (lane == 0) results[(int64_t)inst * NQ + i] = v;
     }
-    results[(int64_t)inst * NQ + i] = v;
 }
 
 // ------------------------------------------------------------------ conversions
 
+// Calls fn(instance, I, dense voxel index v, compact index j or -1, catalyst count
+// of reacting lanes) for every lane of the segment whose x lies inside the grid.
 template <typename Fn>
 __device__ __forceinline__ void for_lanes(const Lattice &L, const int2 *blk, Fn fn) {
     const int lane = threadIdx.x & 63;
@@ -271,17 +267,13 @@ __device__ __forceinline__ void for_lanes(const Lattice &L, const int2 *blk, Fn 
     const InstDev &I = L.inst[t.x];
     const int64_t sl = (int64_t)t.y + wave;
     if (sl >= I.nseg) return;
-    const Seg q = locate(I, sl);
-    const uint64_t m = L.m_fluid[q.g];
-    int ncat = 0;
-    if (m) ncat = catalyst_count(L, q, I.nsx, lane);
-    const uint64_t mreact = L.m_react[q.g];
-    const int x = q.s * 64 + lane;
+    const SegRec &R = L.rec[I.seg_base + sl];
+    const int x = (int)R.s * 64 + lane;
     if (x >= I.nx) return;
-    const int64_t v = ((int64_t)q.z * I.ny + q.y) * I.nx + x;
-    const bool fluid = bit(m, lane);
-    const int64_t j = fluid ? (int64_t)L.prefix[q.g] + mbcnt64(m) : -1;
-    fn(t.x, I, v, j, (double)ncat * bit(mreact, lane));
+    const int64_t v = ((int64_t)R.z * I.ny + R.y) * I.nx + x;
+    const bool fluid = bit(R.m, lane);
+    const int64_t j = fluid ? (int64_t)R.pre + mbcnt64(R.m) : -1;
+    fn(t.x, I, v, j, (double)react_n(R, lane));
 }
 
 __global__ __launch_bounds__(256) void k_init_eq(Lattice L, const int2 *blk, int react, const float *c_dense,
@@ -293,7 +285,7 @@ __global__ __launch_bounds__(256) void k_init_eq(Lattice L, const int2 *blk, int
         const int x = (int)(v % I.nx);
         const double post = C * (1.0 - kn) - (I.sh0 - I.slope * x);  // equilibrium after the sink, shifted
         f[j] = (float)(I.w0 * post);
-        for (int i = 1; i < 7; ++i) f[i * L.stride + j] = (float)(I.w1 * post);
+        for (int i = 1; i < 7; ++i) f[i * (int64_t)L.stride + j] = (float)(I.w1 * post);
         csnap[j] = (float)C;
     });
 }
@@ -305,7 +297,7 @@ __global__ __launch_bounds__(256) void k_set_pop(Lattice L, const int2 *blk, con
         const int64_t d = dbase[inst] + v;
         const double sh = I.sh0 - I.slope * (double)(v % I.nx);
         f[j] = (float)((double)fd[d] - I.w0 * sh);
-        for (int i = 1; i < 7; ++i) f[i * L.stride + j] = (float)((double)fd[i * dstride + d] - I.w1 * sh);
+        for (int i = 1; i < 7; ++i) f[i * (int64_t)L.stride + j] = (float)((double)fd[i * dstride + d] - I.w1 * sh);
     });
 }
 
@@ -316,7 +308,7 @@ __global__ __launch_bounds__(256) void k_get_pop(Lattice L, const int2 *blk, con
         const double sh = I.sh0 - I.slope * (double)(v % I.nx);
         for (int i = 0; i < 7; ++i) {
             const double w = i == 0 ? I.w0 : I.w1;
-            fd[i * dstride + d] = j < 0 ? 0.f : (float)((double)f[i * L.stride + j] + w * sh);
+            fd[i * dstride + d] = j < 0 ? 0.f : (float)((double)f[i * (int64_t)L.stride + j] + w * sh);
         }
     });
 }
@@ -327,7 +319,7 @@ __global__ __launch_bounds__(256) void k_conc(Lattice L, const int2 *blk, int re
         float out = 0.f;
         if (j >= 0) {
             double cs = 0.0;
-            for (int i = 0; i < 7; ++i) cs += (double)f[i * L.stride + j];
+            for (int i = 0; i < 7; ++i) cs += (double)f[i * (int64_t)L.stride + j];
             const double kn = react ? I.k * n : 0.0;
             out = (float)((cs + (I.sh0 - I.slope * (double)(v % I.nx))) / (1.0 - kn));
         }
@@ -335,30 +327,37 @@ __global__ __launch_bounds__(256) void k_conc(Lattice L, const int2 *blk, int re
     });
 }
 
-template <int W, int SPW>
+template <int W, int SPW, bool SINGLE>
 hipError_t launch_step_t(const Lattice &L, const StepLaunch &S, bool kn, bool re, const float *fin, float *fout,
                          hipStream_t st) {
     const dim3 grid(S.nblk), block(W * 64);
     (void)hipGetLastError();  // drop a stale error (e.g. hipErrorNotReady from an event query)
     if (kn && re) {
-        hipLaunchKernelGGL((k_step<W, SPW, true, true>), grid, block, 0, st, L, S.seg, S.nent, S.nblk, S.xcd, fin, fout);
+        hipLaunchKernelGGL((k_step<W, SPW, true, true, SINGLE>), grid, block, 0, st, L, S, fin, fout);
     } else if (kn) {
-        hipLaunchKernelGGL((k_step<W, SPW, true, false>), grid, block, 0, st, L, S.seg, S.nent, S.nblk, S.xcd, fin, fout);
+        hipLaunchKernelGGL((k_step<W, SPW, true, false, SINGLE>), grid, block, 0, st, L, S, fin, fout);
     } else if (re) {
-        hipLaunchKernelGGL((k_step<W, SPW, false, true>), grid, block, 0, st, L, S.seg, S.nent, S.nblk, S.xcd, fin, fout);
+        hipLaunchKernelGGL((k_step<W, SPW, false, true, SINGLE>), grid, block, 0, st, L, S, fin, fout);
     } else {
-        hipLaunchKernelGGL((k_step<W, SPW, false, false>), grid, block, 0, st, L, S.seg, S.nent, S.nblk, S.xcd, fin, fout);
+        hipLaunchKernelGGL((k_step<W, SPW, false, false, SINGLE>), grid, block, 0, st, L, S, fin, fout);
     }
     return hipGetLastError();
+}
+
+template <int W, int SPW>
+hipError_t launch_step_s(const Lattice &L, const StepLaunch &S, bool kn, bool re, const float *fin, float *fout,
+                         hipStream_t st) {
+    return S.single ? launch_step_t<W, SPW, true>(L, S, kn, re, fin, fout, st)
+                    : launch_step_t<W, SPW, false>(L, S, kn, re, fin, fout, st);
 }
 
 template <int W>
 hipError_t launch_step_w(const Lattice &L, const StepLaunch &S, bool kn, bool re, const float *fin, float *fout,
                          hipStream_t st) {
     switch (S.spw) {
-        case 1: return launch_step_t<W, 1>(L, S, kn, re, fin, fout, st);
-        case 2: return launch_step_t<W, 2>(L, S, kn, re, fin, fout, st);
-        case 4: return launch_step_t<W, 4>(L, S, kn, re, fin, fout, st);
+        case 1: return launch_step_s<W, 1>(L, S, kn, re, fin, fout, st);
+        case 2: return launch_step_s<W, 2>(L, S, kn, re, fin, fout, st);
+        case 4: return launch_step_s<W, 4>(L, S, kn, re, fin, fout, st);
         default: return hipErrorInvalidValue;
     }
 }
