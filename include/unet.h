@@ -1,0 +1,112 @@
+/*
+ * unet.h — C ABI of the learned warm start's kernels (gfx950).
+ *
+ * A 3-D U-Net predicts the steady concentration field of the reactive problem
+ * (Chen et al., arXiv 1410.1914, Sections 3.4-3.5.2, Eqs. 15, 18a, 20a, 20b) from
+ * the structure, and the lattice Boltzmann solver of lbm.h starts from that field
+ * (equilibrium populations, Eq. 23) instead of from C = 0.  The network itself is
+ * not part of the paper's method: it only changes the starting point, and the
+ * converged answer is the solver's.
+ *
+ * Conventions
+ *   - Activations and activation gradients are BF16 in NDHWC order (channel
+ *     fastest): a[((z*ny + y)*nx + x)*ld + off + c].  ld is the channel stride of
+ *     the buffer (a multiple of 8), off the first channel the call reads or writes,
+ *     so two tensors can share one buffer (U-Net skip concatenation).
+ *   - Channel counts of 3x3x3 convolutions are multiples of 16.
+ *   - Weights are BF16 [cout][kpad] with k = tap * cin + ci, tap = (dz+1)*9 +
+ *     (dy+1)*3 + (dx+1), zero beyond 27*cin up to kpad = unet_kpad(cin).  Weight
+ *     gradients, biases, master weights and Adam moments are FP32.
+ *   - Every pointer is device memory; every call enqueues on the given HIP stream
+ *     and returns 0, or -1 on invalid arguments, -6 if the launch failed.
+ *   - Zero padding at the domain boundary for 3x3x3 convolutions.
+ */
+#ifndef PAPER_1410_1914_AMD_UNET_H
+#define PAPER_1410_1914_AMD_UNET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* padded K extent of a 3x3x3 convolution with cin input channels (multiple of 32) */
+int32_t unet_kpad(int32_t cin);
+
+/* y[v, off_y + co] = act(b[co] + sum_k W[co, k] x[v + tap(k), off_x + ci(k)]),
+ * act = ReLU when relu != 0, else identity.  BF16 MFMA (16x16x32) with FP32
+ * accumulation.  Output is BF16; when y32 is not NULL the FP32 result is also
+ * written to y32[v * cout + co]. */
+int unet_conv3d_fwd(const uint16_t *x, int32_t ldx, int32_t offx, const uint16_t *w, const float *b,
+                    uint16_t *y, int32_t ldy, int32_t offy, float *y32, int32_t nz, int32_t ny, int32_t nx,
+                    int32_t cin, int32_t cout, int32_t relu, void *stream);
+
+/* Weights of the backward-data convolution: wt[ci, tap' * cout + co] =
+ * w[co, (26 - tap') * cin + ci]; wt has kpad = unet_kpad(cout).  Running
+ * unet_conv3d_fwd with wt (cin and cout swapped, no bias, no ReLU) on dy gives dx. */
+int unet_conv3d_wtrans(const uint16_t *w, uint16_t *wt, int32_t cin, int32_t cout, void *stream);
+
+/* dw[co, k] += sum_v dy[v, offdy + co] x[v + tap(k), offx + ci(k)] (FP32
+ * accumulation), and, when db is not NULL, db[co] += sum_v dy[v, offdy + co].
+ * dw is [cout][kpad] FP32. */
+int unet_conv3d_wgrad(const uint16_t *x, int32_t ldx, int32_t offx, const uint16_t *dy, int32_t lddy, int32_t offdy,
+                      int32_t nz, int32_t ny, int32_t nx, int32_t cin, int32_t cout, float *dw, float *db,
+                      void *stream);
+
+/* dpre[v, c] = dy[v, c] * (y[v, c] > 0) (ReLU backward, in place allowed) */
+int unet_relu_bwd(const uint16_t *y, int32_t ldy, int32_t offy, uint16_t *dy, int32_t ldd, int32_t offd,
+                  int64_t nvox, int32_t c, void *stream);
+
+/* 2x2x2 average pooling (even sizes): y at (nz/2, ny/2, nx/2); backward adds
+ * dy/8 into the eight children (accumulate into dx). */
+int unet_pool_fwd(const uint16_t *x, int32_t ldx, int32_t offx, uint16_t *y, int32_t ldy, int32_t offy,
+                  int32_t nz, int32_t ny, int32_t nx, int32_t c, void *stream);
+int unet_pool_bwd(const uint16_t *dy, int32_t ldy, int32_t offy, uint16_t *dx, int32_t ldx, int32_t offx,
+                  int32_t nz, int32_t ny, int32_t nx, int32_t c, void *stream);
+
+/* Nearest-neighbour 2x upsampling from (nz/2, ny/2, nx/2) to (nz, ny, nx);
+ * backward sums the eight children (overwrites dx). */
+int unet_up_fwd(const uint16_t *x, int32_t ldx, int32_t offx, uint16_t *y, int32_t ldy, int32_t offy,
+                int32_t nz, int32_t ny, int32_t nx, int32_t c, void *stream);
+int unet_up_bwd(const uint16_t *dy, int32_t ldy, int32_t offy, uint16_t *dx, int32_t ldx, int32_t offx,
+                int32_t nz, int32_t ny, int32_t nx, int32_t c, void *stream);
+
+/* Output head (1x1x1, c -> 1, FP32): out[v] = base[v] + b + sum_c w[c] x[v, c]. */
+int unet_head_fwd(const uint16_t *x, int32_t ldx, const float *w, const float *b, const float *base, float *out,
+                  int64_t nvox, int32_t c, void *stream);
+/* Head backward from dout (FP32): dx[v, c] = dout[v] w[c] (BF16), dw[c] += sum
+ * dout[v] x[v, c], db += sum dout[v]. */
+int unet_head_bwd(const uint16_t *x, int32_t ldx, const float *w, const float *dout, uint16_t *dx, float *dw,
+                  float *db, int64_t nvox, int32_t c, void *stream);
+
+/* Masked mean squared error over voxels with mask != 0: loss[0] += sum/count and
+ * dout[v] = 2 (pred - target) mask / count. */
+int unet_mse(const float *pred, const float *target, const uint8_t *mask, float *dout, float *loss, int64_t nvox,
+             int64_t count, void *stream);
+
+/* Adam step on FP32 master weights p with moments m, v; also writes the BF16
+ * copy pb (may be NULL).  t is the 1-based step number. */
+int unet_adam(float *p, float *m, float *v, const float *g, uint16_t *pb, int64_t n, float lr, float beta1,
+              float beta2, float eps, int32_t t, void *stream);
+
+/* FP32 -> BF16 (round to nearest even) and zero fill helpers. */
+int unet_to_bf16(const float *src, uint16_t *dst, int64_t n, void *stream);
+int unet_zero(void *dst, int64_t bytes, void *stream);
+
+/* Input features of the network (16 channels, BF16) from the solver's dense
+ * fields on the simulated grid: c0 active, c1 log10(omega-derived D / D_ref)/3 on
+ * active voxels, c2 n_cat/6 on active reacting voxels, c3 x/(nx-1), rest 0.
+ * omega is 1/tau as stored by lbm_get_host_fields (uploaded to the device). */
+int unet_features(const uint8_t *active, const uint8_t *n_cat, const float *omega, float tau_ref,
+                  uint16_t *feat, int32_t nz, int32_t ny, int32_t nx, void *stream);
+
+/* Lane-layout self check of the MFMA builtin: a = A (16x32, row major FP32),
+ * b = B (32x16); writes D = A B through the kernels' fragment mapping into d
+ * (16x16).  Used by the tests to pin the mapping on the device. */
+int unet_mfma_selftest(const float *a, const float *b, float *d, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

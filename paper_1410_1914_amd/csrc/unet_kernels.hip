@@ -1,0 +1,532 @@
+// Kernels of the learned warm start's 3-D U-Net (gfx950): BF16 MFMA implicit-GEMM
+// 3x3x3 convolutions with FP32 accumulation, their backward passes, pooling,
+// upsampling, the output head, the masked MSE loss and Adam.  The C ABI is in
+// include/unet.h.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/unet.h"
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((__vector_size__(8 * sizeof(__bf16))));
+typedef float f32x4 __attribute__((__vector_size__(4 * sizeof(float))));
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// round to nearest even (NaN kept quiet)
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__host__ __device__ __forceinline__ int kpad_of(int cin) { return (27 * cin + 31) / 32 * 32; }
+
+int status(hipError_t e) { return e == hipSuccess ? 0 : -6; }
+
+// ------------------------------------------------------------------ conv3d forward
+//
+// Implicit GEMM: rows = voxels, columns = output channels, K = 27 taps x cin.
+// Each wave owns 16 consecutive voxels and a slice of 16 * NT output channels
+// (blockIdx.y picks the slice); per K
+// chunk of 32 it loads one A fragment (8 channels of one voxel at one tap, 16 B)
+// and NT B fragments (8 consecutive k of one output channel, 16 B), then issues
+// NT v_mfma_f32_16x16x32_bf16.  Fragment mapping (pinned by unet_mfma_selftest):
+//   A[m][k]: lane l holds m = l % 16, k = 8 (l / 16) + j;  B[k][n]: n = l % 16, same k;
+//   D[m][n]: lane l holds m = 4 (l / 16) + i, n = l % 16.
+struct ConvArgs {
+    const uint16_t *x;
+    const uint16_t *w;
+    const float *b;
+    uint16_t *y;
+    float *y32;
+    int ldx, offx, ldy, offy;
+    int nz, ny, nx, cin, cout, kpad, relu;
+};
+
+template <int NT>
+__global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int co0 = blockIdx.y * 16 * NT;  // this workgroup's slice of output channels
+    const int64_t nvox = (int64_t)a.nz * a.ny * a.nx;
+    const int64_t vbase = (int64_t)blockIdx.x * 64 + wave * 16;
+    const int m = lane & 15, kb = lane >> 4;
+    const int64_t va = vbase + m;
+    const bool rowok = va < nvox;
+    int x = 0, y = 0, z = 0;
+    if (rowok) {
+        x = (int)(va % a.nx);
+        const int64_t r = va / a.nx;
+        y = (int)(r % a.ny);
+        z = (int)(r / a.ny);
+    }
+    f32x4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    const int nchunk = a.kpad / 32;
+    for (int q = 0; q < nchunk; ++q) {
+        const int k = 32 * q + 8 * kb;
+        const int tap = k / a.cin, ci = k - tap * a.cin;
+        uint4 av = make_uint4(0u, 0u, 0u, 0u);
+        if (rowok && tap < 27) {
+            const int zz = z + tap / 9 - 1, yy = y + (tap / 3) % 3 - 1, xx = x + tap % 3 - 1;
+            if (zz >= 0 && zz < a.nz && yy >= 0 && yy < a.ny && xx >= 0 && xx < a.nx) {
+                const int64_t nb = ((int64_t)zz * a.ny + yy) * a.nx + xx;
+                av = *reinterpret_cast<const uint4 *>(a.x + nb * a.ldx + a.offx + ci);
+            }
+        }
+        const bf16x8 A = __builtin_bit_cast(bf16x8, av);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int co = co0 + 16 * t + m;
+            const uint4 bv = *reinterpret_cast<const uint4 *>(a.w + (int64_t)co * a.kpad + k);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, __builtin_bit_cast(bf16x8, bv), acc[t], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int co = co0 + 16 * t + m;
+        const float bias = a.b ? a.b[co] : 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t vm = vbase + 4 * kb + i;
+            if (vm >= nvox) continue;
+            float v = acc[t][i] + bias;
+            if (a.relu) v = fmaxf(v, 0.f);
+            a.y[vm * a.ldy + a.offy + co] = f2bf(v);
+            if (a.y32) a.y32[vm * a.cout + co] = v;
+        }
+    }
+}
+
+// wt[ci][tap' * cout + co] = w[co][(26 - tap') * cin + ci]
+__global__ void k_wtrans(const uint16_t *w, uint16_t *wt, int cin, int cout, int kpad_in, int kpad_out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)cin * kpad_out) return;
+    const int ci = (int)(i / kpad_out), kk = (int)(i % kpad_out);
+    uint16_t v = 0;
+    if (kk < 27 * cout) {
+        const int tp = kk / cout, co = kk % cout;
+        v = w[(int64_t)co * kpad_in + (26 - tp) * cin + ci];
+    }
+    wt[i] = v;
+}
+
+// ------------------------------------------------------------------ conv3d weight gradient
+//
+// dw[co][k] += sum_v dy[v][co] X(v, k): a GEMM with the voxels as K, tiled 64 (co)
+// x 64 (k) per workgroup over a voxel range, 16 voxels per LDS stage, 4 x 4 FP32
+// outputs per thread; partial sums are added to dw atomically.
+constexpr int kWgVox = 16;
+
+__global__ __launch_bounds__(256) void k_wgrad(const uint16_t *x, int ldx, int offx, const uint16_t *dy, int lddy,
+                                               int offdy, int nz, int ny, int nx, int cin, int cout, int kpad,
+                                               int64_t vper, float *dw, float *db) {
+    __shared__ float As[kWgVox][64];
+    __shared__ float Bs[kWgVox][64];
+    const int tid = threadIdx.x;
+    const int tr = tid >> 4, tc = tid & 15;  // 16 x 16 threads, 4 x 4 outputs each
+    const int k0 = blockIdx.x * 64, co0 = blockIdx.z * 64;
+    const int64_t nvox = (int64_t)nz * ny * nx;
+    const int64_t v0 = (int64_t)blockIdx.y * vper;
+    const int64_t v1 = min(nvox, v0 + vper);
+    float acc[4][4] = {};
+    float bacc = 0.f;
+    const int K = 27 * cin;
+    for (int64_t vs = v0; vs < v1; vs += kWgVox) {
+        for (int e = tid; e < kWgVox * 64; e += 256) {
+            const int vv = e >> 6, cc = e & 63;
+            const int64_t v = vs + vv;
+            const int co = co0 + cc;
+            As[vv][cc] = (v < v1 && co < cout) ? bf2f(dy[v * lddy + offdy + co]) : 0.f;
+            const int k = k0 + cc;
+            float xv = 0.f;
+            if (v < v1 && k < K) {
+                const int tap = k / cin, ci = k - tap * cin;
+                const int xx0 = (int)(v % nx);
+                const int64_t r = v / nx;
+                const int yy0 = (int)(r % ny), zz0 = (int)(r / ny);
+                const int zz = zz0 + tap / 9 - 1, yy = yy0 + (tap / 3) % 3 - 1, xx = xx0 + tap % 3 - 1;
+                if (zz >= 0 && zz < nz && yy >= 0 && yy < ny && xx >= 0 && xx < nx)
+                    xv = bf2f(x[(((int64_t)zz * ny + yy) * nx + xx) * ldx + offx + ci]);
+            }
+            Bs[vv][cc] = xv;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int vv = 0; vv < kWgVox; ++vv) {
+            float a4[4], b4[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                a4[i] = As[vv][tr * 4 + i];
+                b4[i] = Bs[vv][tc * 4 + i];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) acc[i][jj] = fmaf(a4[i], b4[jj], acc[i][jj]);
+        }
+        if (db && blockIdx.x == 0 && tid < 64)
+            for (int vv = 0; vv < kWgVox; ++vv) bacc += As[vv][tid];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int co = co0 + tr * 4 + i;
+        if (co >= cout) continue;
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            const int k = k0 + tc * 4 + jj;
+            if (k < K && acc[i][jj] != 0.f) atomicAdd(&dw[(int64_t)co * kpad + k], acc[i][jj]);
+        }
+    }
+    if (db && blockIdx.x == 0 && tid < 64 && co0 + tid < cout) atomicAdd(&db[co0 + tid], bacc);
+}
+
+// ------------------------------------------------------------------ elementwise layers
+
+__global__ void k_relu_bwd(const uint16_t *y, int ldy, int offy, uint16_t *d, int ldd, int offd, int64_t nvox, int c) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nvox * c) return;
+    const int64_t v = i / c;
+    const int ch = (int)(i % c);
+    if (!(bf2f(y[v * ldy + offy + ch]) > 0.f)) d[v * ldd + offd + ch] = 0;
+}
+
+__global__ void k_pool_fwd(const uint16_t *x, int ldx, int offx, uint16_t *y, int ldy, int offy, int nz, int ny,
+                           int nx, int c) {
+    const int hz = nz / 2, hy = ny / 2, hx = nx / 2;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)hz * hy * hx * c) return;
+    const int ch = (int)(i % c);
+    const int64_t p = i / c;
+    const int X = (int)(p % hx), Y = (int)((p / hx) % hy), Z = (int)(p / ((int64_t)hx * hy));
+    float s = 0.f;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx)
+                s += bf2f(x[(((int64_t)(2 * Z + dz) * ny + 2 * Y + dy) * nx + 2 * X + dx) * ldx + offx + ch]);
+    y[p * ldy + offy + ch] = f2bf(0.125f * s);
+}
+
+__global__ void k_pool_bwd(const uint16_t *dy, int ldy, int offy, uint16_t *dx, int ldx, int offx, int nz, int ny,
+                           int nx, int c) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)nz * ny * nx * c) return;
+    const int ch = (int)(i % c);
+    const int64_t v = i / c;
+    const int x = (int)(v % nx), y = (int)((v / nx) % ny), z = (int)(v / ((int64_t)nx * ny));
+    const int64_t p = ((int64_t)(z / 2) * (ny / 2) + y / 2) * (nx / 2) + x / 2;
+    uint16_t *o = dx + v * ldx + offx + ch;
+    *o = f2bf(bf2f(*o) + 0.125f * bf2f(dy[p * ldy + offy + ch]));
+}
+
+__global__ void k_up_fwd(const uint16_t *x, int ldx, int offx, uint16_t *y, int ldy, int offy, int nz, int ny, int nx,
+                         int c) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)nz * ny * nx * c) return;
+    const int ch = (int)(i % c);
+    const int64_t v = i / c;
+    const int xx = (int)(v % nx), yy = (int)((v / nx) % ny), zz = (int)(v / ((int64_t)nx * ny));
+    const int64_t p = ((int64_t)(zz / 2) * (ny / 2) + yy / 2) * (nx / 2) + xx / 2;
+    y[v * ldy + offy + ch] = x[p * ldx + offx + ch];
+}
+
+__global__ void k_up_bwd(const uint16_t *dy, int ldy, int offy, uint16_t *dx, int ldx, int offx, int nz, int ny,
+                         int nx, int c) {
+    const int hz = nz / 2, hy = ny / 2, hx = nx / 2;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)hz * hy * hx * c) return;
+    const int ch = (int)(i % c);
+    const int64_t p = i / c;
+    const int X = (int)(p % hx), Y = (int)((p / hx) % hy), Z = (int)(p / ((int64_t)hx * hy));
+    float s = 0.f;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dyy = 0; dyy < 2; ++dyy)
+            for (int ddx = 0; ddx < 2; ++ddx)
+                s += bf2f(dy[(((int64_t)(2 * Z + dz) * ny + 2 * Y + dyy) * nx + 2 * X + ddx) * ldy + offy + ch]);
+    dx[p * ldx + offx + ch] = f2bf(s);
+}
+
+__global__ void k_head_fwd(const uint16_t *x, int ldx, const float *w, const float *b, const float *base, float *out,
+                           int64_t nvox, int c) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nvox) return;
+    float s = b[0] + (base ? base[v] : 0.f);
+    for (int ch = 0; ch < c; ++ch) s = fmaf(w[ch], bf2f(x[v * ldx + ch]), s);
+    out[v] = s;
+}
+
+__device__ __forceinline__ float block_sum(float v, float *red) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    float t = 0.f;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += red[i];
+    __syncthreads();
+    return t;
+}
+
+// one workgroup per 256 voxels: dx, and per-channel partials of dw, db added atomically
+__global__ __launch_bounds__(256) void k_head_bwd(const uint16_t *x, int ldx, const float *w, const float *dout,
+                                                  uint16_t *dx, float *dw, float *db, int64_t nvox, int c) {
+    __shared__ float red[4];
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const float g = v < nvox ? dout[v] : 0.f;
+    for (int ch = 0; ch < c; ++ch) {
+        const float xv = v < nvox ? bf2f(x[v * ldx + ch]) : 0.f;
+        if (v < nvox) dx[v * c + ch] = f2bf(g * w[ch]);
+        const float s = block_sum(g * xv, red);
+        if (threadIdx.x == 0) atomicAdd(&dw[ch], s);
+    }
+    const float s = block_sum(g, red);
+    if (threadIdx.x == 0) atomicAdd(db, s);
+}
+
+__global__ __launch_bounds__(256) void k_mse(const float *pred, const float *target, const uint8_t *mask, float *dout,
+                                             float *loss, int64_t nvox, float inv_count) {
+    __shared__ float red[4];
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float e = 0.f;
+    if (v < nvox) {
+        const float d = mask[v] ? pred[v] - target[v] : 0.f;
+        dout[v] = 2.f * d * inv_count;
+        e = d * d * inv_count;
+    }
+    const float s = block_sum(e, red);
+    if (threadIdx.x == 0) atomicAdd(loss, s);
+}
+
+__global__ void k_adam(float *p, float *m, float *v, const float *g, uint16_t *pb, int64_t n, float lr, float b1,
+                       float b2, float eps, float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+    p[i] = pi;
+    if (pb) pb[i] = f2bf(pi);
+}
+
+__global__ void k_to_bf16(const float *s, uint16_t *d, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = f2bf(s[i]);
+}
+
+__global__ void k_zero(uint32_t *d, int64_t nwords) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nwords) d[i] = 0u;
+}
+
+__global__ void k_features(const uint8_t *active, const uint8_t *ncat, const float *omega, float tau_ref,
+                           uint16_t *feat, int nz, int ny, int nx) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= (int64_t)nz * ny * nx) return;
+    const int x = (int)(v % nx);
+    float f[4] = {0.f, 0.f, 0.f, nx > 1 ? (float)x / (float)(nx - 1) : 0.f};
+    if (active[v]) {
+        f[0] = 1.f;
+        const float tau = 1.f / omega[v];
+        const float drel = (tau - 0.5f) / (tau_ref - 0.5f);
+        f[1] = log10f(fmaxf(drel, 1e-9f)) / 3.f;
+        f[2] = (float)ncat[v] / 6.f;
+    }
+    uint16_t *o = feat + v * 16;
+    for (int c = 0; c < 16; ++c) o[c] = c < 4 ? f2bf(f[c]) : (uint16_t)0;
+}
+
+// D = A B (16x32 by 32x16) through the conv kernel's fragment mapping
+__global__ void k_mfma_selftest(const float *a, const float *b, float *d) {
+    const int lane = threadIdx.x;
+    const int m = lane & 15, kb = lane >> 4;
+    uint16_t av[8], bv[8];
+    for (int j = 0; j < 8; ++j) {
+        av[j] = f2bf(a[m * 32 + 8 * kb + j]);
+        bv[j] = f2bf(b[(8 * kb + j) * 16 + m]);
+    }
+    const bf16x8 A = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(av));
+    const bf16x8 B = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(bv));
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, acc, 0, 0, 0);
+    for (int i = 0; i < 4; ++i) d[(4 * kb + i) * 16 + m] = acc[i];
+}
+
+dim3 grid1(int64_t n, int bs = 256) { return dim3((unsigned)((n + bs - 1) / bs)); }
+
+bool ch_ok(int ld, int off, int c) { return ld > 0 && off >= 0 && c > 0 && off + c <= ld; }
+
+}  // namespace
+
+extern "C" {
+
+int32_t unet_kpad(int32_t cin) { return kpad_of(cin); }
+
+int unet_conv3d_fwd(const uint16_t *x, int32_t ldx, int32_t offx, const uint16_t *w, const float *b, uint16_t *y,
+                    int32_t ldy, int32_t offy, float *y32, int32_t nz, int32_t ny, int32_t nx, int32_t cin,
+                    int32_t cout, int32_t relu, void *stream) {
+    if (!x || !w || !y || nz <= 0 || ny <= 0 || nx <= 0 || cin % 16 || !ch_ok(ldx, offx, cin) ||
+        !ch_ok(ldy, offy, cout) || (ldx % 8) || (offx % 8))
+        return -1;
+    if (cout % 16) return -1;
+    const int tiles = cout / 16;
+    const int nt = tiles % 4 == 0 ? 4 : tiles % 3 == 0 ? 3 : tiles % 2 == 0 ? 2 : 1;
+    ConvArgs a{x, w, b, y, y32, ldx, offx, ldy, offy, nz, ny, nx, cin, cout, kpad_of(cin), relu};
+    const int64_t nvox = (int64_t)nz * ny * nx;
+    const dim3 g((unsigned)((nvox + 63) / 64), (unsigned)(tiles / nt)), blk(256);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    (void)hipGetLastError();
+    switch (nt) {
+        case 1: hipLaunchKernelGGL(k_conv_fwd<1>, g, blk, 0, st, a); break;
+        case 2: hipLaunchKernelGGL(k_conv_fwd<2>, g, blk, 0, st, a); break;
+        case 3: hipLaunchKernelGGL(k_conv_fwd<3>, g, blk, 0, st, a); break;
+        default: hipLaunchKernelGGL(k_conv_fwd<4>, g, blk, 0, st, a); break;
+    }
+    return status(hipGetLastError());
+}
+
+int unet_conv3d_wtrans(const uint16_t *w, uint16_t *wt, int32_t cin, int32_t cout, void *stream) {
+    if (!w || !wt || cin <= 0 || cout <= 0) return -1;
+    const int64_t n = (int64_t)cin * kpad_of(cout);
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_wtrans, grid1(n), dim3(256), 0, static_cast<hipStream_t>(stream), w, wt, cin, cout,
+                       kpad_of(cin), kpad_of(cout));
+    return status(hipGetLastError());
+}
+
+int unet_conv3d_wgrad(const uint16_t *x, int32_t ldx, int32_t offx, const uint16_t *dy, int32_t lddy, int32_t offdy,
+                      int32_t nz, int32_t ny, int32_t nx, int32_t cin, int32_t cout, float *dw, float *db,
+                      void *stream) {
+    if (!x || !dy || !dw || nz <= 0 || ny <= 0 || nx <= 0 || !ch_ok(ldx, offx, cin) || !ch_ok(lddy, offdy, cout))
+        return -1;
+    const int64_t nvox = (int64_t)nz * ny * nx;
+    const int64_t vper = 4096;
+    const dim3 g((unsigned)((27 * cin + 63) / 64), (unsigned)((nvox + vper - 1) / vper), (unsigned)((cout + 63) / 64));
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_wgrad, g, dim3(256), 0, static_cast<hipStream_t>(stream), x, ldx, offx, dy, lddy, offdy, nz,
+                       ny, nx, cin, cout, kpad_of(cin), vper, dw, db);
+    return status(hipGetLastError());
+}
+
+int unet_relu_bwd(const uint16_t *y, int32_t ldy, int32_t offy, uint16_t *dy, int32_t ldd, int32_t offd, int64_t nvox,
+                  int32_t c, void *stream) {
+    if (!y || !dy || !ch_ok(ldy, offy, c) || !ch_ok(ldd, offd, c) || nvox <= 0) return -1;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_relu_bwd, grid1(nvox * c), dim3(256), 0, static_cast<hipStream_t>(stream), y, ldy, offy, dy,
+                       ldd, offd, nvox, c);
+    return status(hipGetLastError());
+}
+
+int unet_pool_fwd(const uint16_t *x, int32_t ldx, int32_t offx, uint16_t *y, int32_t ldy, int32_t offy, int32_t nz,
+                  int32_t ny, int32_t nx, int32_t c, void *stream) {
+    if (!x || !y || (nz | ny | nx) & 1 || nz <= 0 || !ch_ok(ldx, offx, c) || !ch_ok(ldy, offy, c)) return -1;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_pool_fwd, grid1((int64_t)nz * ny * nx / 8 * c), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), x, ldx, offx, y, ldy, offy, nz, ny, nx, c);
+    return status(hipGetLastError());
+}
+
+int unet_pool_bwd(const uint16_t *dy, int32_t ldy, int32_t offy, uint16_t *dx, int32_t ldx, int32_t offx, int32_t nz,
+                  int32_t ny, int32_t nx, int32_t c, void *stream) {
+    if (!dy || !dx || (nz | ny | nx) & 1 || nz <= 0 || !ch_ok(ldx, offx, c) || !ch_ok(ldy, offy, c)) return -1;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_pool_bwd, grid1((int64_t)nz * ny * nx * c), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       dy, ldy, offy, dx, ldx, offx, nz, ny, nx, c);
+    return status(hipGetLastError());
+}
+
+int unet_up_fwd(const uint16_t *x, int32_t ldx, int32_t offx, uint16_t *y, int32_t ldy, int32_t offy, int32_t nz,
+                int32_t ny, int32_t nx, int32_t c, void *stream) {
+    if (!x || !y || (nz | ny | nx) & 1 || nz <= 0 || !ch_ok(ldx, offx, c) || !ch_ok(ldy, offy, c)) return -1;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_up_fwd, grid1((int64_t)nz * ny * nx * c), dim3(256), 0, static_cast<hipStream_t>(stream), x,
+                       ldx, offx, y, ldy, offy, nz, ny, nx, c);
+    return status(hipGetLastError());
+}
+
+int unet_up_bwd(const uint16_t *dy, int32_t ldy, int32_t offy, uint16_t *dx, int32_t ldx, int32_t offx, int32_t nz,
+                int32_t ny, int32_t nx, int32_t c, void *stream) {
+    if (!dy || !dx || (nz | ny | nx) & 1 || nz <= 0 || !ch_ok(ldx, offx, c) || !ch_ok(ldy, offy, c)) return -1;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_up_bwd, grid1((int64_t)nz * ny * nx / 8 * c), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), dy, ldy, offy, dx, ldx, offx, nz, ny, nx, c);
+    return status(hipGetLastError());
+}
+
+int unet_head_fwd(const uint16_t *x, int32_t ldx, const float *w, const float *b, const float *base, float *out,
+                  int64_t nvox, int32_t c, void *stream) {
+    if (!x || !w || !b || !out || nvox <= 0 || c <= 0 || ldx < c) return -1;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_head_fwd, grid1(nvox), dim3(256), 0, static_cast<hipStream_t>(stream), x, ldx, w, b, base,
+                       out, nvox, c);
+    return status(hipGetLastError());
+}
+
+int unet_head_bwd(const uint16_t *x, int32_t ldx, const float *w, const float *dout, uint16_t *dx, float *dw,
+                  float *db, int64_t nvox, int32_t c, void *stream) {
+    if (!x || !w || !dout || !dx || !dw || !db || nvox <= 0 || c <= 0 || ldx < c) return -1;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_head_bwd, grid1(nvox), dim3(256), 0, static_cast<hipStream_t>(stream), x, ldx, w, dout, dx,
+                       dw, db, nvox, c);
+    return status(hipGetLastError());
+}
+
+int unet_mse(const float *pred, const float *target, const uint8_t *mask, float *dout, float *loss, int64_t nvox,
+             int64_t count, void *stream) {
+    if (!pred || !target || !mask || !dout || !loss || nvox <= 0 || count <= 0) return -1;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_mse, grid1(nvox), dim3(256), 0, static_cast<hipStream_t>(stream), pred, target, mask, dout,
+                       loss, nvox, 1.0f / (float)count);
+    return status(hipGetLastError());
+}
+
+int unet_adam(float *p, float *m, float *v, const float *g, uint16_t *pb, int64_t n, float lr, float beta1,
+              float beta2, float eps, int32_t t, void *stream) {
+    if (!p || !m || !v || !g || n <= 0 || t < 1) return -1;
+    const float c1 = 1.f / (1.f - powf(beta1, (float)t)), c2 = 1.f / (1.f - powf(beta2, (float)t));
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_adam, grid1(n), dim3(256), 0, static_cast<hipStream_t>(stream), p, m, v, g, pb, n, lr, beta1,
+                       beta2, eps, c1, c2);
+    return status(hipGetLastError());
+}
+
+int unet_to_bf16(const float *src, uint16_t *dst, int64_t n, void *stream) {
+    if (!src || !dst || n <= 0) return -1;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_to_bf16, grid1(n), dim3(256), 0, static_cast<hipStream_t>(stream), src, dst, n);
+    return status(hipGetLastError());
+}
+
+int unet_zero(void *dst, int64_t bytes, void *stream) {
+    if (!dst || bytes < 0 || (bytes & 3)) return -1;
+    if (bytes == 0) return 0;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_zero, grid1(bytes / 4), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       static_cast<uint32_t *>(dst), bytes / 4);
+    return status(hipGetLastError());
+}
+
+int unet_features(const uint8_t *active, const uint8_t *n_cat, const float *omega, float tau_ref, uint16_t *feat,
+                  int32_t nz, int32_t ny, int32_t nx, void *stream) {
+    if (!active || !n_cat || !omega || !feat || nz <= 0 || ny <= 0 || nx <= 0 || !(tau_ref > 0.5f)) return -1;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_features, grid1((int64_t)nz * ny * nx), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       active, n_cat, omega, tau_ref, feat, nz, ny, nx);
+    return status(hipGetLastError());
+}
+
+int unet_mfma_selftest(const float *a, const float *b, float *d, void *stream) {
+    if (!a || !b || !d) return -1;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_mfma_selftest, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream), a, b, d);
+    return status(hipGetLastError());
+}
+
+}  // extern "C"

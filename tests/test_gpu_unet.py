@@ -1,0 +1,279 @@
+"""Warm-start network kernels on the GPU against the FP64 layer oracle.
+
+Inputs are rounded to BF16 before both sides see them, so the oracle computes on
+exactly the values the kernels read; FP32-accumulated outputs then agree to the
+accumulation order (relative 1e-4 here), BF16 outputs to one BF16 rounding."""
+import numpy as np
+import pytest
+
+from oracle import conv as C
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def U():
+    from paper_1410_1914_amd import lbm, unet
+
+    lbm.require_gpu()
+    unet.load()
+    return unet
+
+
+def _bf(rng, *shape, scale=1.0):
+    """Random values exactly representable in BF16 (returned as float64)."""
+    import torch
+
+    x = torch.tensor(rng.standard_normal(shape) * scale, dtype=torch.float32).to(torch.bfloat16)
+    return x.to(torch.float64).numpy()
+
+
+def _dev_bf16(a):
+    import torch
+
+    return torch.tensor(np.asarray(a), dtype=torch.float32).to(torch.bfloat16).cuda()
+
+
+def _dev_f32(a):
+    import torch
+
+    return torch.tensor(np.asarray(a), dtype=torch.float32).cuda()
+
+
+def _host(t):
+    import torch
+
+    torch.cuda.synchronize()
+    return t.to(torch.float64).cpu().numpy()
+
+
+def _wmat(w, cin, kpad):
+    """(cout, 27, cin) -> (cout, kpad) with k = tap * cin + ci, zero padded."""
+    cout = w.shape[0]
+    m = np.zeros((cout, kpad))
+    m[:, :27 * cin] = w.reshape(cout, 27 * cin)
+    return m
+
+
+def test_mfma_lane_layout(U):
+    rng = np.random.default_rng(0)
+    A, B = _bf(rng, 16, 32), _bf(rng, 32, 16)
+    d = _dev_f32(np.zeros((16, 16)))
+    U.unet_mfma_selftest(_dev_f32(A), _dev_f32(B), d)
+    assert np.allclose(_host(d), A @ B, rtol=1e-5, atol=1e-5)
+
+
+CONV = [  # cin, cout, (ldx, offx), (ldy, offy), relu
+    (16, 16, (16, 0), (16, 0), True),
+    (16, 32, (48, 16), (32, 0), False),
+    (48, 192, (48, 0), (192, 0), True),
+    (32, 64, (32, 0), (96, 32), True),
+    (64, 48, (64, 0), (48, 0), False),
+]
+
+
+@pytest.mark.parametrize("cin,cout,xs,ys,relu", CONV)
+def test_conv3d_forward(U, cin, cout, xs, ys, relu):
+    import torch
+
+    rng = np.random.default_rng(cin + cout)
+    shape = (4, 6, 9)  # 216 voxels: four workgroups, the last one ragged
+    ldx, offx = xs
+    ldy, offy = ys
+    xbuf = _bf(rng, *shape, ldx)
+    x = xbuf[..., offx:offx + cin]
+    w = _bf(rng, cout, 27, cin, scale=0.2)
+    b = _bf(rng, cout)
+    kp = U.unet_kpad(cin)
+    y = torch.zeros(shape + (ldy,), dtype=torch.bfloat16, device="cuda")
+    y32 = torch.zeros(shape + (cout,), dtype=torch.float32, device="cuda")
+    U.unet_conv3d_fwd(_dev_bf16(xbuf), ldx, offx, _dev_bf16(_wmat(w, cin, kp)), _dev_f32(b), y, ldy, offy, y32,
+                      shape, cin, cout, relu)
+    ref = C.conv3d(x, w, b, relu=relu)
+    got = _host(y32)
+    assert np.allclose(got, ref, rtol=1e-4, atol=1e-4)
+    yb = _host(y)
+    assert np.allclose(yb[..., offy:offy + cout], ref, rtol=1e-2, atol=1e-2)
+    assert np.all(yb[..., :offy] == 0) and np.all(yb[..., offy + cout:] == 0)
+
+
+@pytest.mark.parametrize("cin,cout", [(16, 16), (48, 16), (32, 64), (192, 64)])
+def test_conv3d_backward_data(U, cin, cout):
+    import torch
+
+    rng = np.random.default_rng(7 + cin)
+    shape = (4, 4, 8)
+    w = _bf(rng, cout, 27, cin, scale=0.2)
+    dy = _bf(rng, *shape, cout)
+    wt = torch.zeros(cin * U.unet_kpad(cout), dtype=torch.bfloat16, device="cuda")
+    U.unet_conv3d_wtrans(_dev_bf16(_wmat(w, cin, U.unet_kpad(cin))), wt, cin, cout)
+    dx = torch.zeros(shape + (cin,), dtype=torch.bfloat16, device="cuda")
+    dx32 = torch.zeros(shape + (cin,), dtype=torch.float32, device="cuda")
+    U.unet_conv3d_fwd(_dev_bf16(dy), cout, 0, wt, None, dx, cin, 0, dx32, shape, cout, cin, False)
+    assert np.allclose(_host(dx32), C.conv3d_dgrad(dy, w), rtol=1e-4, atol=1e-4)
+
+
+@pytest.mark.parametrize("cin,cout,ld,off", [(16, 16, 16, 0), (48, 32, 96, 64), (64, 128, 128, 0)])
+def test_conv3d_weight_gradient(U, cin, cout, ld, off):
+    import torch
+
+    rng = np.random.default_rng(11 + cin)
+    shape = (4, 6, 8)
+    x = _bf(rng, *shape, cin)
+    dybuf = _bf(rng, *shape, ld)
+    dy = dybuf[..., off:off + cout]
+    kp = U.unet_kpad(cin)
+    dw = torch.zeros((cout, kp), dtype=torch.float32, device="cuda")
+    db = torch.zeros(cout, dtype=torch.float32, device="cuda")
+    U.unet_conv3d_wgrad(_dev_bf16(x), cin, 0, _dev_bf16(dybuf), ld, off, shape, cin, cout, dw, db)
+    rdw, rdb = C.conv3d_wgrad(x, dy)
+    got = _host(dw)
+    assert np.allclose(got[:, :27 * cin], rdw.reshape(cout, -1), rtol=1e-4, atol=1e-4)
+    assert np.all(got[:, 27 * cin:] == 0)
+    assert np.allclose(_host(db), rdb, rtol=1e-4, atol=1e-4)
+
+
+def test_pool_up_relu(U):
+    import torch
+
+    rng = np.random.default_rng(5)
+    shape, c = (4, 6, 8), 16
+    x = _bf(rng, *shape, 32)
+    y = torch.zeros((2, 3, 4, 16), dtype=torch.bfloat16, device="cuda")
+    U.unet_pool_fwd(_dev_bf16(x), 32, 16, y, 16, 0, shape, c)
+    assert np.allclose(_host(y), C.pool(x[..., 16:]), rtol=8e-3, atol=1e-3)
+    # backward accumulates
+    dy = _bf(rng, 2, 3, 4, c)
+    base = _bf(rng, *shape, c)
+    dx = _dev_bf16(base)
+    U.unet_pool_bwd(_dev_bf16(dy), c, 0, dx, c, 0, shape, c)
+    assert np.allclose(_host(dx), base + C.pool_bwd(dy), rtol=8e-3, atol=1e-2)
+    xs = _bf(rng, 2, 3, 4, c)
+    yu = torch.zeros(shape + (48,), dtype=torch.bfloat16, device="cuda")
+    U.unet_up_fwd(_dev_bf16(xs), c, 0, yu, 48, 16, shape, c)
+    assert np.array_equal(_host(yu)[..., 16:32], C.up(xs))
+    dyu = _bf(rng, *shape, 48)
+    dxs = torch.zeros((2, 3, 4, c), dtype=torch.bfloat16, device="cuda")
+    U.unet_up_bwd(_dev_bf16(dyu), 48, 32, dxs, c, 0, shape, c)
+    assert np.allclose(_host(dxs), C.up_bwd(dyu[..., 32:]), rtol=8e-3, atol=1e-2)
+    # ReLU backward zeroes the gradient where the output is not positive
+    yv = _bf(rng, 10, c)
+    d = _bf(rng, 10, c)
+    dd = _dev_bf16(d)
+    U.unet_relu_bwd(_dev_bf16(yv), c, 0, dd, c, 0, 10, c)
+    assert np.array_equal(_host(dd), np.where(yv > 0, d, 0.0))
+
+
+def test_head_mse_adam(U):
+    import torch
+
+    rng = np.random.default_rng(9)
+    nvox, c = 500, 16
+    x = _bf(rng, nvox, c)
+    w, b = rng.standard_normal(c), rng.standard_normal(1)
+    base = rng.standard_normal(nvox)
+    out = torch.zeros(nvox, dtype=torch.float32, device="cuda")
+    U.unet_head_fwd(_dev_bf16(x), c, _dev_f32(w), _dev_f32(b), _dev_f32(base), out, nvox, c)
+    ref = x @ w + b[0] + base
+    assert np.allclose(_host(out), ref, rtol=1e-5, atol=1e-4)
+    dout = rng.standard_normal(nvox)
+    dx = torch.zeros((nvox, c), dtype=torch.bfloat16, device="cuda")
+    dw = torch.zeros(c, dtype=torch.float32, device="cuda")
+    db = torch.zeros(1, dtype=torch.float32, device="cuda")
+    U.unet_head_bwd(_dev_bf16(x), c, _dev_f32(w), _dev_f32(dout), dx, dw, db, nvox, c)
+    douf = dout.astype(np.float32).astype(np.float64)
+    assert np.allclose(_host(dw), x.T @ douf, rtol=1e-4, atol=1e-4)
+    assert _host(db)[0] == pytest.approx(douf.sum(), rel=1e-4, abs=1e-4)
+    assert np.allclose(_host(dx), np.outer(douf, w), rtol=1e-2, atol=1e-2)
+    # masked MSE
+    pred, tgt = rng.standard_normal(nvox), rng.standard_normal(nvox)
+    mask = (rng.random(nvox) < 0.7).astype(np.uint8)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    g = torch.zeros(nvox, dtype=torch.float32, device="cuda")
+    U.unet_mse(_dev_f32(pred), _dev_f32(tgt), torch.tensor(mask).cuda(), g, loss, nvox, int(mask.sum()))
+    rl, rg = C.mse(pred, tgt, mask)
+    assert _host(loss)[0] == pytest.approx(rl, rel=1e-5)
+    assert np.allclose(_host(g), rg, rtol=1e-5, atol=1e-7)
+    # Adam: two steps against the oracle
+    n = 1000
+    p0, g1, g2 = rng.standard_normal(n), rng.standard_normal(n), rng.standard_normal(n)
+    p, m, v = _dev_f32(p0), _dev_f32(np.zeros(n)), _dev_f32(np.zeros(n))
+    pb = torch.zeros(n, dtype=torch.bfloat16, device="cuda")
+    rp, rm, rv = p0, np.zeros(n), np.zeros(n)
+    for t, gg in ((1, g1), (2, g2)):
+        U.unet_adam(p, m, v, _dev_f32(gg), pb, n, 1e-2, 0.9, 0.999, 1e-8, t)
+        rp, rm, rv = C.adam(rp, rm, rv, gg.astype(np.float32).astype(np.float64), t, 1e-2)
+    assert np.allclose(_host(p), rp, rtol=1e-5, atol=1e-6)
+    assert np.allclose(_host(pb), rp, rtol=1e-2, atol=1e-2)
+
+
+def test_features(U):
+    import torch
+
+    rng = np.random.default_rng(3)
+    shape = (3, 4, 10)
+    act = (rng.random(shape) < 0.6).astype(np.uint8)
+    ncat = rng.integers(0, 7, shape).astype(np.uint8)
+    tau = 0.5 + rng.random(shape) * 0.5 + 1e-3
+    om = np.where(act, 1 / tau, 0).astype(np.float32)
+    feat = torch.zeros(shape + (16,), dtype=torch.bfloat16, device="cuda")
+    U.unet_features(torch.tensor(act).cuda(), torch.tensor(ncat).cuda(), _dev_f32(om), 1.0, feat, shape)
+    f = _host(feat)
+    t32 = 1.0 / om.astype(np.float64)
+    want1 = np.where(act, np.log10(np.maximum((t32 - 0.5) / 0.5, 1e-9)) / 3, 0)
+    assert np.array_equal(f[..., 0], act.astype(float))
+    assert np.allclose(f[..., 1], want1, atol=1e-2)
+    assert np.allclose(f[..., 2], np.where(act, ncat / 6, 0), atol=1e-2)
+    assert np.allclose(f[..., 3], np.broadcast_to(np.arange(10) / 9, shape), atol=1e-2)
+    assert np.all(f[..., 4:] == 0)
+
+
+def test_network_gradient_matches_finite_differences(U):
+    """The whole backward pass of the BF16 network against FP64 finite differences
+    of the oracle network along two directions per layer checked."""
+    import torch
+
+    rng = np.random.default_rng(1)
+    shape = (8, 8, 8)
+    net = U.UNet(seed=3)
+    feat = _bf(rng, *shape, 16)
+    feat[..., 4:] = 0
+    target = rng.standard_normal(shape) * 0.1
+    mask = (rng.random(shape) < 0.7).astype(np.uint8)
+    count = int(mask.sum())
+    fd_t = _dev_bf16(feat.reshape(-1, 16))
+    b = net._alloc(shape, True)
+    pred = net.forward(fd_t, shape, train=True)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    U.unet_mse(pred, _dev_f32(target.ravel()), torch.tensor(mask.ravel()).cuda(), b["g_out"], loss, pred.numel(), count)
+    net.backward(fd_t, b["g_out"])
+    torch.cuda.synchronize()
+
+    def params():
+        P = {}
+        for name, cin, cout in net.specs:
+            wb = net.Wb[name].to(torch.float64).cpu().numpy()[:, :27 * cin].reshape(cout, 27, cin)
+            P[name] = (wb, net.B[name].cpu().numpy().astype(np.float64))
+        P["head"] = (net.W["head"].cpu().numpy().astype(np.float64), float(net.B["head"].cpu().numpy()[0]))
+        return P
+
+    P = params()
+    ref_pred = C.unet_forward(P, feat)
+    assert np.allclose(_host(pred).reshape(shape), ref_pred, rtol=5e-2, atol=5e-2 * np.abs(ref_pred).max())
+
+    def L(Pp):
+        return C.mse(C.unet_forward(Pp, feat), target, mask)[0]
+
+    for name in ("e1a", "e2b", "b4b", "d3a", "d1b"):
+        cin = dict((n, c) for n, c, _ in net.specs)[name]
+        g = net.gW[name].cpu().numpy().astype(np.float64)[:, :27 * cin].reshape(P[name][0].shape)
+        for d in (g / np.linalg.norm(g), rng.standard_normal(g.shape)):
+            d = d / np.linalg.norm(d)
+            eps = 1e-3
+            Pp = dict(P)
+            Pm = dict(P)
+            Pp[name] = (P[name][0] + eps * d, P[name][1])
+            Pm[name] = (P[name][0] - eps * d, P[name][1])
+            fd = (L(Pp) - L(Pm)) / (2 * eps)
+            an = float(np.sum(g * d))
+            assert an == pytest.approx(fd, rel=0.15, abs=0.05 * np.linalg.norm(g)), (name, an, fd)
