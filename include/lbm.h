@@ -241,6 +241,11 @@ int lbm_batch_run(lbm_batch *b, lbm_run_info *infos);
 int lbm_batch_deff(const lbm_batch *b, int32_t i, double *deff_over_d0);
 int lbm_batch_reaction_rate(const lbm_batch *b, int32_t i, double *rate_per_area, double *j_in);
 int lbm_batch_get_info(const lbm_batch *b, int32_t i, lbm_info *info);
+/* Instance i's dense FP32 concentration on its own simulated grid (device) and
+ * its preprocessed host fields (as lbm_get_host_fields). */
+int lbm_batch_concentration(const lbm_batch *b, int32_t i, float *c_dev);
+int lbm_batch_get_host_fields(const lbm_batch *b, int32_t i, uint8_t *active_host, uint8_t *n_cat_host,
+                              float *omega_host);
 void lbm_batch_destroy(lbm_batch *b);
 
 #ifdef __cplusplus

@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <thread>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -59,6 +61,8 @@ struct Engine {
 
     // workspace
     size_t ws_need = 0;
+    size_t off_zbase = 0;  // per-instance zeros: dense output on one instance's own grid
+    std::vector<int> cb_start, cb_count;  // conversion blocks of each instance
     size_t off_f0 = 0, off_f1 = 0, off_om = 0, off_snap = 0, off_rec = 0, off_inst = 0, off_dbase = 0, off_sblk = 0,
            off_cblk = 0, off_mblk = 0, off_rng = 0, off_part = 0, off_res = 0;
     int64_t cap_sblk = 0, cap_cblk = 0, cap_mblk = 0;
@@ -126,6 +130,7 @@ struct Engine {
         off_rec = take(sizeof(SegRec) * nseg_total);
         off_inst = take(sizeof(InstDev) * ninst);
         off_dbase = take(sizeof(int64_t) * ninst);
+        off_zbase = take(sizeof(int64_t) * ninst);
         off_sblk = take(sizeof(uint32_t) * cap_sblk);
         off_cblk = take(sizeof(int2) * cap_cblk);
         off_mblk = take(sizeof(int4) * cap_mblk);
@@ -256,6 +261,8 @@ struct Engine {
         L.inst = at<InstDev>(off_inst);
         L.stride = (uint32_t)stride;
         // metadata (host staging, then one synchronisation)
+        cb_start.clear();
+        cb_count.clear();
         std::vector<SegRec> rec(nseg_total);
         std::vector<float> om(knudsen ? nf_total : 0);
         std::vector<InstDev> id(ninst);
@@ -265,9 +272,12 @@ struct Engine {
             const Prepared &p = P[i];
             if (knudsen) std::copy(p.omega_c.begin(), p.omega_c.end(), om.begin() + fluid_base[i]);
             id[i] = inst_dev(i);
+            cb_start.push_back((int)cb.size());
             for (int64_t b = 0; b < (p.nseg + 3) / 4; ++b) cb.push_back(make_int2(i, (int)(b * 4)));
+            cb_count.push_back((int)cb.size() - cb_start.back());
         }
         conv_nblk = (int)cb.size();
+        const std::vector<int64_t> zeros(ninst, 0);
         auto up = [&](size_t off, const void *src, size_t n) {
             return note(n ? hipMemcpyAsync(ws + off, src, n, hipMemcpyHostToDevice, st) : hipSuccess, "upload");
         };
@@ -275,6 +285,7 @@ struct Engine {
         if (knudsen && (e = up(off_om, om.data(), 4 * om.size())) != hipSuccess) return e;
         if ((e = up(off_inst, id.data(), sizeof(InstDev) * id.size())) != hipSuccess) return e;
         if ((e = up(off_dbase, dense_base.data(), 8 * dense_base.size())) != hipSuccess) return e;
+        if ((e = up(off_zbase, zeros.data(), 8 * zeros.size())) != hipSuccess) return e;
         if ((e = up(off_cblk, cb.data(), sizeof(int2) * cb.size())) != hipSuccess) return e;
         if ((e = note(hipStreamSynchronize(st), "bind sync")) != hipSuccess) return e;
         bound = true;
@@ -590,10 +601,21 @@ int make_engine(int n, const lbm_grid *grids, const uint8_t *const *phases, cons
     auto E = std::make_unique<Engine>();
     E->ninst = n;
     E->P.resize(n);
-    for (int i = 0; i < n; ++i) {
+    for (int i = 0; i < n; ++i)
         if (!phases[i]) return LBM_ERR_INVALID_ARG;
-        const int st = prepare(grids[i], phases[i], params[i], E->P[i]);
-        if (st != LBM_OK) return st;
+    // instances are independent: preprocess them on parallel host threads
+    std::vector<int> st(n, LBM_OK);
+    const int nth = std::max(1, std::min<int>(n, (int)std::thread::hardware_concurrency()));
+    std::atomic<int> next{0};
+    auto work = [&]() {
+        for (int i = next++; i < n; i = next++) st[i] = prepare(grids[i], phases[i], params[i], E->P[i]);
+    };
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nth; ++t) pool.emplace_back(work);
+    work();
+    for (auto &t : pool) t.join();
+    for (int i = 0; i < n; ++i) {
+        if (st[i] != LBM_OK) return st[i];
         if (i > 0 && (params[i].mode != params[0].mode || E->P[i].knudsen != E->P[0].knudsen))
             return LBM_ERR_INVALID_ARG;
     }
@@ -980,6 +1002,26 @@ int lbm_batch_get_info(const lbm_batch *b, int32_t i, lbm_info *info) {
     if (!b || !info || i < 0 || i >= b->E->ninst) return LBM_ERR_INVALID_ARG;
     std::memset(info, 0, sizeof(*info));
     b->E->info_of(i, *info);
+    return LBM_OK;
+}
+
+int lbm_batch_concentration(const lbm_batch *b, int32_t i, float *c_dev) {
+    if (!b || !c_dev || i < 0 || i >= b->E->ninst) return LBM_ERR_INVALID_ARG;
+    const cl::Engine &E = *b->E;
+    if (!E.bound) return LBM_ERR_UNBOUND;
+    cl::DeviceGuard dg(E.device);
+    hipError_t e = cl::launch_conc(E.L, E.cb_count[i], E.at<int2>(E.off_cblk) + E.cb_start[i], E.react, E.f[E.cur],
+                                   E.at<int64_t>(E.off_zbase), c_dev, E.st);
+    if (e == hipSuccess) e = hipStreamSynchronize(E.st);
+    return cl::hip_status(e);
+}
+
+int lbm_batch_get_host_fields(const lbm_batch *b, int32_t i, uint8_t *active, uint8_t *n_cat, float *omega) {
+    if (!b || i < 0 || i >= b->E->ninst) return LBM_ERR_INVALID_ARG;
+    const cl::Prepared &p = b->E->P[i];
+    if (active) std::copy(p.active.begin(), p.active.end(), active);
+    if (n_cat) std::copy(p.n_cat.begin(), p.n_cat.end(), n_cat);
+    if (omega) std::copy(p.omega_dense.begin(), p.omega_dense.end(), omega);
     return LBM_OK;
 }
 

@@ -107,6 +107,9 @@ SIGNATURES = {
     "lbm_batch_deff": ([_P, c_int32, ctypes.POINTER(c_double)], c_int32),
     "lbm_batch_reaction_rate": ([_P, c_int32, ctypes.POINTER(c_double), ctypes.POINTER(c_double)], c_int32),
     "lbm_batch_get_info": ([_P, c_int32, ctypes.POINTER(lbm_info)], c_int32),
+    "lbm_batch_concentration": ([_P, c_int32, _P], c_int32),
+    "lbm_batch_get_host_fields": ([_P, c_int32, ctypes.POINTER(c_uint8), ctypes.POINTER(c_uint8),
+                                   ctypes.POINTER(c_float)], c_int32),
     "lbm_batch_destroy": ([_P], None),
 }
 
@@ -349,6 +352,22 @@ def lbm_batch_get_info(h, i: int) -> lbm_info:
     return o
 
 
+def lbm_batch_concentration(h, i: int, c_ptr):
+    return _check("lbm_batch_concentration", load().lbm_batch_concentration(h, i, c_ptr))
+
+
+def lbm_batch_get_host_fields(h, i: int):
+    inf = lbm_batch_get_info(h, i)
+    shape = (inf.nz, inf.ny, inf.nx)
+    act = np.zeros(shape, np.uint8)
+    ncat = np.zeros(shape, np.uint8)
+    om = np.zeros(shape, np.float32)
+    _check("lbm_batch_get_host_fields", load().lbm_batch_get_host_fields(
+        h, i, act.ctypes.data_as(ctypes.POINTER(c_uint8)), ncat.ctypes.data_as(ctypes.POINTER(c_uint8)),
+        om.ctypes.data_as(ctypes.POINTER(c_float))))
+    return act, ncat, om
+
+
 def lbm_batch_destroy(h):
     if h:
         load().lbm_batch_destroy(h)
@@ -512,6 +531,18 @@ class Batch:
 
     def info(self, i):
         return lbm_batch_get_info(self.h, i)
+
+    def concentration(self, i):
+        import torch
+
+        inf = self.info(i)
+        out = torch.empty((inf.nz, inf.ny, inf.nx), dtype=torch.float32, device=self.device)
+        torch.cuda.current_stream(self.device).synchronize()
+        lbm_batch_concentration(self.h, i, out.data_ptr())
+        return out
+
+    def host_fields(self, i):
+        return lbm_batch_get_host_fields(self.h, i)
 
     def __del__(self):
         try:
