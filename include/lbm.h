@@ -144,6 +144,15 @@ int lbm_get_info(const lbm_solver *s, lbm_info *info);
  * simulated voxels (FP32 as used on the device), 0 elsewhere. */
 int lbm_get_host_fields(const lbm_solver *s, uint8_t *active_host, uint8_t *n_cat_host, float *omega_host);
 
+/* Structure descriptor used by the learned warm start (not part of the paper's
+ * method): for every voxel of the simulated grid (N bytes, host), the number of
+ * 6-neighbour steps through simulated voxels (periodic in y and z) from the pore
+ * voxels joined to a Dirichlet face through pore voxels alone.  0 on those pores,
+ * 1..254 beyond them (ionomer films, pore pockets reached only through ionomer),
+ * 255 for voxels that are not simulated, farther than 254 steps or unreached.
+ * Computed on the host on each call (O(N)). */
+int lbm_get_pore_depth(const lbm_solver *s, uint8_t *depth_host);
+
 /* Device bytes the solver needs (distributions, metadata, reduction scratch). */
 int lbm_workspace_bytes(const lbm_solver *s, size_t *bytes);
 
@@ -244,6 +253,8 @@ int lbm_batch_get_info(const lbm_batch *b, int32_t i, lbm_info *info);
 /* Instance i's dense FP32 concentration on its own simulated grid (device) and
  * its preprocessed host fields (as lbm_get_host_fields). */
 int lbm_batch_concentration(const lbm_batch *b, int32_t i, float *c_dev);
+/* Instance i's pore-depth map (as lbm_get_pore_depth). */
+int lbm_batch_get_pore_depth(const lbm_batch *b, int32_t i, uint8_t *depth_host);
 int lbm_batch_get_host_fields(const lbm_batch *b, int32_t i, uint8_t *active_host, uint8_t *n_cat_host,
                               float *omega_host);
 void lbm_batch_destroy(lbm_batch *b);

@@ -80,10 +80,11 @@ int unet_head_fwd(const uint16_t *x, int32_t ldx, const float *w, const float *b
 int unet_head_bwd(const uint16_t *x, int32_t ldx, const float *w, const float *dout, uint16_t *dx, float *dw,
                   float *db, int64_t nvox, int32_t c, void *stream);
 
-/* Masked mean squared error over voxels with mask != 0: loss[0] += sum/count and
- * dout[v] = 2 (pred - target) mask / count. */
-int unet_mse(const float *pred, const float *target, const uint8_t *mask, float *dout, float *loss, int64_t nvox,
-             int64_t count, void *stream);
+/* Weighted masked mean squared error over voxels with mask != 0:
+ * loss[0] += sum_v w[v] (pred - target)^2 / count and dout[v] = 2 w[v] (pred - target) / count,
+ * with w = weight[v], or 1 when weight is NULL. */
+int unet_mse(const float *pred, const float *target, const uint8_t *mask, const float *weight, float *dout,
+             float *loss, int64_t nvox, int64_t count, void *stream);
 
 /* Adam step on FP32 master weights p with moments m, v; also writes the BF16
  * copy pb (may be NULL).  t is the 1-based step number. */
@@ -95,11 +96,31 @@ int unet_to_bf16(const float *src, uint16_t *dst, int64_t n, void *stream);
 int unet_zero(void *dst, int64_t bytes, void *stream);
 
 /* Input features of the network (16 channels, BF16) from the solver's dense
- * fields on the simulated grid: c0 active, c1 log10(omega-derived D / D_ref)/3 on
- * active voxels, c2 n_cat/6 on active reacting voxels, c3 x/(nx-1), rest 0.
- * omega is 1/tau as stored by lbm_get_host_fields (uploaded to the device). */
+ * fields on the simulated grid: c0 active, c1 log10(D / D_ref)/3 on active voxels
+ * (D / D_ref = (tau - 1/2) / (tau_ref - 1/2), Eq. 24), c2 n_cat/6, c3 exp(-x/24),
+ * c4 exp(-x/96), c5 exp(-(nx-1-x)/24) (distances from the inlet and outlet faces in
+ * voxels), rest 0.  omega is 1/tau as stored by lbm_get_host_fields (uploaded to the
+ * device).  When weight is not NULL it receives the training weight of each voxel:
+ * min(weight_cap, (D_ref / D)^weight_power) on active voxels, 0 elsewhere (slowly
+ * relaxing, low-diffusivity voxels weigh more; weight_cap >= 1, 0 <= weight_power <= 4). */
 int unet_features(const uint8_t *active, const uint8_t *n_cat, const float *omega, float tau_ref,
-                  uint16_t *feat, int32_t nz, int32_t ny, int32_t nx, void *stream);
+                  uint16_t *feat, float *weight, float weight_power, float weight_cap, int32_t nz, int32_t ny,
+                  int32_t nx, void *stream);
+
+/* Log-space training target and its inverse (elementwise, in place allowed):
+ * inverse == 0: dst = ln(max(src, 0) + eps); inverse != 0: dst = min(cmax, max(0,
+ * exp(src) - eps)).  Training on ln(C + eps) makes the network's error relative to
+ * C, which is what decides whether a start beats C = 0 in voxels where C is small.
+ * eps > 0, cmax > 0. */
+int unet_log_map(const float *src, float *dst, int64_t n, float eps, int32_t inverse, float cmax, void *stream);
+
+/* Start field of the solver from a log-space prediction y (FP32, n voxels):
+ * c[v] = min(cmax, max(0, exp(y[v]) - eps)) where depth[v] <= depth_max, else 0
+ * (the cold-start value).  depth is the pore-depth map of lbm_get_pore_depth,
+ * uploaded to the device.  Voxels deep in ionomer relax slowly and hold small
+ * concentrations, so C = 0 is the better start there. */
+int unet_start_field(const float *y, const uint8_t *depth, int32_t depth_max, float eps, float cmax, float *c,
+                     int64_t n, void *stream);
 
 /* Lane-layout self check of the MFMA builtin: a = A (16x32, row major FP32),
  * b = B (32x16); writes D = A B through the kernels' fragment mapping into d

@@ -6,7 +6,7 @@ weights are (cout, 27, cin) with tap = (dz+1)*9 + (dy+1)*3 + (dx+1).
 
 Each function is the textbook definition: a 3x3x3 convolution with zero padding,
 its adjoints with respect to the input and to the weights, 2x2x2 average pooling,
-nearest-neighbour upsampling, a 1x1x1 head, a masked mean squared error and one
+nearest-neighbour upsampling, a 1x1x1 head, a weighted masked mean squared error and one
 Adam step (Kingma and Ba, 2015).  ``np.einsum`` serves as the contraction.
 """
 from __future__ import annotations
@@ -76,11 +76,13 @@ def head(x, w, b, base=None):
     return out + base if base is not None else out
 
 
-def mse(pred, target, mask):
+def mse(pred, target, mask, weight=None):
+    """sum over masked voxels of w (pred - target)^2, divided by the masked count."""
     m = mask.astype(bool)
     d = np.where(m, pred - target, 0.0)
+    w = np.ones_like(d) if weight is None else np.asarray(weight, np.float64)
     n = m.sum()
-    return float((d * d).sum() / n), 2.0 * d / n
+    return float((w * d * d).sum() / n), 2.0 * w * d / n
 
 
 def adam(p, m, v, g, t, lr, b1=0.9, b2=0.999, eps=1e-8):

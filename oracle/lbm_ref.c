@@ -249,6 +249,9 @@ static int64_t wrap_period(int ny, int nz, int dy, int dz) {
 void orc_chords(int nx, int ny, int nz, const uint8_t *pore, double *dp) {
     const int64_t N = (int64_t)nx * ny * nz;
     for (int64_t v = 0; v < N; ++v) dp[v] = 0.0;
+    /* voxels are independent: rows are shared out over threads, each voxel's sum is
+       formed in the same order as in a serial loop */
+#pragma omp parallel for collapse(2) schedule(dynamic, 4)
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {

@@ -527,7 +527,13 @@ struct Engine {
                 live = keep;
                 if (upload_tables() != hipSuccess) return LBM_ERR_HIP;
             }
-            if (!live.empty() && all_slow && (int64_t)K * reps * 2 <= kMaxWindow) reps *= 2;
+            // longer windows while every live instance is slow, but never longer than
+            // an eighth of the steps taken so far, so a stop found at the end of a
+            // window overshoots the first passing check by at most that fraction
+            int64_t taken = std::numeric_limits<int64_t>::max();
+            for (int i : live) taken = std::min(taken, rs[i].info.steps);
+            if (!live.empty() && all_slow && (int64_t)K * reps * 2 <= kMaxWindow && (int64_t)K * reps * 16 <= taken)
+                reps *= 2;
         }
         int worst = LBM_OK;
         for (int i = 0; i < ninst; ++i) {
@@ -708,6 +714,14 @@ int lbm_get_host_fields(const lbm_solver *s, uint8_t *active, uint8_t *n_cat, fl
     if (n_cat) std::copy(p.n_cat.begin(), p.n_cat.end(), n_cat);
     if (omega) std::copy(p.omega_dense.begin(), p.omega_dense.end(), omega);
     return LBM_OK;
+}
+
+int lbm_get_pore_depth(const lbm_solver *s, uint8_t *depth) {
+    LBM_GUARD_BEGIN
+    if (!s || !depth) return LBM_ERR_INVALID_ARG;
+    cl::pore_depth(s->E->P[0], depth);
+    return LBM_OK;
+    LBM_GUARD_END
 }
 
 int lbm_workspace_bytes(const lbm_solver *s, size_t *bytes) {
@@ -1023,6 +1037,14 @@ int lbm_batch_get_host_fields(const lbm_batch *b, int32_t i, uint8_t *active, ui
     if (n_cat) std::copy(p.n_cat.begin(), p.n_cat.end(), n_cat);
     if (omega) std::copy(p.omega_dense.begin(), p.omega_dense.end(), omega);
     return LBM_OK;
+}
+
+int lbm_batch_get_pore_depth(const lbm_batch *b, int32_t i, uint8_t *depth) {
+    LBM_GUARD_BEGIN
+    if (!b || !depth || i < 0 || i >= b->E->ninst) return LBM_ERR_INVALID_ARG;
+    cl::pore_depth(b->E->P[i], depth);
+    return LBM_OK;
+    LBM_GUARD_END
 }
 
 void lbm_batch_destroy(lbm_batch *b) { delete b; }

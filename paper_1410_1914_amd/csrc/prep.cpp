@@ -151,6 +151,8 @@ int prepare(const lbm_grid &g, const uint8_t *phase, const lbm_params &p, Prepar
             std::copy(src, src + g.nx, dst + res);
         }
 
+    o.phase = ph;
+
     // transport phases: pore + ionomer carry O2 (Eq. 15); ionomer alone carries protons
     std::vector<uint8_t> transport(N);
     for (int64_t v = 0; v < N; ++v)
@@ -299,6 +301,53 @@ int prepare(const lbm_grid &g, const uint8_t *phase, const lbm_params &p, Prepar
         o.sh0 = p.c_in - 0.5 * o.slope;
     }
     return LBM_OK;
+}
+
+void pore_depth(const Prepared &p, uint8_t *depth) {
+    const int nx = p.nx, ny = p.ny, nz = p.nz;
+    const int64_t N = (int64_t)nx * ny * nz;
+    const bool react = p.mode == LBM_MODE_REACT;
+    // pores joined to a Dirichlet face through pores
+    std::vector<uint8_t> pore(N), seed(N, 0), joined;
+    for (int64_t v = 0; v < N; ++v) pore[v] = p.active[v] && p.phase[v] == LBM_PORE;
+    for (int64_t r = 0; r < (int64_t)ny * nz; ++r) {
+        seed[r * nx] = 1;
+        if (!react) seed[r * nx + nx - 1] = 1;
+    }
+    flood(nx, ny, nz, pore, seed, joined);
+    // breadth-first distance from them through the active voxels
+    std::fill(depth, depth + N, (uint8_t)255);
+    std::vector<int64_t> cur, next;
+    for (int64_t v = 0; v < N; ++v)
+        if (joined[v]) {
+            depth[v] = 0;
+            cur.push_back(v);
+        }
+    const int64_t plane = (int64_t)nx * ny;
+    for (int d = 1; d <= 254 && !cur.empty(); ++d) {
+        next.clear();
+        for (const int64_t v : cur) {
+            const int x = (int)(v % nx);
+            const int y = (int)((v / nx) % ny);
+            const int z = (int)(v / plane);
+            int64_t nb[6];
+            int k = 0;
+            if (x > 0) nb[k++] = v - 1;
+            if (x + 1 < nx) nb[k++] = v + 1;
+            nb[k++] = ((int64_t)z * ny + wrap(y - 1, ny)) * nx + x;
+            nb[k++] = ((int64_t)z * ny + wrap(y + 1, ny)) * nx + x;
+            nb[k++] = ((int64_t)wrap(z - 1, nz) * ny + y) * nx + x;
+            nb[k++] = ((int64_t)wrap(z + 1, nz) * ny + y) * nx + x;
+            for (int i = 0; i < k; ++i) {
+                const int64_t t = nb[i];
+                if (p.active[t] && depth[t] == 255) {
+                    depth[t] = (uint8_t)d;
+                    next.push_back(t);
+                }
+            }
+        }
+        cur.swap(next);
+    }
 }
 
 }  // namespace cl

@@ -26,6 +26,7 @@ struct Prepared {
     double w0 = 0.25, w1 = 0.125;
     float om_pore = 1.f, om_ion = 1.f;  // relaxation rates when not per voxel
     // dense over the simulated grid
+    std::vector<uint8_t> phase;  // phase ids, the reservoir plane included
     std::vector<uint8_t> active, n_cat;
     std::vector<float> omega_dense;
     // per segment
@@ -37,6 +38,12 @@ struct Prepared {
 
 // Returns an LBM_* status.
 int prepare(const lbm_grid &g, const uint8_t *phase, const lbm_params &p, Prepared &out);
+
+// Distance (6-neighbour steps through active voxels, periodic in y and z) of every
+// simulated voxel from the pore voxels joined to a Dirichlet face through pore
+// voxels alone: 0 on those pores, 1..254 beyond them, 255 for inactive voxels, for
+// voxels farther than 254 steps and for voxels no such path reaches.
+void pore_depth(const Prepared &p, uint8_t *depth);
 
 // 13-direction averaged pore size (voxel edges) of every voxel of `pore`.
 void pore_size_13(int nx, int ny, int nz, const uint8_t *pore, std::vector<double> &dp);

@@ -288,15 +288,17 @@ __global__ __launch_bounds__(256) void k_head_bwd(const uint16_t *x, int ldx, co
     if (threadIdx.x == 0) atomicAdd(db, s);
 }
 
-__global__ __launch_bounds__(256) void k_mse(const float *pred, const float *target, const uint8_t *mask, float *dout,
-                                             float *loss, int64_t nvox, float inv_count) {
+__global__ __launch_bounds__(256) void k_mse(const float *pred, const float *target, const uint8_t *mask,
+                                             const float *weight, float *dout, float *loss, int64_t nvox,
+                                             float inv_count) {
     __shared__ float red[4];
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     float e = 0.f;
     if (v < nvox) {
         const float d = mask[v] ? pred[v] - target[v] : 0.f;
-        dout[v] = 2.f * d * inv_count;
-        e = d * d * inv_count;
+        const float wd = (weight ? weight[v] : 1.f) * d;
+        dout[v] = 2.f * wd * inv_count;
+        e = wd * d * inv_count;
     }
     const float s = block_sum(e, red);
     if (threadIdx.x == 0) atomicAdd(loss, s);
@@ -327,20 +329,44 @@ __global__ void k_zero(uint32_t *d, int64_t nwords) {
 }
 
 __global__ void k_features(const uint8_t *active, const uint8_t *ncat, const float *omega, float tau_ref,
-                           uint16_t *feat, int nz, int ny, int nx) {
+                           uint16_t *feat, float *weight, float weight_power, float weight_cap, int nz, int ny,
+                           int nx) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= (int64_t)nz * ny * nx) return;
     const int x = (int)(v % nx);
-    float f[4] = {0.f, 0.f, 0.f, nx > 1 ? (float)x / (float)(nx - 1) : 0.f};
+    // distances to the inlet and outlet faces in voxels, not fractions of the length,
+    // so that a network trained on short domains transfers to longer ones
+    const float xi = (float)x, xo = (float)(nx - 1 - x);
+    float f[6] = {0.f, 0.f, 0.f, expf(-xi / 24.f), expf(-xi / 96.f), expf(-xo / 24.f)};
+    float w = 0.f;
     if (active[v]) {
         f[0] = 1.f;
         const float tau = 1.f / omega[v];
-        const float drel = (tau - 0.5f) / (tau_ref - 0.5f);
-        f[1] = log10f(fmaxf(drel, 1e-9f)) / 3.f;
+        const float drel = fmaxf((tau - 0.5f) / (tau_ref - 0.5f), 1e-9f);
+        f[1] = log10f(drel) / 3.f;
         f[2] = (float)ncat[v] / 6.f;
+        w = fminf(weight_cap, powf(1.f / drel, weight_power));
     }
     uint16_t *o = feat + v * 16;
-    for (int c = 0; c < 16; ++c) o[c] = c < 4 ? f2bf(f[c]) : (uint16_t)0;
+    for (int c = 0; c < 16; ++c) o[c] = c < 6 ? f2bf(f[c]) : (uint16_t)0;
+    if (weight) weight[v] = w;
+}
+
+// y = ln(max(c, 0) + eps), or its inverse c = min(cmax, max(0, exp(y) - eps))
+__global__ void k_log_map(const float *src, float *dst, int64_t n, float eps, int inverse, float cmax) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float v = src[i];
+    dst[i] = inverse ? fminf(cmax, fmaxf(0.f, expf(v) - eps)) : logf(fmaxf(v, 0.f) + eps);
+}
+
+// start field of the solver from the network's log-space output: the prediction
+// where the pore depth is at most depth_max, zero (the cold start) elsewhere
+__global__ void k_start_field(const float *y, const uint8_t *depth, int depth_max, float eps, float cmax, float *c,
+                              int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    c[i] = (int)depth[i] <= depth_max ? fminf(cmax, fmaxf(0.f, expf(y[i]) - eps)) : 0.f;
 }
 
 // D = A B (16x32 by 32x16) through the conv kernel's fragment mapping
@@ -478,12 +504,12 @@ int unet_head_bwd(const uint16_t *x, int32_t ldx, const float *w, const float *d
     return status(hipGetLastError());
 }
 
-int unet_mse(const float *pred, const float *target, const uint8_t *mask, float *dout, float *loss, int64_t nvox,
-             int64_t count, void *stream) {
+int unet_mse(const float *pred, const float *target, const uint8_t *mask, const float *weight, float *dout,
+             float *loss, int64_t nvox, int64_t count, void *stream) {
     if (!pred || !target || !mask || !dout || !loss || nvox <= 0 || count <= 0) return -1;
     (void)hipGetLastError();
-    hipLaunchKernelGGL(k_mse, grid1(nvox), dim3(256), 0, static_cast<hipStream_t>(stream), pred, target, mask, dout,
-                       loss, nvox, 1.0f / (float)count);
+    hipLaunchKernelGGL(k_mse, grid1(nvox), dim3(256), 0, static_cast<hipStream_t>(stream), pred, target, mask, weight,
+                       dout, loss, nvox, 1.0f / (float)count);
     return status(hipGetLastError());
 }
 
@@ -514,11 +540,30 @@ int unet_zero(void *dst, int64_t bytes, void *stream) {
 }
 
 int unet_features(const uint8_t *active, const uint8_t *n_cat, const float *omega, float tau_ref, uint16_t *feat,
-                  int32_t nz, int32_t ny, int32_t nx, void *stream) {
+                  float *weight, float weight_power, float weight_cap, int32_t nz, int32_t ny, int32_t nx,
+                  void *stream) {
     if (!active || !n_cat || !omega || !feat || nz <= 0 || ny <= 0 || nx <= 0 || !(tau_ref > 0.5f)) return -1;
+    if (weight && !(weight_cap >= 1.f && weight_power >= 0.f && weight_power <= 4.f)) return -1;
     (void)hipGetLastError();
     hipLaunchKernelGGL(k_features, grid1((int64_t)nz * ny * nx), dim3(256), 0, static_cast<hipStream_t>(stream),
-                       active, n_cat, omega, tau_ref, feat, nz, ny, nx);
+                       active, n_cat, omega, tau_ref, feat, weight, weight_power, weight_cap, nz, ny, nx);
+    return status(hipGetLastError());
+}
+
+int unet_log_map(const float *src, float *dst, int64_t n, float eps, int32_t inverse, float cmax, void *stream) {
+    if (!src || !dst || n <= 0 || !(eps > 0.f) || !(cmax > 0.f)) return -1;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_log_map, grid1(n), dim3(256), 0, static_cast<hipStream_t>(stream), src, dst, n, eps,
+                       inverse ? 1 : 0, cmax);
+    return status(hipGetLastError());
+}
+
+int unet_start_field(const float *y, const uint8_t *depth, int32_t depth_max, float eps, float cmax, float *c,
+                     int64_t n, void *stream) {
+    if (!y || !depth || !c || n <= 0 || depth_max < 0 || !(eps > 0.f) || !(cmax > 0.f)) return -1;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_start_field, grid1(n), dim3(256), 0, static_cast<hipStream_t>(stream), y, depth, depth_max,
+                       eps, cmax, c, n);
     return status(hipGetLastError());
 }
 

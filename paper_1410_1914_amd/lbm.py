@@ -78,6 +78,7 @@ SIGNATURES = {
     "lbm_create": ([ctypes.POINTER(lbm_grid), ctypes.POINTER(c_uint8), ctypes.POINTER(lbm_params), _PP], c_int32),
     "lbm_get_info": ([_P, ctypes.POINTER(lbm_info)], c_int32),
     "lbm_get_host_fields": ([_P, ctypes.POINTER(c_uint8), ctypes.POINTER(c_uint8), ctypes.POINTER(c_float)], c_int32),
+    "lbm_get_pore_depth": ([_P, ctypes.POINTER(c_uint8)], c_int32),
     "lbm_workspace_bytes": ([_P, ctypes.POINTER(ctypes.c_size_t)], c_int32),
     "lbm_bind": ([_P, _P, ctypes.c_size_t, _P], c_int32),
     "lbm_set_initial_concentration": ([_P, _P], c_int32),
@@ -110,6 +111,7 @@ SIGNATURES = {
     "lbm_batch_concentration": ([_P, c_int32, _P], c_int32),
     "lbm_batch_get_host_fields": ([_P, c_int32, ctypes.POINTER(c_uint8), ctypes.POINTER(c_uint8),
                                    ctypes.POINTER(c_float)], c_int32),
+    "lbm_batch_get_pore_depth": ([_P, c_int32, ctypes.POINTER(c_uint8)], c_int32),
     "lbm_batch_destroy": ([_P], None),
 }
 
@@ -194,6 +196,13 @@ def lbm_get_host_fields(h):
         h, act.ctypes.data_as(ctypes.POINTER(c_uint8)), ncat.ctypes.data_as(ctypes.POINTER(c_uint8)),
         om.ctypes.data_as(ctypes.POINTER(c_float))))
     return act, ncat, om
+
+
+def lbm_get_pore_depth(h):
+    i = lbm_get_info(h)
+    depth = np.zeros((i.nz, i.ny, i.nx), np.uint8)
+    _check("lbm_get_pore_depth", load().lbm_get_pore_depth(h, depth.ctypes.data_as(ctypes.POINTER(c_uint8))))
+    return depth
 
 
 def lbm_workspace_bytes(h) -> int:
@@ -368,6 +377,14 @@ def lbm_batch_get_host_fields(h, i: int):
     return act, ncat, om
 
 
+def lbm_batch_get_pore_depth(h, i: int):
+    inf = lbm_batch_get_info(h, i)
+    depth = np.zeros((inf.nz, inf.ny, inf.nx), np.uint8)
+    _check("lbm_batch_get_pore_depth", load().lbm_batch_get_pore_depth(
+        h, i, depth.ctypes.data_as(ctypes.POINTER(c_uint8))))
+    return depth
+
+
 def lbm_batch_destroy(h):
     if h:
         load().lbm_batch_destroy(h)
@@ -481,6 +498,9 @@ class Solver:
     def host_fields(self):
         return lbm_get_host_fields(self.h)
 
+    def pore_depth(self):
+        return lbm_get_pore_depth(self.h)
+
     def close(self):
         lbm_destroy(self.h)
         self.h = None
@@ -543,6 +563,9 @@ class Batch:
 
     def host_fields(self, i):
         return lbm_batch_get_host_fields(self.h, i)
+
+    def pore_depth(self, i):
+        return lbm_batch_get_pore_depth(self.h, i)
 
     def __del__(self):
         try:

@@ -33,11 +33,13 @@ SIGNATURES = {
     "unet_up_bwd": ([_P, _i32, _i32, _P, _i32, _i32, _i32, _i32, _i32, _i32, _P], _i32),
     "unet_head_fwd": ([_P, _i32, _P, _P, _P, _P, _i64, _i32, _P], _i32),
     "unet_head_bwd": ([_P, _i32, _P, _P, _P, _P, _P, _i64, _i32, _P], _i32),
-    "unet_mse": ([_P, _P, _P, _P, _P, _i64, _i64, _P], _i32),
+    "unet_mse": ([_P, _P, _P, _P, _P, _P, _i64, _i64, _P], _i32),
     "unet_adam": ([_P, _P, _P, _P, _P, _i64, _f32, _f32, _f32, _f32, _i32, _P], _i32),
     "unet_to_bf16": ([_P, _P, _i64, _P], _i32),
     "unet_zero": ([_P, _i64, _P], _i32),
-    "unet_features": ([_P, _P, _P, _f32, _P, _i32, _i32, _i32, _P], _i32),
+    "unet_log_map": ([_P, _P, _i64, _f32, _i32, _f32, _P], _i32),
+    "unet_start_field": ([_P, _P, _i32, _f32, _f32, _P, _i64, _P], _i32),
+    "unet_features": ([_P, _P, _P, _f32, _P, _P, _f32, _f32, _i32, _i32, _i32, _P], _i32),
     "unet_mfma_selftest": ([_P, _P, _P, _P], _i32),
 }
 
@@ -126,8 +128,9 @@ def unet_head_bwd(x, ldx, w, dout, dx, dw, db, nvox, c):
     _call("unet_head_bwd", _ptr(x), ldx, _ptr(w), _ptr(dout), _ptr(dx), _ptr(dw), _ptr(db), nvox, c, _stream())
 
 
-def unet_mse(pred, target, mask, dout, loss, nvox, count):
-    _call("unet_mse", _ptr(pred), _ptr(target), _ptr(mask), _ptr(dout), _ptr(loss), nvox, count, _stream())
+def unet_mse(pred, target, mask, dout, loss, nvox, count, weight=None):
+    _call("unet_mse", _ptr(pred), _ptr(target), _ptr(mask), _ptr(weight), _ptr(dout), _ptr(loss), nvox, count,
+          _stream())
 
 
 def unet_adam(p, m, v, g, pb, n, lr, b1, b2, eps, t):
@@ -142,8 +145,17 @@ def unet_zero(t):
     _call("unet_zero", _ptr(t), t.numel() * t.element_size(), _stream())
 
 
-def unet_features(active, n_cat, omega, tau_ref, feat, shape):
-    _call("unet_features", _ptr(active), _ptr(n_cat), _ptr(omega), tau_ref, _ptr(feat), *shape, _stream())
+def unet_features(active, n_cat, omega, tau_ref, feat, shape, weight=None, weight_power=0.5, weight_cap=32.0):
+    _call("unet_features", _ptr(active), _ptr(n_cat), _ptr(omega), tau_ref, _ptr(feat), _ptr(weight), weight_power,
+          weight_cap, *shape, _stream())
+
+
+def unet_log_map(src, dst, n, eps, inverse, cmax=2.0):
+    _call("unet_log_map", _ptr(src), _ptr(dst), n, eps, 1 if inverse else 0, cmax, _stream())
+
+
+def unet_start_field(y, depth, depth_max, eps, cmax, c, n):
+    _call("unet_start_field", _ptr(y), _ptr(depth), depth_max, eps, cmax, _ptr(c), n, _stream())
 
 
 def unet_mfma_selftest(a, b, d):
@@ -191,6 +203,7 @@ class UNet:
         self.mb = {k: torch.zeros_like(v) for k, v in self.B.items()}
         self.vb = {k: torch.zeros_like(v) for k, v in self.B.items()}
         self.t = 0
+        self.target_eps = 0.0  # > 0: the network predicts ln(C + target_eps) instead of C
         self._bufs = None
 
     # parameters -------------------------------------------------------------
@@ -205,6 +218,7 @@ class UNet:
     def state_dict(self):
         d = {f"W_{k}": v.cpu().numpy() for k, v in self.W.items()}
         d.update({f"B_{k}": v.cpu().numpy() for k, v in self.B.items()})
+        d["target_eps"] = np.array(self.target_eps, np.float64)
         return d
 
     def load_state_dict(self, d):
@@ -213,6 +227,7 @@ class UNet:
         for k in self.W:
             self.W[k] = torch.from_numpy(np.asarray(d[f"W_{k}"], np.float32)).to(self.device)
             self.B[k] = torch.from_numpy(np.asarray(d[f"B_{k}"], np.float32)).to(self.device)
+        self.target_eps = float(d["target_eps"]) if "target_eps" in d else 0.0
         self._sync_bf16()
 
     def save(self, path):
@@ -346,12 +361,12 @@ class UNet:
             unet_adam(self.W[k], self.m[k], self.v[k], self.gW[k], wb, self.W[k].numel(), lr, b1, b2, eps, self.t)
             unet_adam(self.B[k], self.mb[k], self.vb[k], self.gB[k], None, self.B[k].numel(), lr, b1, b2, eps, self.t)
 
-    def train_step(self, feat, shape, target, mask, count, lr):
-        """One Adam step on the masked MSE between the prediction and target."""
+    def train_step(self, feat, shape, target, mask, count, lr, weight=None):
+        """One Adam step on the (weighted) masked MSE between the prediction and target."""
         b = self._alloc(shape, True)
         pred = self.forward(feat, shape, train=True)
         unet_zero(b["loss"])
-        unet_mse(pred, target, mask, b["g_out"], b["loss"], b["V"][0], count)
+        unet_mse(pred, target, mask, b["g_out"], b["loss"], b["V"][0], count, weight)
         self.backward(feat, b["g_out"])
         self.adam_step(lr)
         return b["loss"]

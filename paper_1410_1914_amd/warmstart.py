@@ -10,13 +10,22 @@ plane) is a multiple of 8 for the network's three poolings.
 
 Pipeline:
   1. training fields: the batched HIP solver's steady states on seeded structures;
-  2. training: the U-Net of ``unet.py`` on the GPU with the project's own kernels
-     (masked MSE on the simulated voxels, Adam);
-  3. use: features of a new structure -> predicted concentration -> equilibrium
-     populations (``lbm_set_initial_concentration``) -> the solver refines to its own
-     stop rule.  If the windowed residual rises between the first two checks the
-     solve falls back to the cold start, so the network can never change the answer,
-     only the number of steps.
+  2. training: the U-Net of ``unet.py`` on the GPU with the project's own kernels.
+     The target is ln(C + 1e-3), so the error is relative to C, and the masked
+     MSE weighs a voxel by sqrt(D_ref / D) (capped), so slowly relaxing ionomer
+     counts more;
+  3. use: features of a new structure -> predicted concentration, kept where the
+     pore depth (lbm_get_pore_depth) is at most DEPTH_MAX and C = 0 deeper in ->
+     equilibrium populations (``lbm_set_initial_concentration``) -> the solver
+     refines to its own stop rule.  If the windowed residual rises between the
+     first two checks the solve falls back to the cold start, so the network can
+     never change the answer, only the number of steps.
+
+Why the depth mask: the steps a solve needs are set by the voxels that relax
+slowest, which are ionomer films and blobs (D = 1e-3 D0, tau close to 1/2).  Their
+concentration is small, so the cold start's error there is already small, and a
+prediction only helps where its error is smaller still; beyond two voxels into the
+ionomer the trained network's is not.
 """
 from __future__ import annotations
 
@@ -35,6 +44,11 @@ K_LAT = 1e-2
 VOXEL_M = 2e-9
 TRAIN_SHAPE = (96, 96, 95)    # structure (nz, ny, nx); simulated grid (96, 96, 96)
 TEST_SHAPE = (192, 192, 191)  # simulated grid (192, 192, 192)
+WEIGHT_POWER = 0.5
+WEIGHT_CAP = 32.0
+TARGET_EPS = 1e-3   # the network predicts ln(C + TARGET_EPS)
+DEPTH_MAX = 2       # the prediction is used up to this pore depth; C = 0 (cold) deeper in
+C_MAX = 1.5         # upper clip of a predicted start (the discrete field may exceed C_in slightly)
 
 
 def params(**kw):
@@ -73,11 +87,28 @@ def features(active, ncat, omega, tau_ref=1.0):
     return feat, a
 
 
-def predict(net, active, ncat, omega):
-    """Predicted steady concentration (FP32, dense simulated grid, on the GPU)."""
+def predict(net, active, ncat, omega, depth=None, depth_max=DEPTH_MAX):
+    """Start field for the solver (FP32, dense simulated grid, on the GPU): the
+    predicted steady concentration, and, when the pore-depth map is given, the cold
+    value 0 in voxels deeper than depth_max (ionomer interiors relax slowly and hold
+    little oxygen; a wrong guess there costs more steps than C = 0)."""
+    import torch
+
     feat, _ = features(active, ncat, omega)
     out = net.forward(feat, active.shape)
-    return out.view(active.shape)
+    c = torch.empty(out.numel(), dtype=torch.float32, device=out.device)
+    if depth is not None:
+        if not net.target_eps > 0:
+            raise ValueError("the depth-masked start needs a log-space network")
+        d = torch.from_numpy(np.ascontiguousarray(depth)).to(out.device)
+        unet.unet_start_field(out, d, depth_max, net.target_eps, C_MAX, c, out.numel())
+    elif net.target_eps > 0:
+        unet.unet_log_map(out, c, out.numel(), net.target_eps, True, C_MAX)
+    else:
+        # linear-output network: the same clip through the map's inverse of ln(C + 1)
+        unet.unet_log_map(out, c, out.numel(), 1.0, False)
+        unet.unet_log_map(c, c, out.numel(), 1.0, True, C_MAX)
+    return c.view(active.shape)
 
 
 # ------------------------------------------------------------------ solves
@@ -109,7 +140,7 @@ def solve(solver, c0=None, fallback=True):
 
 # ------------------------------------------------------------------ training data
 
-def make_dataset(seeds, shape=TRAIN_SHAPE, batch=32, tol_flux=1e-4, log=print):
+def make_dataset(seeds, shape=TRAIN_SHAPE, batch=32, tol_flux=1e-4, tol_change=1e-8, log=print):
     """Steady fields of the batched solver.  Returns a list of per-sample dicts of
     GPU tensors (active u8, ncat u8, omega f32, target f32) and host shape."""
     import torch
@@ -119,7 +150,7 @@ def make_dataset(seeds, shape=TRAIN_SHAPE, batch=32, tol_flux=1e-4, log=print):
     for s0 in range(0, len(phases), batch):
         chunk = phases[s0:s0 + batch]
         t = time.perf_counter()
-        b = lbm.Batch(chunk, [params(tol_flux=tol_flux) for _ in chunk], voxel_m=VOXEL_M)
+        b = lbm.Batch(chunk, [params(tol_flux=tol_flux, tol_change=tol_change) for _ in chunk], voxel_m=VOXEL_M)
         st, infos = b.run()
         for i in range(len(chunk)):
             act, ncat, om = b.host_fields(i)
@@ -133,13 +164,36 @@ def make_dataset(seeds, shape=TRAIN_SHAPE, batch=32, tol_flux=1e-4, log=print):
     return data
 
 
-def train(net, data, epochs=4, lr=1e-3, log=print, seed=0):
-    """Adam on the masked MSE, cosine learning-rate decay; returns the loss history."""
+def _log_targets(data, eps):
+    """ln(C + eps) of every sample's target (kept with the sample)."""
+    import torch
+
+    key = ("y", eps)
+    for d in data:
+        if d.get("y_key") != key:
+            t = d["target"].view(-1)
+            d["y"] = torch.empty_like(t)
+            unet.unet_log_map(t, d["y"], t.numel(), eps, False)
+            d["y_key"] = key
+
+
+def train(net, data, epochs=4, lr=1e-3, log=print, seed=0, weight_power=WEIGHT_POWER, weight_cap=WEIGHT_CAP,
+          target_eps=TARGET_EPS):
+    """Adam on the weighted masked MSE, cosine learning-rate decay; returns the loss
+    history.  The weight of a voxel is (D_ref / D)^weight_power capped at weight_cap: an error
+    left in a low-diffusivity voxel (ionomer) relaxes slowly, so it costs the solver
+    far more steps than the same error in a pore."""
     import torch
 
     rng = np.random.default_rng(seed)
     hist = []
     total = epochs * len(data)
+    if target_eps > 0:
+        _log_targets(data, target_eps)
+        if net.t == 0:  # start the output bias at the mean log target
+            m = float(np.mean([float(d["y"][d["active"].view(-1) > 0].mean()) for d in data[:32]]))
+            net.B["head"].fill_(m)
+    net.target_eps = target_eps
     step = 0
     for ep in range(epochs):
         order = rng.permutation(len(data))
@@ -147,9 +201,10 @@ def train(net, data, epochs=4, lr=1e-3, log=print, seed=0):
         losses = []
         for idx in order:
             d = data[idx]
-            feat, _ = _features_dev(d)
+            feat, weight = _features_dev(d, weight_power, weight_cap)
             lr_t = lr * 0.5 * (1 + np.cos(np.pi * step / total))
-            loss = net.train_step(feat, d["shape"], d["target"].view(-1), d["active"].view(-1), d["count"], lr_t)
+            tgt = d["y"] if target_eps > 0 else d["target"].view(-1)
+            loss = net.train_step(feat, d["shape"], tgt, d["active"].view(-1), d["count"], lr_t, weight)
             losses.append(loss.clone())
             step += 1
         torch.cuda.synchronize()
@@ -159,20 +214,31 @@ def train(net, data, epochs=4, lr=1e-3, log=print, seed=0):
     return hist
 
 
-def _features_dev(d):
+def _features_dev(d, weight_power=WEIGHT_POWER, weight_cap=WEIGHT_CAP):
+    """Features and per-voxel loss weights of one training sample (on the GPU)."""
     import torch
 
     shape = d["shape"]
     feat = torch.empty((int(np.prod(shape)), unet.IN_CH), dtype=torch.bfloat16, device="cuda")
-    unet.unet_features(d["active"], d["ncat"], d["omega"], 1.0, feat, shape)
-    return feat, d["active"]
+    weight = torch.empty(int(np.prod(shape)), dtype=torch.float32, device="cuda")
+    unet.unet_features(d["active"], d["ncat"], d["omega"], 1.0, feat, shape, weight, weight_power, weight_cap)
+    return feat, weight
 
 
 # ------------------------------------------------------------------ evaluation
 
+def linear_profile(shape, c_in=1.0):
+    """C_in (1 - x / (nx - 1)) on the simulated grid: the linear-profile start."""
+    import torch
+
+    nx = shape[2]
+    prof = c_in * (1.0 - torch.arange(nx, dtype=torch.float32, device="cuda") / max(nx - 1, 1))
+    return prof.expand(shape).contiguous()
+
+
 def compare(net, seeds, shape=TEST_SHAPE, log=print):
-    """Cold start, uniform-inlet start (C = C_in everywhere) and learned start on
-    fresh structures: steps, wall time (inference included) and converged rate."""
+    """Cold start (C = 0), linear-profile start and learned start on fresh
+    structures: steps, wall time (inference included) and converged rate."""
     import torch
 
     phases = [structure(s, shape) for s in seeds]
@@ -181,18 +247,21 @@ def compare(net, seeds, shape=TEST_SHAPE, log=print):
         s = lbm.Solver(ph, params(), voxel_m=VOXEL_M)
         act, ncat, om = s.host_fields()
         cold = solve(s, None)
-        uni = solve(s, torch.ones(act.shape, dtype=torch.float32, device="cuda"))
+        lin = solve(s, linear_profile(act.shape))
+        unmasked = solve(s, predict(net, act, ncat, om))
         t0 = time.perf_counter()
-        c0 = predict(net, act, ncat, om).clamp(0.0, 1.0)
+        depth = s.pore_depth()
+        c0 = predict(net, act, ncat, om, depth)
         torch.cuda.synchronize()
         t_inf = time.perf_counter() - t0
         warm = solve(s, c0)
         warm["wall_s"] += t_inf
         warm["inference_s"] = t_inf
-        row = {"seed": seed, "cold": cold, "uniform": uni, "warm": warm,
+        row = {"seed": seed, "cold": cold, "linear": lin, "warm": warm, "warm_unmasked": unmasked,
                "rate_rel_diff": abs(warm["rate"] / cold["rate"] - 1)}
         rows.append(row)
-        log(f"[warm] seed {seed}: steps cold {cold['steps']} uniform {uni['steps']} warm {warm['steps']} "
+        log(f"[warm] seed {seed}: steps cold {cold['steps']} linear {lin['steps']} warm {warm['steps']} "
+            f"(unmasked prediction {unmasked['steps']}) "
             f"(inference {t_inf * 1e3:.1f} ms); wall cold {cold['wall_s']:.2f}s warm {warm['wall_s']:.2f}s; "
             f"rate diff {row['rate_rel_diff']:.1e}, fallback {warm['fallback']}")
         s.close()
@@ -200,18 +269,21 @@ def compare(net, seeds, shape=TEST_SHAPE, log=print):
         "workload": f"Pt CL reactive, k={K_LAT}, Knudsen, {shape[0]}x{shape[1]}x{shape[2] + 1} simulated",
         "seeds": list(seeds),
         "steps_cold": float(np.mean([r["cold"]["steps"] for r in rows])),
-        "steps_uniform": float(np.mean([r["uniform"]["steps"] for r in rows])),
+        "steps_linear": float(np.mean([r["linear"]["steps"] for r in rows])),
         "steps_warm": float(np.mean([r["warm"]["steps"] for r in rows])),
+        "steps_warm_unmasked": float(np.mean([r["warm_unmasked"]["steps"] for r in rows])),
         "wall_cold_s": float(np.mean([r["cold"]["wall_s"] for r in rows])),
-        "wall_uniform_s": float(np.mean([r["uniform"]["wall_s"] for r in rows])),
+        "wall_linear_s": float(np.mean([r["linear"]["wall_s"] for r in rows])),
         "wall_warm_s": float(np.mean([r["warm"]["wall_s"] for r in rows])),
         "inference_ms": float(np.mean([r["warm"]["inference_s"] for r in rows]) * 1e3),
+        "depth_max": DEPTH_MAX,
         "fallbacks": int(sum(r["warm"]["fallback"] for r in rows)),
         "max_rate_rel_diff": float(max(r["rate_rel_diff"] for r in rows)),
     }
     summ["speedup_steps"] = summ["steps_cold"] / summ["steps_warm"]
     summ["speedup_wall"] = summ["wall_cold_s"] / summ["wall_warm_s"]
-    summ["speedup_wall_vs_uniform"] = summ["wall_uniform_s"] / summ["wall_warm_s"]
+    summ["speedup_steps_vs_linear"] = summ["steps_linear"] / summ["steps_warm"]
+    summ["speedup_wall_vs_linear"] = summ["wall_linear_s"] / summ["wall_warm_s"]
     return summ
 
 

@@ -141,3 +141,63 @@ def test_segment_count_and_reservoir_plane():
     assert (i.nx, i.nx_struct) == (131, 130)
     assert i.n_segments == 3 * 5 * 4
     lbm.lbm_destroy(h)
+
+
+def _depth_reference(phase_sim, active, react):
+    """Breadth-first distances, written out plainly: seeds are pore voxels joined to
+    a Dirichlet face through pore voxels (6-neighbours, periodic y and z)."""
+    from collections import deque
+
+    nz, ny, nx = active.shape
+    pore = active & (phase_sim == sg.PORE)
+
+    def nbrs(z, y, x):
+        if x > 0:
+            yield z, y, x - 1
+        if x + 1 < nx:
+            yield z, y, x + 1
+        yield z, (y - 1) % ny, x
+        yield z, (y + 1) % ny, x
+        yield (z - 1) % nz, y, x
+        yield (z + 1) % nz, y, x
+
+    joined = np.zeros_like(pore)
+    q = deque()
+    faces = [0] if react else [0, nx - 1]
+    for z in range(nz):
+        for y in range(ny):
+            for x in faces:
+                if pore[z, y, x] and not joined[z, y, x]:
+                    joined[z, y, x] = True
+                    q.append((z, y, x))
+    while q:
+        v = q.popleft()
+        for t in nbrs(*v):
+            if pore[t] and not joined[t]:
+                joined[t] = True
+                q.append(t)
+    depth = np.full(active.shape, 255, np.int64)
+    depth[joined] = 0
+    q = deque(zip(*np.nonzero(joined)))
+    while q:
+        v = q.popleft()
+        for t in nbrs(*v):
+            if active[t] and depth[t] == 255 and depth[v] + 1 <= 254:
+                depth[t] = depth[v] + 1
+                q.append(t)
+    return depth
+
+
+@pytest.mark.parametrize("mode,seed", [(lbm.MODE_REACT, 3), (lbm.MODE_DEFF, 4), (lbm.MODE_REACT, 11)])
+def test_pore_depth_matches_breadth_first_search(mode, seed):
+    ph = sg.pt_cl(seed, shape=(6, 7, 24))
+    h = lbm.lbm_create(ph, lbm.lbm_params_default(mode=mode, k_lat=0.01 if mode == lbm.MODE_REACT else 0.0))
+    act, _, _ = lbm.lbm_get_host_fields(h)
+    depth = lbm.lbm_get_pore_depth(h)
+    lbm.lbm_destroy(h)
+    react = mode == lbm.MODE_REACT
+    phs = np.concatenate([np.zeros(ph.shape[:2] + (1,), np.uint8), ph], axis=2) if react else ph
+    want = _depth_reference(phs, act.astype(bool), react)
+    assert np.array_equal(depth.astype(np.int64), want)
+    assert (depth[act.astype(bool)] < 255).any() and (depth[~act.astype(bool)] == 255).all()
+    assert set(np.unique(depth[act.astype(bool)])) > {0, 1}

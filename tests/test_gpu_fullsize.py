@@ -1,0 +1,96 @@
+"""Parity at the full workload sizes, in the launch configuration the benchmark times.
+
+The oracle cannot reach the fixed point of a 128^3 or 256^3 structure in seconds,
+but it can take one exact FP64 step.  So each case:
+
+* runs the autotuned HIP solver from the cold start for some steps, so the state
+  has real boundary layers, sinks and interfaces;
+* streams and collides that stored state once with the oracle;
+* compares with the GPU's next stored state, element by element over every fluid
+  voxel;
+* compares the FP64 reductions (fluxes, sink, mass) of a state against the
+  oracle's.
+
+The tolerance is that of the small step tests: a few FP32 ulps of the largest
+population."""
+import numpy as np
+import pytest
+
+import structgen as sg
+from oracle import lbm as O
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # Pt catalyst layer 128^3 at 2 nm: reactive k = 1e-2 on Pt faces, Knudsen, ionomer 1e-3 D0
+    ("pt_cl_128", lambda: sg.pt_cl(1, n=128), 2e-9, dict(mode=1, knudsen=1, k_lat=1e-2)),
+    # NPMC catalyst layer 256^3 at 1 nm: every carbon/Pt face reactive, k = 1e-4, Knudsen
+    ("npmc_cl_256", lambda: sg.npmc_cl(1, n=256), 1e-9,
+     dict(mode=1, knudsen=1, k_lat=1e-4, catalyst_phases=(1 << O.CARBON) | (1 << O.PT))),
+]
+
+
+@pytest.mark.parametrize("name,make,voxel,kw", CASES, ids=[c[0] for c in CASES])
+def test_full_size_step_and_reductions(hip, name, make, voxel, kw):
+    import torch
+
+    print(f"[fullsize] {name}: generating", flush=True)
+    ph = make()
+    s = hip.Solver(ph, hip.lbm_params_default(check_every=100, **kw), voxel_m=voxel)
+    s.autotune(5)  # the benchmark's launch configuration (also advances the state)
+    s.advance(300)
+    torch.cuda.synchronize()
+    print(f"[fullsize] {name}: tiling {s.tiling()}, oracle preparation", flush=True)
+    okw = dict(kw)
+    okw["knudsen"] = bool(okw["knudsen"])
+    prob = O.prepare(ph, O.Params(voxel_m=voxel, **okw))
+    act = prob.active.ravel()
+    assert np.array_equal(s.host_fields()[0].ravel().astype(bool), act)
+
+    g = s.populations().cpu().numpy().reshape(7, -1).astype(np.float64)  # stored post-collision state
+    s.step(1)
+    got = s.populations().cpu().numpy().reshape(7, -1)
+    f1 = O.stream(prob, g)
+    want = O.collide(prob, f1)
+    scale = max(1.0, float(np.abs(want).max()))
+    err = float(np.abs(got[:, act] - want[:, act]).max())
+    print(f"[fullsize] {name}: one step, max |GPU - oracle| = {err:.2e} (scale {scale:.2f})", flush=True)
+    assert err < 2e-6 * scale
+
+    # FP64 reductions of the state whose pre-collision populations are f1
+    s.set_populations(torch.from_numpy(want.astype(np.float32)).reshape((7,) + s.shape))
+    m = s.measure()
+    ref = O.fluxes(prob, f1)
+    sc = max(abs(ref.j_in), abs(ref.rate), 1e-30)
+    print(f"[fullsize] {name}: j_in {m.j_in:.9e} vs {ref.j_in:.9e}, rate {m.rate:.9e} vs {ref.rate:.9e}", flush=True)
+    assert m.j_in == pytest.approx(ref.j_in, abs=1e-6 * sc)
+    assert m.rate == pytest.approx(ref.rate, abs=1e-6 * sc)
+    assert m.mass == pytest.approx(ref.mass, rel=1e-6)
+
+
+def test_batched_instances_match_single_solves(hip):
+    """Instances of the batched workload (uneven sizes, porosities and rates, one
+    launch per step) reach the single-solver answers."""
+    import torch
+
+    phases, ks = [], []
+    for i, (edge, por, k) in enumerate([(48, 0.45, 3e-2), (64, 0.6, 1e-3), (48, 0.35, 1e-1), (64, 0.5, 1e-4)]):
+        phases.append(sg.pt_cl(2024000 + i, shape=(edge, edge, edge), carbon=(1 - por) * 0.35 / 0.55,
+                               ionomer=(1 - por) * 0.20 / 0.55))
+        ks.append(k)
+    params = [hip.lbm_params_default(mode=1, k_lat=k, check_every=200) for k in ks]
+    b = hip.Batch(phases, params)
+    b.autotune(5)
+    st, infos = b.run()
+    assert st == 0
+    torch.cuda.synchronize()
+    for i, ph in enumerate(phases):
+        s = hip.Solver(ph, params[i])
+        st1, _ = s.run_to_steady()
+        assert st1 == 0
+        r_single = s.reaction_rate()[1]
+        r_batch = b.reaction_rate(i)[1]
+        print(f"[batch] instance {i}: rate batched {r_batch:.9e} single {r_single:.9e}", flush=True)
+        assert r_batch == pytest.approx(r_single, rel=2e-5)
+        cb = b.concentration(i)
+        assert torch.allclose(cb, s.concentration(), rtol=0, atol=2e-4)

@@ -194,6 +194,12 @@ def test_head_mse_adam(U):
     rl, rg = C.mse(pred, tgt, mask)
     assert _host(loss)[0] == pytest.approx(rl, rel=1e-5)
     assert np.allclose(_host(g), rg, rtol=1e-5, atol=1e-7)
+    wt = rng.random(nvox) * 4
+    loss.zero_()
+    U.unet_mse(_dev_f32(pred), _dev_f32(tgt), torch.tensor(mask).cuda(), g, loss, nvox, int(mask.sum()), _dev_f32(wt))
+    rl, rg = C.mse(pred, tgt, mask, wt.astype(np.float32).astype(np.float64))
+    assert _host(loss)[0] == pytest.approx(rl, rel=1e-5)
+    assert np.allclose(_host(g), rg, rtol=1e-5, atol=1e-7)
     # Adam: two steps against the oracle
     n = 1000
     p0, g1, g2 = rng.standard_normal(n), rng.standard_normal(n), rng.standard_normal(n)
@@ -217,15 +223,22 @@ def test_features(U):
     tau = 0.5 + rng.random(shape) * 0.5 + 1e-3
     om = np.where(act, 1 / tau, 0).astype(np.float32)
     feat = torch.zeros(shape + (16,), dtype=torch.bfloat16, device="cuda")
-    U.unet_features(torch.tensor(act).cuda(), torch.tensor(ncat).cuda(), _dev_f32(om), 1.0, feat, shape)
+    wt = torch.full(shape, -1.0, dtype=torch.float32, device="cuda")
+    U.unet_features(torch.tensor(act).cuda(), torch.tensor(ncat).cuda(), _dev_f32(om), 1.0, feat, shape, wt, 0.5, 8.0)
     f = _host(feat)
     t32 = 1.0 / om.astype(np.float64)
-    want1 = np.where(act, np.log10(np.maximum((t32 - 0.5) / 0.5, 1e-9)) / 3, 0)
+    drel = np.maximum((t32 - 0.5) / 0.5, 1e-9)
+    want1 = np.where(act, np.log10(drel) / 3, 0)
+    x = np.arange(10, dtype=np.float64)
     assert np.array_equal(f[..., 0], act.astype(float))
     assert np.allclose(f[..., 1], want1, atol=1e-2)
     assert np.allclose(f[..., 2], np.where(act, ncat / 6, 0), atol=1e-2)
-    assert np.allclose(f[..., 3], np.broadcast_to(np.arange(10) / 9, shape), atol=1e-2)
-    assert np.all(f[..., 4:] == 0)
+    for c, prof in ((3, np.exp(-x / 24)), (4, np.exp(-x / 96)), (5, np.exp(-(9 - x) / 24))):
+        assert np.allclose(f[..., c], np.broadcast_to(prof, shape), rtol=1e-2, atol=1e-3)
+    assert np.all(f[..., 6:] == 0)
+    assert np.allclose(_host(wt), np.where(act, np.minimum(8.0, np.sqrt(1 / drel)), 0), rtol=1e-5)
+    U.unet_features(torch.tensor(act).cuda(), torch.tensor(ncat).cuda(), _dev_f32(om), 1.0, feat, shape, wt, 1.0, 3.0)
+    assert np.allclose(_host(wt), np.where(act, np.minimum(3.0, 1 / drel), 0), rtol=1e-5)
 
 
 def test_network_gradient_matches_finite_differences(U):
@@ -277,3 +290,32 @@ def test_network_gradient_matches_finite_differences(U):
             fd = (L(Pp) - L(Pm)) / (2 * eps)
             an = float(np.sum(g * d))
             assert an == pytest.approx(fd, rel=0.15, abs=0.05 * np.linalg.norm(g)), (name, an, fd)
+
+
+def test_log_map_round_trip(U):
+    import torch
+
+    rng = np.random.default_rng(12)
+    c = np.concatenate([rng.random(1000) * 1.3, [-0.5, 0.0, 5.0]])
+    y = torch.zeros(c.size, dtype=torch.float32, device="cuda")
+    U.unet_log_map(_dev_f32(c), y, c.size, 1e-3, False)
+    c32 = c.astype(np.float32).astype(np.float64)
+    assert np.allclose(_host(y), np.log(np.maximum(c32, 0) + 1e-3), rtol=1e-6, atol=1e-6)
+    back = torch.zeros_like(y)
+    U.unet_log_map(y, back, c.size, 1e-3, True, 1.5)
+    assert np.allclose(_host(back), np.clip(c32, 0, 1.5), rtol=1e-5, atol=1e-6)
+
+
+def test_start_field_masks_deep_voxels(U):
+    import torch
+
+    rng = np.random.default_rng(13)
+    n = 3000
+    y = np.log(rng.random(n) * 1.4 + 1e-3)
+    depth = rng.integers(0, 6, n).astype(np.uint8)
+    depth[:10] = 255
+    c = torch.full((n,), -1.0, dtype=torch.float32, device="cuda")
+    U.unet_start_field(_dev_f32(y), torch.tensor(depth).cuda(), 2, 1e-3, 1.2, c, n)
+    y32 = y.astype(np.float32).astype(np.float64)
+    want = np.where(depth <= 2, np.clip(np.exp(y32) - 1e-3, 0, 1.2), 0.0)
+    assert np.allclose(_host(c), want, rtol=1e-5, atol=1e-6)

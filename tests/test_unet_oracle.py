@@ -70,6 +70,14 @@ def test_mse_gradient_and_adam_first_step():
     e[1, 2, 3] = 1e-6
     fd = (C.mse(p + e, t, mask)[0] - C.mse(p - e, t, mask)[0]) / 2e-6
     assert g[1, 2, 3] == pytest.approx(fd, rel=1e-6, abs=1e-12)
+    # weighted: a weight of 2 on one voxel is the same as counting that voxel twice
+    w = np.ones_like(p)
+    w[1, 2, 3] = 2.0
+    lw, gw = C.mse(p, t, mask, w)
+    d = np.where(mask, p - t, 0.0)
+    assert lw == pytest.approx(((d * d).sum() + d[1, 2, 3] ** 2) / mask.sum(), rel=1e-12)
+    fdw = (C.mse(p + e, t, mask, w)[0] - C.mse(p - e, t, mask, w)[0]) / 2e-6
+    assert gw[1, 2, 3] == pytest.approx(fdw, rel=1e-6, abs=1e-12)
     # Adam's first step from zero moments moves each weight by lr * g / (|g| + eps)
     g = _rand(rng, 10)
     p0 = _rand(rng, 10)
