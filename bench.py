@@ -47,6 +47,10 @@ def parse():
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-start leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU time budget of the oracle sample")
     ap.add_argument("--no-tune", action="store_true", help="keep the default tiling (no autotuning)")
+    ap.add_argument("--batch64", action="store_true",
+                    help="also time the uneven 64-structure reactive batch: batched vs sequential solves")
+    ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--batch-max-edge", type=int, default=None)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy three times (calibrates HBM byte counters) and exit")
     return ap.parse_args()
@@ -220,6 +224,56 @@ def solves_leg(lbm, structgen):
             "mean_steps": int(sum(steps) / len(steps)), "tiling": list(b.tiling())}
 
 
+def _batch_instance(i, max_edge):
+    import structgen
+
+    return structgen.batch_instances(2024, count=1, max_edge=max_edge, first=i)[0]
+
+
+def batch64_structures(args):
+    """The uneven 64-structure batch, generated on host processes before any GPU work."""
+    from concurrent.futures import ProcessPoolExecutor
+
+    n = args.batch_count
+    with ProcessPoolExecutor(max_workers=min(16, n)) as ex:
+        return list(ex.map(_batch_instance, range(n), [args.batch_max_edge] * n))
+
+
+def batch64_leg(lbm, insts):
+    """64 sequential single solves vs one batched solve of the same reactive instances."""
+    import torch
+
+    params = [lbm.lbm_params_default(mode=lbm.MODE_REACT, k_lat=d["k"], check_every=200) for d in insts]
+    phases = [d["phase"] for d in insts]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    single, steps = [], []
+    for ph, p in zip(phases, params):
+        s = lbm.Solver(ph, p)
+        st, r = s.run_to_steady()
+        single.append(s.reaction_rate()[1])
+        steps.append(r.steps)
+        s.close()
+        log(f"[bench] batch leg: single solve {len(single)}/{len(phases)} ({ph.shape[0]}^3, {r.steps} steps, "
+            f"status {st})")
+    t_single = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = lbm.Batch(phases, params)
+    b.autotune(20)
+    st, infos = b.run()
+    batched = [b.reaction_rate(i)[1] for i in range(len(phases))]
+    t_batch = time.perf_counter() - t0
+    vox = sum(int(ph.size) for ph in phases)
+    return {"workload": f"{len(phases)} reactive Pt-CL structures, edges in {{48..{max(ph.shape[0] for ph in phases)}}}, "
+                        f"porosity 0.3-0.7, k log-uniform 1e-4..1e-1 ({vox / 1e6:.1f} M voxels)",
+            "single_solves_per_s": round(len(phases) / t_single, 3),
+            "batched_solves_per_s": round(len(phases) / t_batch, 3),
+            "batched_speedup": round(t_single / t_batch, 2),
+            "max_rate_rel_diff": max(abs(a / c - 1) for a, c in zip(batched, single)),
+            "status": st, "max_steps": int(max(steps)), "tiling": list(b.tiling())}
+
+
 def warm_leg():
     try:
         from paper_1410_1914_amd import warmstart
@@ -250,6 +304,7 @@ def main():
     import structgen
     from paper_1410_1914_amd import lbm
 
+    insts = batch64_structures(args) if args.batch64 else None  # host work before the GPU is touched
     lbm.require_gpu()
     head, ph = headline(args, lbm, structgen)
     out = {
@@ -263,7 +318,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 storage, f64 arithmetic and reductions",
+        "dtype": "f64",
+        "storage_dtype": "f32",
         "data": "synthetic (seeded QSGS structure)",
         "config": {"workload": head["workload"], "edge": args.n, "voxel_nm": 1.0, "lbm_steps_per_step": args.lbm_steps,
                    "fluid_voxels": head["n_active"], "k_lat": 1e-4, "parallelism": "single GPU"},
@@ -278,6 +334,9 @@ def main():
     if not args.no_solves:
         log("[bench] 32^3 solves/s legs ...")
         out["solves"] = solves_leg(lbm, structgen)
+    if insts is not None:
+        log("[bench] 64-structure batch leg ...")
+        out["batch64"] = batch64_leg(lbm, insts)
     if not args.no_warm:
         w = warm_leg()
         if w is not None:

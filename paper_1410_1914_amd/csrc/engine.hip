@@ -528,11 +528,11 @@ struct Engine {
                 if (upload_tables() != hipSuccess) return LBM_ERR_HIP;
             }
             // longer windows while every live instance is slow, but never longer than
-            // an eighth of the steps taken so far, so a stop found at the end of a
-            // window overshoots the first passing check by at most that fraction
+            // 1/32 of the steps taken so far, so a stop found at the end of a window
+            // overshoots the first passing check by at most about 3%
             int64_t taken = std::numeric_limits<int64_t>::max();
             for (int i : live) taken = std::min(taken, rs[i].info.steps);
-            if (!live.empty() && all_slow && (int64_t)K * reps * 2 <= kMaxWindow && (int64_t)K * reps * 16 <= taken)
+            if (!live.empty() && all_slow && (int64_t)K * reps * 2 <= kMaxWindow && (int64_t)K * reps * 64 <= taken)
                 reps *= 2;
         }
         int worst = LBM_OK;

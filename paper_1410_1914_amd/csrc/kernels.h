@@ -46,7 +46,8 @@ struct Lattice {
     const SegRec *rec;        // per segment of every instance
     const float *omega;       // per fluid voxel 1/tau (Knudsen problems), else null
     const InstDev *inst;
-    uint32_t stride;          // elements per population array (7 * stride * 4 < 2^32)
+    uint32_t stride;          // fluid voxels rounded up to 64; a lattice is 7 * stride floats in blocks of
+                              // 7 x 64 (one block per 64 compact voxels), 7 * stride * 4 < 2^32
 };
 
 struct StepLaunch {

@@ -10,9 +10,12 @@
 //   * A segment record (SegRec) carries the masks and compact prefixes of the four
 //     neighbour rows, so the compact index of the +-y / +-z neighbour is the same
 //     mbcnt on that row's mask: no per-voxel neighbour table exists.
-//   * Populations are SoA: f[i * stride + j], i = rest, +x, -x, +y, -y, +z, -z, stored
-//     post-collision as g_i = f_i - w_i c_sh(x), c_sh the linear empty-box profile
-//     (a constant for the reactive problem).  The shift is exact; it keeps the stored
+//   * Populations are blocked by 64 compact voxels: f[(j / 64) * 448 + i * 64 + j % 64],
+//     i = rest, +x, -x, +y, -y, +z, -z, so one block (1792 bytes) holds the seven
+//     populations of 64 consecutive fluid voxels and a wave's own loads and stores
+//     stay inside one or two DRAM pages.  They are stored post-collision as
+//     g_i = f_i - w_i c_sh(x), c_sh the linear empty-box profile (a constant for the
+//     reactive problem).  The shift is exact; it keeps the stored
 //     values small so FP32 storage resolves the fluxes.
 //   * Arithmetic is FP64: the seven FP32 loads are summed exactly, and each stored
 //     value carries a single rounding, so rounding does not bias the mass balance.
@@ -73,6 +76,10 @@ __device__ __forceinline__ int react_n(const SegRec &R, int lane) {
     return bit(R.n0, lane) + 2 * bit(R.n1, lane) + 4 * bit(R.n2, lane);
 }
 
+// Element and byte offsets of population i of compact voxel j in the blocked layout.
+__device__ __forceinline__ int64_t pidx(int i, int64_t j) { return (j >> 6) * 448 + i * 64 + (j & 63); }
+__device__ __forceinline__ uint32_t pbyte(uint32_t j) { return 4u * (448u * (j >> 6) + (j & 63u)); }
+
 // Byte offset past every buffer: a lane with nothing to do loads 0 from here.
 constexpr uint32_t kOutOfRange = 0xFFFFFFF0u;
 
@@ -80,15 +87,16 @@ constexpr uint32_t kOutOfRange = 0xFFFFFFF0u;
 // voxel's own opposite one) and the relaxation rate, issued without waiting.
 template <bool KNUDSEN>
 __device__ __forceinline__ void gather(const SegRec &R, __amdgpu_buffer_rsrc_t rin, __amdgpu_buffer_rsrc_t rom,
-                                       uint32_t S4, int lane, bool act, float (&r)[8], uint32_t &j4) {
+                                       bool act, float (&r)[8], uint32_t &j4) {
     const uint32_t j = R.pre + (uint32_t)mbcnt64(R.m);
-    j4 = act ? 4u * j : kOutOfRange;
-    const uint32_t o1 = lane_sel(R.left, 1u * S4 + j4 - 4u, 2u * S4 + j4);
-    const uint32_t o2 = lane_sel(R.right, 2u * S4 + j4 + 4u, 1u * S4 + j4);
-    const uint32_t o3 = lane_sel(R.nb[0], 3u * S4 + 4u * (R.pnb[0] + (uint32_t)mbcnt64(R.nb[0])), 4u * S4 + j4);
-    const uint32_t o4 = lane_sel(R.nb[1], 4u * S4 + 4u * (R.pnb[1] + (uint32_t)mbcnt64(R.nb[1])), 3u * S4 + j4);
-    const uint32_t o5 = lane_sel(R.nb[2], 5u * S4 + 4u * (R.pnb[2] + (uint32_t)mbcnt64(R.nb[2])), 6u * S4 + j4);
-    const uint32_t o6 = lane_sel(R.nb[3], 6u * S4 + 4u * (R.pnb[3] + (uint32_t)mbcnt64(R.nb[3])), 5u * S4 + j4);
+    const uint32_t a = pbyte(j);
+    j4 = act ? a : kOutOfRange;
+    const uint32_t o1 = lane_sel(R.left, pbyte(j - 1u) + 256u, a + 512u);
+    const uint32_t o2 = lane_sel(R.right, pbyte(j + 1u) + 512u, a + 256u);
+    const uint32_t o3 = lane_sel(R.nb[0], pbyte(R.pnb[0] + (uint32_t)mbcnt64(R.nb[0])) + 768u, a + 1024u);
+    const uint32_t o4 = lane_sel(R.nb[1], pbyte(R.pnb[1] + (uint32_t)mbcnt64(R.nb[1])) + 1024u, a + 768u);
+    const uint32_t o5 = lane_sel(R.nb[2], pbyte(R.pnb[2] + (uint32_t)mbcnt64(R.nb[2])) + 1280u, a + 1536u);
+    const uint32_t o6 = lane_sel(R.nb[3], pbyte(R.pnb[3] + (uint32_t)mbcnt64(R.nb[3])) + 1536u, a + 1280u);
     r[0] = ld(rin, j4, 0);
     r[1] = ld(rin, act ? o1 : kOutOfRange, 0);
     r[2] = ld(rin, act ? o2 : kOutOfRange, 0);
@@ -96,13 +104,13 @@ __device__ __forceinline__ void gather(const SegRec &R, __amdgpu_buffer_rsrc_t r
     r[4] = ld(rin, act ? o4 : kOutOfRange, 0);
     r[5] = ld(rin, act ? o5 : kOutOfRange, 0);
     r[6] = ld(rin, act ? o6 : kOutOfRange, 0);
-    if (KNUDSEN) r[7] = ld(rom, j4, 0);
+    if (KNUDSEN) r[7] = ld(rom, act ? 4u * j : kOutOfRange, 0);
 }
 
 // Collide phase of one segment: FP64 collision with the sink, seven FP32 stores.
 template <bool KNUDSEN, bool REACT>
 __device__ __forceinline__ void collide_store(const SegRec &R, const InstDev &I, __amdgpu_buffer_rsrc_t rout,
-                                              uint32_t S4, int lane, const float (&r)[8], uint32_t j4) {
+                                              int lane, const float (&r)[8], uint32_t j4) {
     const int x = (int)R.s * 64 + lane;
     double om;
     if (KNUDSEN)
@@ -126,13 +134,13 @@ __device__ __forceinline__ void collide_store(const SegRec &R, const InstDev &I,
         s1 = I.w1 * sink;
     }
     const double e0 = I.w0 * Cs, e1 = I.w1 * Cs;
-    st((float)(fma(om, e0 - p0, p0) + s0), rout, j4, 0);
-    st((float)(fma(om, e1 - p1, p1) + s1), rout, j4, 1u * S4);
-    st((float)(fma(om, e1 - p2, p2) + s1), rout, j4, 2u * S4);
-    st((float)(fma(om, e1 - p3, p3) + s1), rout, j4, 3u * S4);
-    st((float)(fma(om, e1 - p4, p4) + s1), rout, j4, 4u * S4);
-    st((float)(fma(om, e1 - p5, p5) + s1), rout, j4, 5u * S4);
-    st((float)(fma(om, e1 - p6, p6) + s1), rout, j4, 6u * S4);
+    st((float)(fma(om, e0 - p0, p0) + s0), rout, j4, 0u);
+    st((float)(fma(om, e1 - p1, p1) + s1), rout, j4, 256u);
+    st((float)(fma(om, e1 - p2, p2) + s1), rout, j4, 512u);
+    st((float)(fma(om, e1 - p3, p3) + s1), rout, j4, 768u);
+    st((float)(fma(om, e1 - p4, p4) + s1), rout, j4, 1024u);
+    st((float)(fma(om, e1 - p5, p5) + s1), rout, j4, 1280u);
+    st((float)(fma(om, e1 - p6, p6) + s1), rout, j4, 1536u);
 }
 
 // Fused pull stream + collide.  Each wave takes SPW consecutive list entries (row
@@ -157,13 +165,13 @@ __global__ __launch_bounds__(WAVES * 64) void k_step(Lattice L, StepLaunch S, co
         const bool valid = base + k < S.nent;  // wave-uniform
         R[k] = &L.rec[S.list[valid ? base + k : 0]];
         act[k] = valid && bit(R[k]->m, lane);
-        gather<KNUDSEN>(*R[k], rin, rom, S4, lane, act[k], r[k], j4[k]);
+        gather<KNUDSEN>(*R[k], rin, rom, act[k], r[k], j4[k]);
     }
 #pragma unroll
     for (int k = 0; k < SPW; ++k) {
         if (act[k]) {
             const InstDev &I = L.inst[SINGLE ? 0 : R[k]->inst];
-            collide_store<KNUDSEN, REACT>(*R[k], I, rout, S4, lane, r[k], j4[k]);
+            collide_store<KNUDSEN, REACT>(*R[k], I, rout, lane, r[k], j4[k]);
         }
     }
 }
@@ -192,7 +200,6 @@ __global__ __launch_bounds__(kMeasWaves * 64) void k_measure(Lattice L, MeasureL
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int4 t = M.blk[blockIdx.x];
     const InstDev &I = L.inst[t.x];
-    const int64_t S = L.stride;
     double acc[NQ];
 #pragma unroll
     for (int i = 0; i < NQ; ++i) acc[i] = 0.0;
@@ -205,15 +212,15 @@ __global__ __launch_bounds__(kMeasWaves * 64) void k_measure(Lattice L, MeasureL
         const int x = (int)R.s * 64 + lane;
         double cs = 0.0;
 #pragma unroll
-        for (int i = 0; i < 7; ++i) cs += (double)f[i * S + j];
+        for (int i = 0; i < 7; ++i) cs += (double)f[pidx(i, j)];
         const double kn = REACT ? I.k * react_n(R, lane) : 0.0;
         const double C = (cs + (I.sh0 - I.slope * (double)x)) / (1.0 - kn);
         acc[Q_MASS] += C;
         acc[Q_RATE] += kn * C;
-        if (x == 0) acc[Q_JIN] += I.abb_in - 2.0 * (double)f[2 * S + j];
-        if (!REACT && x == I.nx - 1) acc[Q_JOUT] += 2.0 * (double)f[1 * S + j] - I.abb_out;
+        if (x == 0) acc[Q_JIN] += I.abb_in - 2.0 * (double)f[pidx(2, j)];
+        if (!REACT && x == I.nx - 1) acc[Q_JOUT] += 2.0 * (double)f[pidx(1, j)] - I.abb_out;
         // link flux f*_{+x}(x) - f*_{-x}(x+1); the shifts differ by w1 * slope
-        if (bit(R.right, lane)) acc[Q_JINT] += (double)f[1 * S + j] - (double)f[2 * S + j + 1] + I.pull_dx;
+        if (bit(R.right, lane)) acc[Q_JINT] += (double)f[pidx(1, j)] - (double)f[pidx(2, j + 1)] + I.pull_dx;
         const double dc = fabs(C - (double)M.csnap[j]);
         acc[Q_DCMAX] = fmax(acc[Q_DCMAX], dc);
         acc[Q_CMAX] = fmax(acc[Q_CMAX], fabs(C));
@@ -284,8 +291,8 @@ __global__ __launch_bounds__(256) void k_init_eq(Lattice L, const int2 *blk, int
         const double kn = react ? I.k * n : 0.0;
         const int x = (int)(v % I.nx);
         const double post = C * (1.0 - kn) - (I.sh0 - I.slope * x);  // equilibrium after the sink, shifted
-        f[j] = (float)(I.w0 * post);
-        for (int i = 1; i < 7; ++i) f[i * (int64_t)L.stride + j] = (float)(I.w1 * post);
+        f[pidx(0, j)] = (float)(I.w0 * post);
+        for (int i = 1; i < 7; ++i) f[pidx(i, j)] = (float)(I.w1 * post);
         csnap[j] = (float)C;
     });
 }
@@ -296,8 +303,8 @@ __global__ __launch_bounds__(256) void k_set_pop(Lattice L, const int2 *blk, con
         if (j < 0) return;
         const int64_t d = dbase[inst] + v;
         const double sh = I.sh0 - I.slope * (double)(v % I.nx);
-        f[j] = (float)((double)fd[d] - I.w0 * sh);
-        for (int i = 1; i < 7; ++i) f[i * (int64_t)L.stride + j] = (float)((double)fd[i * dstride + d] - I.w1 * sh);
+        f[pidx(0, j)] = (float)((double)fd[d] - I.w0 * sh);
+        for (int i = 1; i < 7; ++i) f[pidx(i, j)] = (float)((double)fd[i * dstride + d] - I.w1 * sh);
     });
 }
 
@@ -308,7 +315,7 @@ __global__ __launch_bounds__(256) void k_get_pop(Lattice L, const int2 *blk, con
         const double sh = I.sh0 - I.slope * (double)(v % I.nx);
         for (int i = 0; i < 7; ++i) {
             const double w = i == 0 ? I.w0 : I.w1;
-            fd[i * dstride + d] = j < 0 ? 0.f : (float)((double)f[i * (int64_t)L.stride + j] + w * sh);
+            fd[i * dstride + d] = j < 0 ? 0.f : (float)((double)f[pidx(i, j)] + w * sh);
         }
     });
 }
@@ -319,7 +326,7 @@ __global__ __launch_bounds__(256) void k_conc(Lattice L, const int2 *blk, int re
         float out = 0.f;
         if (j >= 0) {
             double cs = 0.0;
-            for (int i = 0; i < 7; ++i) cs += (double)f[i * (int64_t)L.stride + j];
+            for (int i = 0; i < 7; ++i) cs += (double)f[pidx(i, j)];
             const double kn = react ? I.k * n : 0.0;
             out = (float)((cs + (I.sh0 - I.slope * (double)(v % I.nx))) / (1.0 - kn));
         }

@@ -229,14 +229,15 @@ def npmc_cl(seed: int, n: int = 256, carbon_final: float = 0.45, ionomer: float 
 
 
 def batch_instances(master_seed: int = 2024, count: int = 64, edges=(48, 64, 96, 128, 160),
-                    porosity=(0.3, 0.7), k_range=(1e-4, 1e-1), max_edge=None):
+                    porosity=(0.3, 0.7), k_range=(1e-4, 1e-1), max_edge=None, first: int = 0):
     """Uneven batch of Pt-CL-like structures: edge uniform over ``edges``, porosity
     uniform, carbon:ionomer = 0.35:0.20 of the non-pore volume, Pt on 10% of the
     carbon-pore faces, first-order rate k log-uniform over ``k_range`` (lattice
     units).  Instance i uses seed master_seed*1000 + i; unusable draws (no x-spanning
-    transport path) are resampled with the next attempt number."""
+    transport path) are resampled with the next attempt number.  Instances first ..
+    first + count - 1 are made (each depends on its index only)."""
     out = []
-    for i in range(count):
+    for i in range(first, first + count):
         rng = np.random.default_rng([master_seed, i])
         attempt = 0
         while True:
