@@ -122,6 +122,17 @@ int unet_log_map(const float *src, float *dst, int64_t n, float eps, int32_t inv
 int unet_start_field(const float *y, const uint8_t *depth, int32_t depth_max, float eps, float cmax, float *c,
                      int64_t n, void *stream);
 
+/* Corrector target of the effective-diffusivity problem (Dirichlet c_in at the
+ * face x = -1/2, c_out at x = nx - 1/2; Section 3.5.1, Eq. 19), elementwise over a dense
+ * grid with x fastest (nvox a multiple of nx).  With lin(x) = c_in + (c_out - c_in)
+ * (x + 1/2) / nx and s = nx / (c_in - c_out):
+ *   inverse == 0: dst = s (src - lin(x));  inverse != 0: dst = min(cmax, max(0, lin(x) + src / s)).
+ * The corrector of a statistically uniform structure depends on the local structure
+ * only, not on the domain length, so a network trained on short domains predicts it
+ * on long ones.  c_in != c_out, cmax > 0. */
+int unet_corrector_map(const float *src, float *dst, int64_t nvox, int32_t nx, float c_in, float c_out,
+                       int32_t inverse, float cmax, void *stream);
+
 /* Lane-layout self check of the MFMA builtin: a = A (16x32, row major FP32),
  * b = B (32x16); writes D = A B through the kernels' fragment mapping into d
  * (16x16).  Used by the tests to pin the mapping on the device. */

@@ -369,6 +369,18 @@ __global__ void k_start_field(const float *y, const uint8_t *depth, int depth_ma
     c[i] = (int)depth[i] <= depth_max ? fminf(cmax, fmaxf(0.f, expf(y[i]) - eps)) : 0.f;
 }
 
+// corrector of the effective-diffusivity problem: the field minus the linear profile
+// between the two Dirichlet faces, in units of the mean gradient (or its inverse)
+__global__ void k_corrector(const float *src, float *dst, int64_t n, int nx, float c_in, float c_out, int inverse,
+                            float cmax) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float x = (float)(i % nx);
+    const float lin = c_in + (c_out - c_in) * (x + 0.5f) / (float)nx;
+    const float scale = (float)nx / (c_in - c_out);
+    dst[i] = inverse ? fminf(cmax, fmaxf(0.f, lin + src[i] / scale)) : (src[i] - lin) * scale;
+}
+
 // D = A B (16x32 by 32x16) through the conv kernel's fragment mapping
 __global__ void k_mfma_selftest(const float *a, const float *b, float *d) {
     const int lane = threadIdx.x;
@@ -564,6 +576,15 @@ int unet_start_field(const float *y, const uint8_t *depth, int32_t depth_max, fl
     (void)hipGetLastError();
     hipLaunchKernelGGL(k_start_field, grid1(n), dim3(256), 0, static_cast<hipStream_t>(stream), y, depth, depth_max,
                        eps, cmax, c, n);
+    return status(hipGetLastError());
+}
+
+int unet_corrector_map(const float *src, float *dst, int64_t nvox, int32_t nx, float c_in, float c_out,
+                       int32_t inverse, float cmax, void *stream) {
+    if (!src || !dst || nvox <= 0 || nx <= 0 || nvox % nx || !(c_in != c_out) || !(cmax > 0.f)) return -1;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_corrector, grid1(nvox), dim3(256), 0, static_cast<hipStream_t>(stream), src, dst, nvox, nx,
+                       c_in, c_out, inverse ? 1 : 0, cmax);
     return status(hipGetLastError());
 }
 

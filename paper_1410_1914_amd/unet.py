@@ -39,6 +39,7 @@ SIGNATURES = {
     "unet_zero": ([_P, _i64, _P], _i32),
     "unet_log_map": ([_P, _P, _i64, _f32, _i32, _f32, _P], _i32),
     "unet_start_field": ([_P, _P, _i32, _f32, _f32, _P, _i64, _P], _i32),
+    "unet_corrector_map": ([_P, _P, _i64, _i32, _f32, _f32, _i32, _f32, _P], _i32),
     "unet_features": ([_P, _P, _P, _f32, _P, _P, _f32, _f32, _i32, _i32, _i32, _P], _i32),
     "unet_mfma_selftest": ([_P, _P, _P, _P], _i32),
 }
@@ -158,6 +159,10 @@ def unet_start_field(y, depth, depth_max, eps, cmax, c, n):
     _call("unet_start_field", _ptr(y), _ptr(depth), depth_max, eps, cmax, _ptr(c), n, _stream())
 
 
+def unet_corrector_map(src, dst, nvox, nx, c_in, c_out, inverse, cmax=2.0):
+    _call("unet_corrector_map", _ptr(src), _ptr(dst), nvox, nx, c_in, c_out, 1 if inverse else 0, cmax, _stream())
+
+
 def unet_mfma_selftest(a, b, d):
     _call("unet_mfma_selftest", _ptr(a), _ptr(b), _ptr(d), _stream())
 
@@ -175,6 +180,15 @@ def layer_specs():
             ("e3a", c2, c3), ("e3b", c3, c3), ("b4a", c3, c4), ("b4b", c4, c4),
             ("d3a", c4 + c3, c3), ("d3b", c3, c3), ("d2a", c3 + c2, c2), ("d2b", c2, c2),
             ("d1a", c2 + c1, c1), ("d1b", c1, c1)]
+
+
+def conv_flops(shape):
+    """Multiply-add flops (2 per MAC) of the 3x3x3 convolutions of one forward pass
+    on a (nz, ny, nx) grid; the backward pass costs about twice that (data and
+    weight gradients)."""
+    level = {"e1": 0, "d1": 0, "e2": 1, "d2": 1, "e3": 2, "d3": 2, "b4": 3}
+    vox = [int(np.prod([s // (2 ** l) for s in shape])) for l in range(4)]
+    return sum(2 * 27 * cin * cout * vox[level[name[:2]]] for name, cin, cout in layer_specs())
 
 
 class UNet:

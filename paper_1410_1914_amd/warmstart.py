@@ -1,31 +1,38 @@
-"""Learned warm start for the reactive catalyst-layer problem.
+"""Learned warm start for the catalyst-layer solves.
 
-Workload: four-phase Pt catalyst layers (carbon + Pt 0.35, ionomer 0.20, Pt on 10%
-of the carbon-pore faces, pores 0.45) at 2 nm voxels, reactive problem of Chen et
-al. (arXiv 1410.1914, Section 3.5.2: inlet reservoir plane, Dirichlet inlet,
-zero-gradient outlet, periodic y and z) with Knudsen pore diffusivity, ionomer
-D = 1e-3 D0 and a first-order sink k = 1e-2 (lattice units) per Pt face.
-Structures are 95 voxels long in x so that the simulated grid (with the reservoir
-plane) is a multiple of 8 for the network's three poolings.
+The structures are four-phase Pt catalyst layers at 2 nm voxels: carbon + Pt 0.35,
+ionomer 0.20, Pt on 10% of the carbon-pore faces, pores 0.45. The problems use
+Knudsen pore diffusivity and ionomer D = 1e-3 D0 (Chen et al., arXiv 1410.1914,
+Sections 3.4-3.5). There are two workloads, each with its own network:
+
+* ``react``: the reactive problem of Section 3.5.2, with a first-order sink
+  k = 1e-2 (lattice units) per Pt face. Its boundaries are the inlet reservoir
+  plane, Dirichlet inlet, zero-gradient outlet, and periodic y and z. Structures
+  are 95 voxels long in x, so the simulated grid, reservoir plane included, is a
+  multiple of 8 for the network's three poolings. The network predicts
+  ln(C + 1e-3), so its error is relative to C.
+* ``deff``: the effective-diffusivity problem of Section 3.5.1 (Eq. 19), Dirichlet
+  C = 1 and C = 0 at the x faces. The network predicts the corrector
+  N_x (C - linear profile). For a statistically uniform structure that field
+  depends on the local structure only, so training on 64^3 transfers to 192^3.
 
 Pipeline:
-  1. training fields: the batched HIP solver's steady states on seeded structures;
-  2. training: the U-Net of ``unet.py`` on the GPU with the project's own kernels.
-     The target is ln(C + 1e-3), so the error is relative to C, and the masked
-     MSE weighs a voxel by sqrt(D_ref / D) (capped), so slowly relaxing ionomer
-     counts more;
-  3. use: features of a new structure -> predicted concentration, kept where the
-     pore depth (lbm_get_pore_depth) is at most DEPTH_MAX and C = 0 deeper in ->
-     equilibrium populations (``lbm_set_initial_concentration``) -> the solver
-     refines to its own stop rule.  If the windowed residual rises between the
-     first two checks the solve falls back to the cold start, so the network can
-     never change the answer, only the number of steps.
+  1. Training fields are the batched HIP solver's steady states on seeded structures.
+  2. The U-Net of ``unet.py`` trains on the GPU with the project's own kernels. The
+     loss is a masked MSE weighted by sqrt(D_ref / D) (capped), so slowly relaxing
+     ionomer counts more.
+  3. To use it: features of a new structure -> predicted field -> equilibrium
+     populations (``lbm_set_initial_concentration``) -> the solver refines to its own
+     stop rule. If the windowed residual rises between the first two checks, the
+     solve falls back to the cold start. The network can never change the answer,
+     only the number of steps.
 
-Why the depth mask: the steps a solve needs are set by the voxels that relax
-slowest, which are ionomer films and blobs (D = 1e-3 D0, tau close to 1/2).  Their
-concentration is small, so the cold start's error there is already small, and a
-prediction only helps where its error is smaller still; deep inside the ionomer
-(beyond DEPTH_MAX voxels from the connected pores) the trained network's is not.
+In the reactive problem, the steps a solve needs are set by the voxels that relax
+slowest: ionomer films and blobs (D = 1e-3 D0, tau close to 1/2). Their
+concentration is small, so the cold start's error there is already small. A
+prediction only helps where its error is smaller still. Deep inside the ionomer,
+beyond ``depth_max`` voxels from the connected pores (lbm_get_pore_depth), the
+trained network's error is not smaller, and the start keeps C = 0 there.
 """
 from __future__ import annotations
 
@@ -33,27 +40,49 @@ import json
 import os
 import sys
 import time
+from dataclasses import dataclass
 
 import numpy as np
 
 from . import lbm, unet
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-WEIGHTS = os.path.join(HERE, "weights", "unet_react_ptcl.npz")
-K_LAT = 1e-2
 VOXEL_M = 2e-9
-TRAIN_SHAPE = (96, 96, 95)    # structure (nz, ny, nx); simulated grid (96, 96, 96)
-TEST_SHAPE = (192, 192, 191)  # simulated grid (192, 192, 192)
 WEIGHT_POWER = 0.5
 WEIGHT_CAP = 32.0
-TARGET_EPS = 1e-3   # the network predicts ln(C + TARGET_EPS)
-DEPTH_MAX = 4       # the prediction is used up to this pore depth; C = 0 (cold) deeper in (chosen on
-                    # validation structures, seeds 30000 and 30001)
 C_MAX = 1.5         # upper clip of a predicted start (the discrete field may exceed C_in slightly)
 
 
-def params(**kw):
-    p = lbm.lbm_params_default(mode=lbm.MODE_REACT, knudsen=1, k_lat=K_LAT, check_every=200)
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    mode: int
+    k_lat: float
+    train_shape: tuple    # structure (nz, ny, nx)
+    test_shape: tuple
+    target: str           # "log": ln(C + eps); "corrector": N_x (C - linear profile)
+    target_eps: float = 0.0
+    depth_max: int = -1   # >= 0: keep the prediction up to this pore depth, C = 0 deeper in
+    description: str = ""
+    chunk: int = 0        # > 0: test solves advance in chunks of this many steps, printing progress
+
+    @property
+    def weights(self):
+        return os.path.join(HERE, "weights", f"unet_{self.name}_ptcl.npz")
+
+
+WORKLOADS = {
+    "react": Workload("react", lbm.MODE_REACT, 1e-2, (96, 96, 95), (192, 192, 191), "log", target_eps=1e-3,
+                      # depth limit chosen on validation structures (seeds 30000 and 30001)
+                      depth_max=4,
+                      description="Pt CL reactive, k=1e-2 per Pt face, Knudsen"),
+    "deff": Workload("deff", lbm.MODE_DEFF, 0.0, (64, 64, 64), (192, 192, 192), "corrector",
+                     description="Pt CL effective diffusivity, Knudsen", chunk=400_000),
+}
+
+
+def params(w: Workload, **kw):
+    p = lbm.lbm_params_default(mode=w.mode, knudsen=1, k_lat=w.k_lat, check_every=200)
     for k, v in kw.items():
         setattr(p, k, v)
     return p
@@ -75,48 +104,60 @@ def _structures(seeds, shape, workers=16):
 
 # ------------------------------------------------------------------ features and prediction
 
-def features(active, ncat, omega, tau_ref=1.0):
+def _ncat_input(w: Workload, ncat):
+    # catalyst counts only matter where a sink acts
+    return ncat if w.mode == lbm.MODE_REACT else np.zeros_like(ncat)
+
+
+def features(w: Workload, active, ncat, omega, tau_ref=1.0):
     """BF16 (V, 16) network input from the solver's dense host fields (simulated grid)."""
     import torch
 
     shape = active.shape
     feat = torch.empty((int(np.prod(shape)), unet.IN_CH), dtype=torch.bfloat16, device="cuda")
     a = torch.from_numpy(np.ascontiguousarray(active)).cuda()
-    n = torch.from_numpy(np.ascontiguousarray(ncat)).cuda()
+    n = torch.from_numpy(np.ascontiguousarray(_ncat_input(w, ncat))).cuda()
     o = torch.from_numpy(np.ascontiguousarray(omega)).cuda()
     unet.unet_features(a, n, o, tau_ref, feat, shape)
     return feat, a
 
 
-def predict(net, active, ncat, omega, depth=None, depth_max=DEPTH_MAX):
-    """Start field for the solver (FP32, dense simulated grid, on the GPU): the
-    predicted steady concentration, and, when the pore-depth map is given, the cold
-    value 0 in voxels deeper than depth_max (ionomer interiors relax slowly and hold
-    little oxygen; a wrong guess there costs more steps than C = 0)."""
+def predict(net, w: Workload, active, ncat, omega, depth=None, depth_max=None):
+    """Start field for the solver (FP32, dense simulated grid, on the GPU).
+
+    ``react``: the predicted steady concentration; when the pore-depth map is given,
+    the cold value 0 in voxels deeper than depth_max. ``deff``: the linear profile
+    plus the predicted corrector."""
     import torch
 
-    feat, _ = features(active, ncat, omega)
+    feat, _ = features(w, active, ncat, omega)
     out = net.forward(feat, active.shape)
     c = torch.empty(out.numel(), dtype=torch.float32, device=out.device)
-    if depth is not None:
-        if not net.target_eps > 0:
-            raise ValueError("the depth-masked start needs a log-space network")
+    if w.target == "corrector":
+        p = params(w)
+        unet.unet_corrector_map(out, c, out.numel(), active.shape[2], p.c_in, p.c_out, True, C_MAX)
+    elif depth is not None:
         d = torch.from_numpy(np.ascontiguousarray(depth)).to(out.device)
-        unet.unet_start_field(out, d, depth_max, net.target_eps, C_MAX, c, out.numel())
-    elif net.target_eps > 0:
-        unet.unet_log_map(out, c, out.numel(), net.target_eps, True, C_MAX)
+        dm = w.depth_max if depth_max is None else depth_max
+        unet.unet_start_field(out, d, dm, w.target_eps, C_MAX, c, out.numel())
     else:
-        # linear-output network: the same clip through the map's inverse of ln(C + 1)
-        unet.unet_log_map(out, c, out.numel(), 1.0, False)
-        unet.unet_log_map(c, c, out.numel(), 1.0, True, C_MAX)
+        unet.unet_log_map(out, c, out.numel(), w.target_eps, True, C_MAX)
     return c.view(active.shape)
 
 
 # ------------------------------------------------------------------ solves
 
-def solve(solver, c0=None, fallback=True):
+def _output(solver, w: Workload):
+    if w.mode == lbm.MODE_REACT:
+        return solver.reaction_rate()[1]
+    return solver.deff()[1]
+
+
+def solve(solver, w: Workload, c0=None, fallback=True, chunk=0, log=None):
     """Steady solve from c0 (None: cold start C = 0).  Returns a dict with the steps,
-    wall time, status, reaction rate and whether the cold fallback was taken."""
+    wall time, status, output (reaction rate or D_eff/D0) and whether the cold
+    fallback was taken.  With chunk > 0 the solve runs as successive lbm_advance
+    calls of at most that many steps, each followed by a progress line."""
     import torch
 
     t0 = time.perf_counter()
@@ -132,30 +173,39 @@ def solve(solver, c0=None, fallback=True):
         if st != lbm.OK and i2.residual > i1.residual:
             used_fallback = True
             solver.set_initial_concentration(None)
-    st, info = solver.run_to_steady()
+    if chunk > 0:
+        while True:
+            st, info = solver.advance(chunk)
+            if log:
+                log(f"  ... {info.steps} steps, residual {info.residual:.2e}, estimate {info.est_error:.1e}, "
+                    f"status {st} ({time.perf_counter() - t0:.0f}s)")
+            if st != lbm.NOT_CONVERGED or info.steps >= solver.params.max_steps:
+                break
+    else:
+        st, info = solver.run_to_steady()
     torch.cuda.synchronize()
-    _, rate, jin = solver.reaction_rate()
-    return {"status": st, "steps": int(info.steps), "wall_s": time.perf_counter() - t0, "rate": rate,
+    return {"status": st, "steps": int(info.steps), "wall_s": time.perf_counter() - t0, "out": _output(solver, w),
             "fallback": used_fallback}
 
 
 # ------------------------------------------------------------------ training data
 
-def make_dataset(seeds, shape=TRAIN_SHAPE, batch=32, tol_flux=1e-4, tol_change=1e-8, log=print):
+def make_dataset(w: Workload, seeds, batch=32, tol_flux=1e-4, tol_change=1e-8, log=print):
     """Steady fields of the batched solver.  Returns a list of per-sample dicts of
     GPU tensors (active u8, ncat u8, omega f32, target f32) and host shape."""
     import torch
 
-    phases = _structures(list(seeds), shape)
+    phases = _structures(list(seeds), w.train_shape)
     data = []
     for s0 in range(0, len(phases), batch):
         chunk = phases[s0:s0 + batch]
         t = time.perf_counter()
-        b = lbm.Batch(chunk, [params(tol_flux=tol_flux, tol_change=tol_change) for _ in chunk], voxel_m=VOXEL_M)
+        b = lbm.Batch(chunk, [params(w, tol_flux=tol_flux, tol_change=tol_change) for _ in chunk], voxel_m=VOXEL_M)
         st, infos = b.run()
         for i in range(len(chunk)):
             act, ncat, om = b.host_fields(i)
-            data.append({"active": torch.from_numpy(act).cuda(), "ncat": torch.from_numpy(ncat).cuda(),
+            data.append({"active": torch.from_numpy(act).cuda(),
+                         "ncat": torch.from_numpy(np.ascontiguousarray(_ncat_input(w, ncat))).cuda(),
                          "omega": torch.from_numpy(om).cuda(), "target": b.concentration(i).clone(),
                          "shape": act.shape, "count": int(act.sum()), "steps": int(infos[i].steps)})
         del b
@@ -165,54 +215,21 @@ def make_dataset(seeds, shape=TRAIN_SHAPE, batch=32, tol_flux=1e-4, tol_change=1
     return data
 
 
-def _log_targets(data, eps):
-    """ln(C + eps) of every sample's target (kept with the sample)."""
+def _targets(w: Workload, data):
+    """The network's target of every sample (kept with the sample)."""
     import torch
 
-    key = ("y", eps)
+    p = params(w)
     for d in data:
-        if d.get("y_key") != key:
-            t = d["target"].view(-1)
-            d["y"] = torch.empty_like(t)
-            unet.unet_log_map(t, d["y"], t.numel(), eps, False)
-            d["y_key"] = key
-
-
-def train(net, data, epochs=4, lr=1e-3, log=print, seed=0, weight_power=WEIGHT_POWER, weight_cap=WEIGHT_CAP,
-          target_eps=TARGET_EPS):
-    """Adam on the weighted masked MSE, cosine learning-rate decay; returns the loss
-    history.  The weight of a voxel is (D_ref / D)^weight_power capped at weight_cap: an error
-    left in a low-diffusivity voxel (ionomer) relaxes slowly, so it costs the solver
-    far more steps than the same error in a pore."""
-    import torch
-
-    rng = np.random.default_rng(seed)
-    hist = []
-    total = epochs * len(data)
-    if target_eps > 0:
-        _log_targets(data, target_eps)
-        if net.t == 0:  # start the output bias at the mean log target
-            m = float(np.mean([float(d["y"][d["active"].view(-1) > 0].mean()) for d in data[:32]]))
-            net.B["head"].fill_(m)
-    net.target_eps = target_eps
-    step = 0
-    for ep in range(epochs):
-        order = rng.permutation(len(data))
-        t = time.perf_counter()
-        losses = []
-        for idx in order:
-            d = data[idx]
-            feat, weight = _features_dev(d, weight_power, weight_cap)
-            lr_t = lr * 0.5 * (1 + np.cos(np.pi * step / total))
-            tgt = d["y"] if target_eps > 0 else d["target"].view(-1)
-            loss = net.train_step(feat, d["shape"], tgt, d["active"].view(-1), d["count"], lr_t, weight)
-            losses.append(loss.clone())
-            step += 1
-        torch.cuda.synchronize()
-        ep_loss = float(torch.stack(losses).mean().cpu()) if losses else float("nan")
-        hist.append(ep_loss)
-        log(f"[train] epoch {ep + 1}/{epochs}: mean loss {ep_loss:.3e} ({time.perf_counter() - t:.1f}s)")
-    return hist
+        if d.get("y_key") == w.name:
+            continue
+        t = d["target"].view(-1)
+        d["y"] = torch.empty_like(t)
+        if w.target == "log":
+            unet.unet_log_map(t, d["y"], t.numel(), w.target_eps, False)
+        else:
+            unet.unet_corrector_map(t, d["y"], t.numel(), d["shape"][2], p.c_in, p.c_out, False)
+        d["y_key"] = w.name
 
 
 def _features_dev(d, weight_power=WEIGHT_POWER, weight_cap=WEIGHT_CAP):
@@ -226,6 +243,41 @@ def _features_dev(d, weight_power=WEIGHT_POWER, weight_cap=WEIGHT_CAP):
     return feat, weight
 
 
+def train(net, w: Workload, data, epochs=4, lr=1e-3, log=print, seed=0, weight_power=WEIGHT_POWER,
+          weight_cap=WEIGHT_CAP):
+    """Adam on the weighted masked MSE, cosine learning-rate decay; returns the loss
+    history.  The weight of a voxel is (D_ref / D)^weight_power capped at weight_cap:
+    an error left in a low-diffusivity voxel (ionomer) relaxes slowly, so it costs
+    the solver far more steps than the same error in a pore."""
+    import torch
+
+    rng = np.random.default_rng(seed)
+    hist = []
+    total = epochs * len(data)
+    _targets(w, data)
+    if net.t == 0:  # start the output bias at the mean target
+        m = float(np.mean([float(d["y"][d["active"].view(-1) > 0].mean()) for d in data[:32]]))
+        net.B["head"].fill_(m)
+    net.target_eps = w.target_eps
+    step = 0
+    for ep in range(epochs):
+        order = rng.permutation(len(data))
+        t = time.perf_counter()
+        losses = []
+        for idx in order:
+            d = data[idx]
+            feat, weight = _features_dev(d, weight_power, weight_cap)
+            lr_t = lr * 0.5 * (1 + np.cos(np.pi * step / total))
+            loss = net.train_step(feat, d["shape"], d["y"], d["active"].view(-1), d["count"], lr_t, weight)
+            losses.append(loss.clone())
+            step += 1
+        torch.cuda.synchronize()
+        ep_loss = float(torch.stack(losses).mean().cpu()) if losses else float("nan")
+        hist.append(ep_loss)
+        log(f"[train] epoch {ep + 1}/{epochs}: mean loss {ep_loss:.3e} ({time.perf_counter() - t:.1f}s)")
+    return hist
+
+
 # ------------------------------------------------------------------ evaluation
 
 def linear_profile(shape, c_in=1.0):
@@ -237,50 +289,57 @@ def linear_profile(shape, c_in=1.0):
     return prof.expand(shape).contiguous()
 
 
-def compare(net, seeds, shape=TEST_SHAPE, log=print):
+def compare(net, w: Workload, seeds, shape=None, log=print, unmasked=True):
     """Cold start (C = 0), linear-profile start and learned start on fresh
-    structures: steps, wall time (inference included) and converged rate."""
+    structures: steps, wall time (inference included) and converged output."""
     import torch
 
+    shape = shape or w.test_shape
     phases = [structure(s, shape) for s in seeds]
     rows = []
     for seed, ph in zip(seeds, phases):
-        s = lbm.Solver(ph, params(), voxel_m=VOXEL_M)
+        s = lbm.Solver(ph, params(w), voxel_m=VOXEL_M)
         act, ncat, om = s.host_fields()
-        cold = solve(s, None)
-        lin = solve(s, linear_profile(act.shape))
-        unmasked = solve(s, predict(net, act, ncat, om))
+        kw = dict(chunk=w.chunk, log=log)
+        cold = solve(s, w, None, **kw)
+        log(f"[warm/{w.name}] seed {seed}: cold start done ({cold['steps']} steps)")
+        lin = solve(s, w, linear_profile(act.shape), **kw)
+        log(f"[warm/{w.name}] seed {seed}: linear-profile start done ({lin['steps']} steps)")
+        row = {"seed": seed, "cold": cold, "linear": lin}
+        if unmasked and w.depth_max >= 0:
+            row["warm_unmasked"] = solve(s, w, predict(net, w, act, ncat, om), **kw)
         t0 = time.perf_counter()
-        depth = s.pore_depth()
-        c0 = predict(net, act, ncat, om, depth)
+        depth = s.pore_depth() if w.depth_max >= 0 else None
+        c0 = predict(net, w, act, ncat, om, depth)
         torch.cuda.synchronize()
         t_inf = time.perf_counter() - t0
-        warm = solve(s, c0)
+        warm = solve(s, w, c0, **kw)
         warm["wall_s"] += t_inf
         warm["inference_s"] = t_inf
-        row = {"seed": seed, "cold": cold, "linear": lin, "warm": warm, "warm_unmasked": unmasked,
-               "rate_rel_diff": abs(warm["rate"] / cold["rate"] - 1)}
+        row["warm"] = warm
+        row["out_rel_diff"] = abs(warm["out"] / cold["out"] - 1)
         rows.append(row)
-        log(f"[warm] seed {seed}: steps cold {cold['steps']} linear {lin['steps']} warm {warm['steps']} "
-            f"(unmasked prediction {unmasked['steps']}) "
-            f"(inference {t_inf * 1e3:.1f} ms); wall cold {cold['wall_s']:.2f}s warm {warm['wall_s']:.2f}s; "
-            f"rate diff {row['rate_rel_diff']:.1e}, fallback {warm['fallback']}")
+        extra = f" (unmasked prediction {row['warm_unmasked']['steps']})" if "warm_unmasked" in row else ""
+        log(f"[warm/{w.name}] seed {seed}: steps cold {cold['steps']} linear {lin['steps']} warm {warm['steps']}"
+            f"{extra} (inference {t_inf * 1e3:.1f} ms); wall cold {cold['wall_s']:.2f}s warm {warm['wall_s']:.2f}s; "
+            f"output diff {row['out_rel_diff']:.1e}, fallback {warm['fallback']}")
         s.close()
+    mean = lambda key, f: float(np.mean([r[key][f] for r in rows]))  # noqa: E731
+    nxs = shape[2] + (1 if w.mode == lbm.MODE_REACT else 0)
     summ = {
-        "workload": f"Pt CL reactive, k={K_LAT}, Knudsen, {shape[0]}x{shape[1]}x{shape[2] + 1} simulated",
+        "workload": f"{w.description}, {shape[0]}x{shape[1]}x{nxs} simulated",
         "seeds": list(seeds),
-        "steps_cold": float(np.mean([r["cold"]["steps"] for r in rows])),
-        "steps_linear": float(np.mean([r["linear"]["steps"] for r in rows])),
-        "steps_warm": float(np.mean([r["warm"]["steps"] for r in rows])),
-        "steps_warm_unmasked": float(np.mean([r["warm_unmasked"]["steps"] for r in rows])),
-        "wall_cold_s": float(np.mean([r["cold"]["wall_s"] for r in rows])),
-        "wall_linear_s": float(np.mean([r["linear"]["wall_s"] for r in rows])),
-        "wall_warm_s": float(np.mean([r["warm"]["wall_s"] for r in rows])),
+        "steps_cold": mean("cold", "steps"), "steps_linear": mean("linear", "steps"),
+        "steps_warm": mean("warm", "steps"),
+        "wall_cold_s": mean("cold", "wall_s"), "wall_linear_s": mean("linear", "wall_s"),
+        "wall_warm_s": mean("warm", "wall_s"),
         "inference_ms": float(np.mean([r["warm"]["inference_s"] for r in rows]) * 1e3),
-        "depth_max": DEPTH_MAX,
         "fallbacks": int(sum(r["warm"]["fallback"] for r in rows)),
-        "max_rate_rel_diff": float(max(r["rate_rel_diff"] for r in rows)),
+        "max_output_rel_diff": float(max(r["out_rel_diff"] for r in rows)),
     }
+    if "warm_unmasked" in rows[0]:
+        summ["steps_warm_unmasked"] = mean("warm_unmasked", "steps")
+        summ["depth_max"] = w.depth_max
     summ["speedup_steps"] = summ["steps_cold"] / summ["steps_warm"]
     summ["speedup_wall"] = summ["wall_cold_s"] / summ["wall_warm_s"]
     summ["speedup_steps_vs_linear"] = summ["steps_linear"] / summ["steps_warm"]
@@ -288,49 +347,105 @@ def compare(net, seeds, shape=TEST_SHAPE, log=print):
     return summ
 
 
-def bench_warm_vs_cold(seeds=(20000, 20001), shape=TEST_SHAPE):
-    """Leg of bench.py: needs the trained weights."""
-    if not os.path.exists(WEIGHTS):
-        return None
-    net = unet.UNet.from_file(WEIGHTS)
-    return compare(net, seeds, shape, log=lambda *a: print(*a, file=sys.stderr, flush=True))
+def bench_warm_vs_cold(names=("react", "deff"), seeds=(20000, 20001)):
+    """Leg of bench.py: every workload whose trained weights are present."""
+    out = {}
+    for name in names:
+        w = WORKLOADS[name]
+        if not os.path.exists(w.weights):
+            continue
+        net = unet.UNet.from_file(w.weights)
+        out[name] = compare(net, w, seeds, log=lambda *a: print(*a, file=sys.stderr, flush=True), unmasked=False)
+    return out or None
+
+
+def time_network(w: Workload, reps=10, log=print):
+    """Times inference on the test grid and one training step on the training grid
+    (HIP events on the network's stream); returns ms and achieved TFLOP/s."""
+    import torch
+
+    ph = structure(20000, w.test_shape)
+    s = lbm.Solver(ph, params(w), voxel_m=VOXEL_M)
+    act, ncat, om = s.host_fields()
+    net = unet.UNet.from_file(w.weights) if os.path.exists(w.weights) else unet.UNet(seed=0)
+    feat, _ = features(w, act, ncat, om)
+    shape = act.shape
+    net.forward(feat, shape)  # buffers and first touch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        net.forward(feat, shape)
+    e1.record()
+    e1.synchronize()
+    inf_ms = e0.elapsed_time(e1) / reps
+    tf = unet.conv_flops(shape)
+    # one training step on the training grid, random target (timing only)
+    s.close()
+    pt = structure(10000, w.train_shape)
+    st = lbm.Solver(pt, params(w), voxel_m=VOXEL_M)
+    a2, n2, o2 = st.host_fields()
+    d = {"active": torch.from_numpy(a2).cuda(), "ncat": torch.from_numpy(_ncat_input(w, n2)).cuda(),
+         "omega": torch.from_numpy(o2).cuda(), "shape": a2.shape, "count": int(a2.sum())}
+    f2, wt = _features_dev(d)
+    tgt = torch.rand(int(np.prod(a2.shape)), dtype=torch.float32, device="cuda")
+    trainer = unet.UNet(seed=1)
+    trainer.train_step(f2, a2.shape, tgt, d["active"].view(-1), d["count"], 1e-4, wt)
+    e0.record()
+    for _ in range(reps):
+        trainer.train_step(f2, a2.shape, tgt, d["active"].view(-1), d["count"], 1e-4, wt)
+    e1.record()
+    e1.synchronize()
+    tr_ms = e0.elapsed_time(e1) / reps
+    tt = 3 * unet.conv_flops(a2.shape)
+    res = {"inference_grid": list(shape), "inference_ms": inf_ms, "inference_conv_tflop": tf / 1e12,
+           "inference_tflops": tf / inf_ms / 1e9, "train_grid": list(a2.shape), "train_step_ms": tr_ms,
+           "train_step_tflops_approx": tt / tr_ms / 1e9, "peak_bf16_tflops": 2500.0}
+    log(json.dumps(res))
+    return res
 
 
 def main(argv):
-    """python -m paper_1410_1914_amd.warmstart train [n_samples] [epochs]"""
+    """python -m paper_1410_1914_amd.warmstart train <react|deff> [n_samples] [epochs]
+    python -m paper_1410_1914_amd.warmstart eval <react|deff> [seed ...]
+    python -m paper_1410_1914_amd.warmstart time <react|deff>"""
     import torch
 
-    if len(argv) < 1 or argv[0] not in ("train", "eval"):
+    if len(argv) < 2 or argv[0] not in ("train", "eval", "time") or argv[1] not in WORKLOADS:
         print(main.__doc__)
         return 2
+    w = WORKLOADS[argv[1]]
     log = lambda *a: print(*a, flush=True)  # noqa: E731
     if argv[0] == "train":
-        n = int(argv[1]) if len(argv) > 1 else 512
-        epochs = int(argv[2]) if len(argv) > 2 else 4
+        n = int(argv[2]) if len(argv) > 2 else 512
+        epochs = int(argv[3]) if len(argv) > 3 else 8
         seeds = range(10000, 10000 + n)
-        phases_first = _structures([10000], TRAIN_SHAPE)  # warm the process pool before CUDA
-        del phases_first
+        _structures([10000], w.train_shape)  # start the process pool before the GPU is touched
         lbm.require_gpu()
         t = time.perf_counter()
-        data = make_dataset(seeds, log=log)
+        data = make_dataset(w, seeds, log=log)
         log(f"[data] {len(data)} fields in {time.perf_counter() - t:.1f}s")
         net = unet.UNet(seed=0)
         t = time.perf_counter()
-        hist = train(net, data, epochs=epochs, log=log)
+        hist = train(net, w, data, epochs=epochs, log=log)
         log(f"[train] {epochs} epochs in {time.perf_counter() - t:.1f}s")
-        os.makedirs(os.path.dirname(WEIGHTS), exist_ok=True)
-        out = os.environ.get("WARMSTART_OUT", WEIGHTS)
+        out = os.environ.get("WARMSTART_OUT", w.weights)
+        os.makedirs(os.path.dirname(out) or ".", exist_ok=True)
         net.save(out)
         del data
         torch.cuda.empty_cache()
-        summ = compare(net, (20000, 20001), log=log)
-        summ["train"] = {"samples": n, "epochs": epochs, "loss_history": hist, "train_shape": TRAIN_SHAPE}
+        summ = compare(net, w, (20000, 20001), log=log)
+        summ["train"] = {"samples": n, "epochs": epochs, "loss_history": hist, "train_shape": w.train_shape}
         log(json.dumps(summ))
         with open(os.path.splitext(out)[0] + ".json", "w") as fh:
             json.dump(summ, fh, indent=1)
-    else:
+    elif argv[0] == "time":
         lbm.require_gpu()
-        log(json.dumps(bench_warm_vs_cold()))
+        time_network(w, log=log)
+    else:
+        seeds = tuple(int(a) for a in argv[2:]) or (20000, 20001)
+        lbm.require_gpu()
+        net = unet.UNet.from_file(w.weights)
+        log(json.dumps(compare(net, w, seeds, log=log)))
     return 0
 
 

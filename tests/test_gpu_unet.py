@@ -319,3 +319,19 @@ def test_start_field_masks_deep_voxels(U):
     y32 = y.astype(np.float32).astype(np.float64)
     want = np.where(depth <= 2, np.clip(np.exp(y32) - 1e-3, 0, 1.2), 0.0)
     assert np.allclose(_host(c), want, rtol=1e-5, atol=1e-6)
+
+
+def test_corrector_map_round_trip(U):
+    import torch
+
+    rng = np.random.default_rng(14)
+    nz, ny, nx = 3, 4, 20
+    c = rng.random((nz, ny, nx)) * 0.9 + 0.05
+    y = torch.zeros(c.size, dtype=torch.float32, device="cuda")
+    U.unet_corrector_map(_dev_f32(c), y, c.size, nx, 1.0, 0.0, False)
+    lin = 1.0 - (np.arange(nx) + 0.5) / nx
+    c32 = c.astype(np.float32).astype(np.float64)
+    assert np.allclose(_host(y).reshape(c.shape), nx * (c32 - lin), rtol=1e-5, atol=1e-5)
+    back = torch.zeros_like(y)
+    U.unet_corrector_map(y, back, c.size, nx, 1.0, 0.0, True, 1.5)
+    assert np.allclose(_host(back).reshape(c.shape), c32, rtol=1e-5, atol=1e-6)
