@@ -17,7 +17,11 @@ Also reported on the same JSON line:
   * solves: solves/s to D_eff on the 32^3 two-phase workload (seeds 1..10),
     sequential single solves vs one batched solve, with the error against the
     stored oracle values;
-  * warm_start: learned warm start vs cold start, when the trained network exists.
+  * warm_start: learned start vs cold start (C = 0) and vs a linear-profile start
+    on fresh 192^3 Pt catalyst layers (reactive problem; ``--warm-deff`` adds the
+    slower effective-diffusivity problem), when the trained networks exist;
+  * batch64 (``--batch64``): 64 uneven reactive structures, one batched solve vs
+    64 sequential single solves.
 """
 from __future__ import annotations
 
@@ -45,6 +49,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-solves", action="store_true", help="skip the 32^3 solves/s legs")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-start leg")
+    ap.add_argument("--warm-deff", action="store_true",
+                    help="also run the effective-diffusivity warm-start comparison (several minutes)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU time budget of the oracle sample")
     ap.add_argument("--no-tune", action="store_true", help="keep the default tiling (no autotuning)")
     ap.add_argument("--batch64", action="store_true",
@@ -274,14 +280,14 @@ def batch64_leg(lbm, insts):
             "status": st, "max_steps": int(max(steps)), "tiling": list(b.tiling())}
 
 
-def warm_leg():
-    try:
-        from paper_1410_1914_amd import warmstart
-    except ImportError:
-        return None
-    if not hasattr(warmstart, "bench_warm_vs_cold"):
-        return None
-    return warmstart.bench_warm_vs_cold()
+def warm_leg(args):
+    """Learned start vs cold start (and vs a linear-profile start) at 192^3: the
+    reactive workload by default; the effective-diffusivity workload, whose cold
+    solve alone takes ~2.5 M steps (minutes), with --warm-deff."""
+    from paper_1410_1914_amd import warmstart
+
+    names = ("react", "deff") if args.warm_deff else ("react",)
+    return warmstart.bench_warm_vs_cold(names)
 
 
 def main():
@@ -338,7 +344,7 @@ def main():
         log("[bench] 64-structure batch leg ...")
         out["batch64"] = batch64_leg(lbm, insts)
     if not args.no_warm:
-        w = warm_leg()
+        w = warm_leg(args)
         if w is not None:
             out["warm_start"] = w
     print(json.dumps(out), flush=True)

@@ -347,15 +347,18 @@ def compare(net, w: Workload, seeds, shape=None, log=print, unmasked=True):
     return summ
 
 
-def bench_warm_vs_cold(names=("react", "deff"), seeds=(20000, 20001)):
-    """Leg of bench.py: every workload whose trained weights are present."""
+def bench_warm_vs_cold(names=("react", "deff")):
+    """Leg of bench.py: every named workload whose trained weights are present (two
+    test structures for the reactive one, one for the slow effective-diffusivity one)."""
+    seeds = {"react": (20000, 20001), "deff": (20000,)}
     out = {}
     for name in names:
         w = WORKLOADS[name]
         if not os.path.exists(w.weights):
             continue
         net = unet.UNet.from_file(w.weights)
-        out[name] = compare(net, w, seeds, log=lambda *a: print(*a, file=sys.stderr, flush=True), unmasked=False)
+        out[name] = compare(net, w, seeds[name], log=lambda *a: print(*a, file=sys.stderr, flush=True),
+                            unmasked=False)
     return out or None
 
 
