@@ -267,7 +267,13 @@ def batch64_leg(lbm, insts):
     t0 = time.perf_counter()
     b = lbm.Batch(phases, params)
     b.autotune(20)
-    st, infos = b.run()
+    while True:  # the batched solve in budgets of 100k steps, with a progress line each
+        st, infos = b.advance(100_000)
+        done = sum(1 for r in infos if r.status != lbm.NOT_CONVERGED)
+        log(f"[bench] batch leg: batched solve at {max(r.steps for r in infos)} steps, {done}/{len(infos)} "
+            f"instances finished ({time.perf_counter() - t0:.0f}s)")
+        if st != lbm.NOT_CONVERGED:
+            break
     batched = [b.reaction_rate(i)[1] for i in range(len(phases))]
     t_batch = time.perf_counter() - t0
     vox = sum(int(ph.size) for ph in phases)

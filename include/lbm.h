@@ -247,6 +247,11 @@ int lbm_batch_get_tiling(const lbm_batch *b, int32_t *segs_per_wave, int32_t *wa
 int lbm_batch_autotune(lbm_batch *b, int32_t steps_per_trial, double *ms_best);
 /* Run all instances to their steady states; infos[n] receives per-instance results. */
 int lbm_batch_run(lbm_batch *b, lbm_run_info *infos);
+/* As lbm_batch_run, but stop once max_new_steps more steps have been taken (check
+ * windows are shortened to fit).  Finished instances stay finished; the others
+ * report LBM_NOT_CONVERGED and continue from where they are on the next call.
+ * Returns the worst status, LBM_NOT_CONVERGED while any instance is running. */
+int lbm_batch_advance(lbm_batch *b, int64_t max_new_steps, lbm_run_info *infos);
 int lbm_batch_deff(const lbm_batch *b, int32_t i, double *deff_over_d0);
 int lbm_batch_reaction_rate(const lbm_batch *b, int32_t i, double *rate_per_area, double *j_in);
 int lbm_batch_get_info(const lbm_batch *b, int32_t i, lbm_info *info);

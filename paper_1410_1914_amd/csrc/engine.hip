@@ -1002,6 +1002,14 @@ int lbm_batch_run(lbm_batch *b, lbm_run_info *infos) {
     LBM_GUARD_END
 }
 
+int lbm_batch_advance(lbm_batch *b, int64_t max_new_steps, lbm_run_info *infos) {
+    LBM_GUARD_BEGIN
+    if (!b || max_new_steps < 0) return LBM_ERR_INVALID_ARG;
+    cl::DeviceGuard dg(b->E->device);
+    return b->E->run(infos, max_new_steps);
+    LBM_GUARD_END
+}
+
 int lbm_batch_deff(const lbm_batch *b, int32_t i, double *out) {
     if (!b || !out || i < 0 || i >= b->E->ninst) return LBM_ERR_INVALID_ARG;
     return b->E->deff(i, out);

@@ -105,6 +105,7 @@ SIGNATURES = {
     "lbm_batch_get_tiling": ([_P, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32), ctypes.POINTER(c_int32)], c_int32),
     "lbm_batch_autotune": ([_P, c_int32, ctypes.POINTER(c_double)], c_int32),
     "lbm_batch_run": ([_P, ctypes.POINTER(lbm_run_info)], c_int32),
+    "lbm_batch_advance": ([_P, c_int64, ctypes.POINTER(lbm_run_info)], c_int32),
     "lbm_batch_deff": ([_P, c_int32, ctypes.POINTER(c_double)], c_int32),
     "lbm_batch_reaction_rate": ([_P, c_int32, ctypes.POINTER(c_double), ctypes.POINTER(c_double)], c_int32),
     "lbm_batch_get_info": ([_P, c_int32, ctypes.POINTER(lbm_info)], c_int32),
@@ -341,6 +342,14 @@ def lbm_batch_run(h, n: int):
     return st, list(infos)
 
 
+def lbm_batch_advance(h, n: int, max_new_steps: int):
+    infos = (lbm_run_info * n)()
+    st = load().lbm_batch_advance(h, max_new_steps, infos)
+    if st < 0 and st != ERR_NO_PERCOLATION:
+        raise LbmError("lbm_batch_advance", st)
+    return st, list(infos)
+
+
 def lbm_batch_deff(h, i: int):
     v = c_double()
     st = load().lbm_batch_deff(h, i, ctypes.byref(v))
@@ -542,6 +551,9 @@ class Batch:
 
     def run(self):
         return lbm_batch_run(self.h, self.n)
+
+    def advance(self, max_new_steps):
+        return lbm_batch_advance(self.h, self.n, max_new_steps)
 
     def deff(self, i):
         return lbm_batch_deff(self.h, i)

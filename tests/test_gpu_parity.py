@@ -184,3 +184,22 @@ def test_batch_matches_single(hip):
         prob = O.prepare(phases[i], O.Params(mode=1, k_lat=ks[i]))
         ref = O.solve_fixed_point(prob)
         assert b.reaction_rate(i)[1] == pytest.approx(ref.rate, rel=STEADY_RTOL)
+
+
+def test_batch_advance_resumes_to_the_same_answer(hip):
+    """A batched solve taken in step budgets finishes every instance with the
+    answer of one uninterrupted batched run."""
+    phases = [sg.pt_cl(30 + i, shape=sh) for i, sh in enumerate([(8, 9, 66), (6, 6, 40)])]
+    mk = lambda: [hip.lbm_params_default(mode=1, k_lat=k, check_every=200) for k in (0.05, 0.01)]  # noqa: E731
+    a = hip.Batch(phases, mk())
+    st, _ = a.run()
+    assert st == 0
+    b = hip.Batch(phases, mk())
+    for _ in range(1000):
+        st, infos = b.advance(3000)
+        assert all(r.steps <= infos[0].steps + 3000 or r.status == 0 for r in infos)
+        if st != hip.NOT_CONVERGED:
+            break
+    assert st == 0
+    for i in range(2):
+        assert b.reaction_rate(i)[1] == pytest.approx(a.reaction_rate(i)[1], rel=1e-5)
