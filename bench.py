@@ -81,18 +81,15 @@ def algorithmic_bytes(info, knudsen: bool, n_listed: int) -> float:
     return info.n_active * per_fluid + n_listed * 124.0
 
 
-def ph_listed(ph, n):
-    """Number of 64-voxel row segments holding at least one simulated voxel (the
-    reactive problem prepends one pore plane, so every row's first segment counts)."""
+def listed_segments(active):
+    """Number of 64-voxel row segments holding at least one simulated voxel: the
+    segments the stream-collide launch visits (one wave each)."""
     import numpy as np
 
-    nz, ny, nx = ph.shape
-    nxs = nx + 1
-    nsx = (nxs + 63) // 64
-    transport = np.isin(ph, (0, 3))
+    nz, ny, nx = active.shape
+    nsx = (nx + 63) // 64
     pad = np.zeros((nz, ny, nsx * 64), bool)
-    pad[:, :, 0] = True
-    pad[:, :, 1:nx + 1] = transport
+    pad[:, :, :nx] = active.astype(bool)
     return int(pad.reshape(nz, ny, nsx, 64).any(axis=3).sum())
 
 
@@ -145,7 +142,7 @@ def headline(args, lbm, structgen):
     updates = info.n_active * launches
     mlups = updates / wall / 1e6
     per_launch_s = kms / 1e3 / launches
-    alg = algorithmic_bytes(info, knudsen=True, n_listed=int((ph_listed(ph, n))))
+    alg = algorithmic_bytes(info, knudsen=True, n_listed=listed_segments(s.host_fields()[0]))
     achieved = alg / per_launch_s / 1e9
     log(f"[bench] {launches} LBM steps in {wall:.3f}s: {mlups:.0f} MLUPS; kernel mean {per_launch_s*1e6:.1f} us, "
         f"{achieved:.0f} GB/s algorithmic")
@@ -253,12 +250,13 @@ def batch64_leg(lbm, insts):
     phases = [d["phase"] for d in insts]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    single, steps = [], []
+    single, steps, updates = [], [], 0
     for ph, p in zip(phases, params):
         s = lbm.Solver(ph, p)
         st, r = s.run_to_steady()
         single.append(s.reaction_rate()[1])
         steps.append(r.steps)
+        updates += r.steps * s.info.n_active
         s.close()
         log(f"[bench] batch leg: single solve {len(single)}/{len(phases)} ({ph.shape[0]}^3, {r.steps} steps, "
             f"status {st})")
@@ -276,6 +274,7 @@ def batch64_leg(lbm, insts):
             break
     batched = [b.reaction_rate(i)[1] for i in range(len(phases))]
     t_batch = time.perf_counter() - t0
+    b_updates = sum(r.steps * b.info(i).n_active for i, r in enumerate(infos))
     vox = sum(int(ph.size) for ph in phases)
     return {"workload": f"{len(phases)} reactive Pt-CL structures, edges in {{48..{max(ph.shape[0] for ph in phases)}}}, "
                         f"porosity 0.3-0.7, k log-uniform 1e-4..1e-1 ({vox / 1e6:.1f} M voxels)",
@@ -283,7 +282,8 @@ def batch64_leg(lbm, insts):
             "batched_solves_per_s": round(len(phases) / t_batch, 3),
             "batched_speedup": round(t_single / t_batch, 2),
             "max_rate_rel_diff": max(abs(a / c - 1) for a, c in zip(batched, single)),
-            "status": st, "max_steps": int(max(steps)), "tiling": list(b.tiling())}
+            "status": st, "max_steps": int(max(steps)), "tiling": list(b.tiling()),
+            "fluid_updates_single": int(updates), "fluid_updates_batched": int(b_updates)}
 
 
 def warm_leg(args):

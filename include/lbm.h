@@ -184,10 +184,11 @@ int lbm_step(lbm_solver *s, int64_t nsteps);
 int lbm_measure(lbm_solver *s, lbm_run_info *info);
 
 /* Step to the steady state.  Checks follow windows of K steps (doubled while the
- * mass still decays by less than half per window); the run stops when the windowed
+ * mass of some live instance still decays by less than half per window); the run stops when the windowed
  * residual, the estimated remaining relative error of the output and of the total
  * mass (geometric extrapolation with the decay rate measured on the mass), and the
- * flux balance are all below their tolerances, or after max_steps.  Returns LBM_OK, LBM_NOT_CONVERGED,
+ * flux balance are all below their tolerances, or after max_steps.  A window
+ * never exceeds 1/32 of the steps already taken.  Returns LBM_OK, LBM_NOT_CONVERGED,
  * LBM_ERR_DIVERGED or LBM_ERR_NO_PERCOLATION (D_eff problems without a path). */
 int lbm_run_to_steady(lbm_solver *s, lbm_run_info *info);
 

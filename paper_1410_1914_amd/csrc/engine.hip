@@ -497,7 +497,7 @@ struct Engine {
             live = still;
             if (upload_tables() != hipSuccess) return LBM_ERR_HIP;
         }
-        int64_t reps = 1;  // window = reps * K steps; doubled while every live instance is slow
+        int64_t reps = 1;  // window = reps * K steps; doubled while a live instance is slow
         while (!live.empty()) {
             const int64_t room = (budget - spent) / K;
             if (room < 1) break;
@@ -514,25 +514,27 @@ struct Engine {
             }
             ev_pending = false;
             std::vector<int> keep;
-            bool all_slow = true;
+            bool any_slow = false;
             for (int i : live) {
                 if (evaluate(i, res_host + (size_t)i * NQ, (int64_t)K * reps)) {
                     rs[i].done = 1;
                 } else {
                     keep.push_back(i);
-                    all_slow = all_slow && rs[i].slow;
+                    any_slow = any_slow || rs[i].slow;
                 }
             }
             if (keep.size() != live.size()) {
                 live = keep;
                 if (upload_tables() != hipSuccess) return LBM_ERR_HIP;
             }
-            // longer windows while every live instance is slow, but never longer than
-            // 1/32 of the steps taken so far, so a stop found at the end of a window
-            // overshoots the first passing check by at most about 3%
+            // longer windows while a live instance converges slowly (its rate estimate
+            // needs windows comparable to its decay time; in a batch, instances that
+            // are fast or at their rounding floor must not hold it back), but never
+            // longer than 1/32 of the steps taken so far, so a stop found at the end
+            // of a window overshoots the first passing check by at most about 3%
             int64_t taken = std::numeric_limits<int64_t>::max();
             for (int i : live) taken = std::min(taken, rs[i].info.steps);
-            if (!live.empty() && all_slow && (int64_t)K * reps * 2 <= kMaxWindow && (int64_t)K * reps * 64 <= taken)
+            if (!live.empty() && any_slow && (int64_t)K * reps * 2 <= kMaxWindow && (int64_t)K * reps * 64 <= taken)
                 reps *= 2;
         }
         int worst = LBM_OK;
