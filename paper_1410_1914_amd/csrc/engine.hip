@@ -64,6 +64,7 @@ struct Engine {
     size_t off_zbase = 0;  // per-instance zeros: dense output on one instance's own grid
     std::vector<int> cb_start, cb_count;  // conversion blocks of each instance
     size_t off_f0 = 0, off_f1 = 0, off_om = 0, off_snap = 0, off_rec = 0, off_inst = 0, off_dbase = 0, off_sblk = 0,
+           off_sinst = 0,
            off_cblk = 0, off_mblk = 0, off_rng = 0, off_part = 0, off_res = 0;
     int64_t cap_sblk = 0, cap_cblk = 0, cap_mblk = 0;
 
@@ -132,6 +133,7 @@ struct Engine {
         off_dbase = take(sizeof(int64_t) * ninst);
         off_zbase = take(sizeof(int64_t) * ninst);
         off_sblk = take(sizeof(uint32_t) * cap_sblk);
+        off_sinst = take(sizeof(uint32_t) * (ninst > 1 ? cap_sblk : 1));
         off_cblk = take(sizeof(int2) * cap_cblk);
         off_mblk = take(sizeof(int4) * cap_mblk);
         off_rng = take(sizeof(int2) * ninst);
@@ -164,11 +166,14 @@ struct Engine {
 
     hipError_t upload_tables() {
         // step list: the segments holding fluid of every live instance, in grid order
-        std::vector<uint32_t> sb;
+        std::vector<uint32_t> sb, si;
         for (int i : live) {
             const Prepared &p = P[i];
             for (int64_t g = 0; g < p.nseg; ++g)
-                if (p.m_fluid[g]) sb.push_back((uint32_t)(seg_base[i] + g));
+                if (p.m_fluid[g]) {
+                    sb.push_back((uint32_t)(seg_base[i] + g));
+                    if (ninst > 1) si.push_back((uint32_t)i);
+                }
         }
         step_nent = (int)sb.size();
         const int per = waves * spw;
@@ -186,6 +191,9 @@ struct Engine {
         hipError_t e = hipSuccess;
         if (!sb.empty())
             e = hipMemcpyAsync(at<uint32_t>(off_sblk), sb.data(), sizeof(uint32_t) * sb.size(), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess && !si.empty())
+            e = hipMemcpyAsync(at<uint32_t>(off_sinst), si.data(), sizeof(uint32_t) * si.size(), hipMemcpyHostToDevice,
+                               st);
         if (e == hipSuccess && !mb.empty())
             e = hipMemcpyAsync(at<int4>(off_mblk), mb.data(), sizeof(int4) * mb.size(), hipMemcpyHostToDevice, st);
         if (e == hipSuccess) e = hipMemcpyAsync(at<int2>(off_rng), rg.data(), sizeof(int2) * ninst, hipMemcpyHostToDevice, st);
@@ -323,6 +331,7 @@ struct Engine {
         s.nblk = step_nblk;
         s.nent = step_nent;
         s.list = at<uint32_t>(off_sblk);
+        s.list_inst = at<uint32_t>(off_sinst);
         s.single = ninst == 1 ? 1 : 0;
         return s;
     }

@@ -57,6 +57,8 @@ struct StepLaunch {
     int32_t nblk;             // workgroups
     int32_t nent;             // entries of the list
     const uint32_t *list;     // segments with fluid of the live instances, in grid order
+    const uint32_t *list_inst;// instance of each list entry (several instances), so a wave can load
+                              // its instance constants in parallel with its segment record
     int32_t single;           // 1: one instance (its constants load without waiting for the record)
 };
 

@@ -157,22 +157,22 @@ __global__ __launch_bounds__(WAVES * 64) void k_step(Lattice L, StepLaunch S, co
     const __amdgpu_buffer_rsrc_t rom = rsrc(L.omega, KNUDSEN ? S4 : 0u);
     const int base = (b * WAVES + wave) * SPW;
     const SegRec *R[SPW];
+    const InstDev *Ip[SPW];
     bool act[SPW];
     float r[SPW][8];
     uint32_t j4[SPW];
 #pragma unroll
     for (int k = 0; k < SPW; ++k) {
         const bool valid = base + k < S.nent;  // wave-uniform
-        R[k] = &L.rec[S.list[valid ? base + k : 0]];
+        const int idx = valid ? base + k : 0;
+        R[k] = &L.rec[S.list[idx]];
+        Ip[k] = &L.inst[SINGLE ? 0 : S.list_inst[idx]];  // independent of the record
         act[k] = valid && bit(R[k]->m, lane);
         gather<KNUDSEN>(*R[k], rin, rom, act[k], r[k], j4[k]);
     }
 #pragma unroll
     for (int k = 0; k < SPW; ++k) {
-        if (act[k]) {
-            const InstDev &I = L.inst[SINGLE ? 0 : R[k]->inst];
-            collide_store<KNUDSEN, REACT>(*R[k], I, rout, lane, r[k], j4[k]);
-        }
+        if (act[k]) collide_store<KNUDSEN, REACT>(*R[k], *Ip[k], rout, lane, r[k], j4[k]);
     }
 }
 
