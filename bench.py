@@ -282,7 +282,7 @@ def batch64_leg(lbm, insts):
             "batched_solves_per_s": round(len(phases) / t_batch, 3),
             "batched_speedup": round(t_single / t_batch, 2),
             "max_rate_rel_diff": max(abs(a / c - 1) for a, c in zip(batched, single)),
-            "status": st, "max_steps": int(max(steps)), "tiling": list(b.tiling()),
+            "status": st, "max_steps": int(max(steps)), "tiling": list(b.tiling()), "group_bytes": 192 << 20,
             "fluid_updates_single": int(updates), "fluid_updates_batched": int(b_updates)}
 
 

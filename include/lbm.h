@@ -253,6 +253,12 @@ int lbm_batch_run(lbm_batch *b, lbm_run_info *infos);
  * report LBM_NOT_CONVERGED and continue from where they are on the next call.
  * Returns the worst status, LBM_NOT_CONVERGED while any instance is running. */
 int lbm_batch_advance(lbm_batch *b, int64_t max_new_steps, lbm_run_info *infos);
+/* lbm_batch_run and lbm_batch_advance take the pending instances in groups whose
+ * combined working set (both lattices, 1/tau, snapshot and segment records: about
+ * 64 bytes per simulated voxel) stays within this many bytes, one group after the
+ * other, so each group stays resident in the GPU's 256 MB last-level cache while
+ * it steps.  Default 192 MiB; 0 runs every instance together. */
+int lbm_batch_set_group_bytes(lbm_batch *b, int64_t bytes);
 int lbm_batch_deff(const lbm_batch *b, int32_t i, double *deff_over_d0);
 int lbm_batch_reaction_rate(const lbm_batch *b, int32_t i, double *rate_per_area, double *j_in);
 int lbm_batch_get_info(const lbm_batch *b, int32_t i, lbm_info *info);

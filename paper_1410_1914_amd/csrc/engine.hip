@@ -79,6 +79,11 @@ struct Engine {
     int cur = 0;
 
     int waves = 4, spw = 1, xcd = 1;
+    // Batches run as consecutive groups of instances whose combined working set
+    // (both lattices, 1/tau, snapshot, records) fits this many bytes, so each group
+    // stays in the 256 MB last-level cache (Infinity Cache) while it steps; 0 runs
+    // every instance together.
+    int64_t group_bytes = int64_t(192) << 20;
     int step_nblk = 0, step_nent = 0, meas_nblk = 0, conv_nblk = 0;
     std::vector<int> live;
     std::vector<RunState> rs;
@@ -556,6 +561,53 @@ struct Engine {
         return worst;
     }
 
+    int64_t working_bytes(int i) const {
+        const Prepared &p = P[i];
+        return p.n_fluid * (int64_t)(56 + 4 + (knudsen ? 4 : 0)) + p.nseg * (int64_t)(sizeof(SegRec) + 4);
+    }
+
+    // The steady-state loop over groups of pending instances (see group_bytes): each
+    // group runs until all its instances finish (or the step budget is spent) before
+    // the next group starts.  One instance, or group_bytes == 0: plain run().
+    int run_grouped(lbm_run_info *out, int64_t budget = std::numeric_limits<int64_t>::max()) {
+        if (!bound) return LBM_ERR_UNBOUND;
+        if (ninst == 1 || group_bytes <= 0) return run(out, budget);
+        std::vector<int> pending;
+        for (int i = 0; i < ninst; ++i)
+            if (!rs[i].done) pending.push_back(i);
+        int64_t left = budget;
+        size_t k = 0;
+        while (k < pending.size() && left > 0) {
+            std::vector<int> grp;
+            int64_t bytes = 0;
+            while (k < pending.size() && (grp.empty() || bytes + working_bytes(pending[k]) <= group_bytes)) {
+                bytes += working_bytes(pending[k]);
+                grp.push_back(pending[k++]);
+            }
+            live = grp;
+            if (upload_tables() != hipSuccess) return LBM_ERR_HIP;
+            int64_t s0 = 0, s1 = 0;
+            for (int i : grp) s0 = std::max(s0, rs[i].info.steps);
+            const int st = run(nullptr, left);
+            if (st == LBM_ERR_HIP || st == LBM_ERR_UNBOUND) return st;
+            bool unfinished = false;
+            for (int i : grp) {
+                s1 = std::max(s1, rs[i].info.steps);
+                unfinished = unfinished || !rs[i].done;
+            }
+            left -= std::max<int64_t>(s1 - s0, 0);
+            if (unfinished) break;  // the budget ran out inside this group
+        }
+        int worst = LBM_OK;
+        for (int i = 0; i < ninst; ++i) {
+            if (out) out[i] = rs[i].info;
+            const int s = rs[i].info.status;
+            if (s < 0 && (worst >= 0 || s < worst)) worst = s;
+            if (s == LBM_NOT_CONVERGED && worst == LBM_OK) worst = LBM_NOT_CONVERGED;
+        }
+        return worst;
+    }
+
     int deff(int i, double *out) const {
         const Prepared &p = P[i];
         if (react) return LBM_ERR_WRONG_MODE;
@@ -1009,7 +1061,7 @@ int lbm_batch_run(lbm_batch *b, lbm_run_info *infos) {
     LBM_GUARD_BEGIN
     if (!b) return LBM_ERR_INVALID_ARG;
     cl::DeviceGuard dg(b->E->device);
-    return b->E->run(infos);
+    return b->E->run_grouped(infos);
     LBM_GUARD_END
 }
 
@@ -1017,8 +1069,14 @@ int lbm_batch_advance(lbm_batch *b, int64_t max_new_steps, lbm_run_info *infos) 
     LBM_GUARD_BEGIN
     if (!b || max_new_steps < 0) return LBM_ERR_INVALID_ARG;
     cl::DeviceGuard dg(b->E->device);
-    return b->E->run(infos, max_new_steps);
+    return b->E->run_grouped(infos, max_new_steps);
     LBM_GUARD_END
+}
+
+int lbm_batch_set_group_bytes(lbm_batch *b, int64_t bytes) {
+    if (!b || bytes < 0) return LBM_ERR_INVALID_ARG;
+    b->E->group_bytes = bytes;
+    return LBM_OK;
 }
 
 int lbm_batch_deff(const lbm_batch *b, int32_t i, double *out) {

@@ -106,6 +106,7 @@ SIGNATURES = {
     "lbm_batch_autotune": ([_P, c_int32, ctypes.POINTER(c_double)], c_int32),
     "lbm_batch_run": ([_P, ctypes.POINTER(lbm_run_info)], c_int32),
     "lbm_batch_advance": ([_P, c_int64, ctypes.POINTER(lbm_run_info)], c_int32),
+    "lbm_batch_set_group_bytes": ([_P, c_int64], c_int32),
     "lbm_batch_deff": ([_P, c_int32, ctypes.POINTER(c_double)], c_int32),
     "lbm_batch_reaction_rate": ([_P, c_int32, ctypes.POINTER(c_double), ctypes.POINTER(c_double)], c_int32),
     "lbm_batch_get_info": ([_P, c_int32, ctypes.POINTER(lbm_info)], c_int32),
@@ -554,6 +555,9 @@ class Batch:
 
     def advance(self, max_new_steps):
         return lbm_batch_advance(self.h, self.n, max_new_steps)
+
+    def set_group_bytes(self, nbytes):
+        _check("lbm_batch_set_group_bytes", load().lbm_batch_set_group_bytes(self.h, int(nbytes)))
 
     def deff(self, i):
         return lbm_batch_deff(self.h, i)

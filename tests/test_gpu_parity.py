@@ -258,3 +258,30 @@ def test_every_tiling_gives_identical_batched_steps(hip):
         else:
             for i in range(3):
                 assert np.array_equal(got[i], ref[i]), (t, i)
+
+
+def test_batch_groups_reach_the_same_answers(hip):
+    """A batch run as cache-sized groups (here one instance per group) and the same
+    batch run all together finish every instance with the same output."""
+    phases = [sg.pt_cl(50 + i, shape=sh) for i, sh in enumerate([(8, 9, 66), (6, 6, 40), (10, 10, 70)])]
+    mk = lambda: [hip.lbm_params_default(mode=1, k_lat=k, check_every=200) for k in (0.1, 0.01, 0.03)]  # noqa: E731
+    together = hip.Batch(phases, mk())
+    together.set_group_bytes(0)
+    st, _ = together.run()
+    assert st == 0
+    grouped = hip.Batch(phases, mk())
+    grouped.set_group_bytes(1)
+    st, infos = grouped.run()
+    assert st == 0 and all(r.status == 0 for r in infos)
+    for i in range(3):
+        assert grouped.reaction_rate(i)[1] == pytest.approx(together.reaction_rate(i)[1], rel=1e-5)
+    # in steps budgets, groups are taken one after the other
+    b = hip.Batch(phases, mk())
+    b.set_group_bytes(1)
+    for _ in range(1000):
+        st, infos = b.advance(5000)
+        if st != hip.NOT_CONVERGED:
+            break
+    assert st == 0
+    for i in range(3):
+        assert b.reaction_rate(i)[1] == pytest.approx(together.reaction_rate(i)[1], rel=1e-5)
