@@ -47,9 +47,10 @@ int unet_conv3d_fwd(const uint16_t *x, int32_t ldx, int32_t offx, const uint16_t
  * unet_conv3d_fwd with wt (cin and cout swapped, no bias, no ReLU) on dy gives dx. */
 int unet_conv3d_wtrans(const uint16_t *w, uint16_t *wt, int32_t cin, int32_t cout, void *stream);
 
-/* dw[co, k] += sum_v dy[v, offdy + co] x[v + tap(k), offx + ci(k)] (FP32
- * accumulation), and, when db is not NULL, db[co] += sum_v dy[v, offdy + co].
- * dw is [cout][kpad] FP32. */
+/* dw[co, k] += sum_v dy[v, offdy + co] x[v + tap(k), offx + ci(k)] on BF16 MFMA
+ * (16x16x32) with FP32 accumulation, and, when db is not NULL, db[co] += sum_v
+ * dy[v, offdy + co].  dw is [cout][kpad] FP32.  cin and cout are multiples of 16;
+ * ldx, offx, lddy, offdy multiples of 8 (16-byte loads), else -1. */
 int unet_conv3d_wgrad(const uint16_t *x, int32_t ldx, int32_t offx, const uint16_t *dy, int32_t lddy, int32_t offdy,
                       int32_t nz, int32_t ny, int32_t nx, int32_t cin, int32_t cout, float *dw, float *db,
                       void *stream);

@@ -117,73 +117,112 @@ __global__ void k_wtrans(const uint16_t *w, uint16_t *wt, int cin, int cout, int
 
 // ------------------------------------------------------------------ conv3d weight gradient
 //
-// dw[co][k] += sum_v dy[v][co] X(v, k): a GEMM with the voxels as K, tiled 64 (co)
-// x 64 (k) per workgroup over a voxel range, 16 voxels per LDS stage, 4 x 4 FP32
-// outputs per thread; partial sums are added to dw atomically.
-constexpr int kWgVox = 16;
+// dw[co][k] += sum_v dy[v][co] X(v, k) with X the im2col view of x: a GEMM whose
+// reduction runs over the voxels.  On the 16x16x32 BF16 MFMA: M = output channel,
+// N = k, K = 32 voxels per instruction.  A workgroup (4 waves) owns 16*NCO output
+// channels x 128 k over a voxel range; per stage it stages 32 voxels of dy and of
+// X into LDS transposed (voxels fastest), so each lane reads its 8-voxel fragment
+// with one 16-byte LDS load; each wave accumulates NCO x 2 tiles of 16 x 16 in FP32
+// and adds them to dw atomically at the end.
+constexpr int kWgStage = 32;  // voxels per stage (the MFMA's K)
+constexpr int kWgK = 128;     // k per workgroup
+constexpr int kWgPad = 40;    // LDS row length (bf16): 32 voxels + 8 against bank conflicts
 
+template <int NCO>
 __global__ __launch_bounds__(256) void k_wgrad(const uint16_t *x, int ldx, int offx, const uint16_t *dy, int lddy,
                                                int offdy, int nz, int ny, int nx, int cin, int cout, int kpad,
                                                int64_t vper, float *dw, float *db) {
-    __shared__ float As[kWgVox][64];
-    __shared__ float Bs[kWgVox][64];
-    const int tid = threadIdx.x;
-    const int tr = tid >> 4, tc = tid & 15;  // 16 x 16 threads, 4 x 4 outputs each
-    const int k0 = blockIdx.x * 64, co0 = blockIdx.z * 64;
+    __shared__ __attribute__((aligned(16))) uint16_t XT[kWgK][kWgPad];
+    __shared__ __attribute__((aligned(16))) uint16_t DT[16 * NCO][kWgPad];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int k0 = blockIdx.x * kWgK, co0 = blockIdx.z * 16 * NCO;
+    const int K = 27 * cin;
     const int64_t nvox = (int64_t)nz * ny * nx;
     const int64_t v0 = (int64_t)blockIdx.y * vper;
     const int64_t v1 = min(nvox, v0 + vper);
-    float acc[4][4] = {};
+    // staging roles: X: voxel sv = tid / 8, two 8-wide k chunks c = tid % 8 and + 8
+    const int sv = tid >> 3, sc = tid & 7;
+    int ck[2], cdz[2], cdy[2], cdx[2], cci[2];
+    bool cok[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int k = k0 + 8 * (sc + 8 * h);
+        cok[h] = k < K;
+        const int tap = cok[h] ? k / cin : 0;
+        ck[h] = 8 * (sc + 8 * h);
+        cci[h] = k - tap * cin;
+        cdz[h] = tap / 9 - 1;
+        cdy[h] = (tap / 3) % 3 - 1;
+        cdx[h] = tap % 3 - 1;
+    }
+    // dy: voxel sv, channels 8 * sc .. when 8 * sc < 16 * NCO
+    const bool dact = 8 * sc < 16 * NCO;
+    f32x4 acc[NCO][2];
+#pragma unroll
+    for (int c = 0; c < NCO; ++c)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) acc[c][t] = (f32x4){0.f, 0.f, 0.f, 0.f};
     float bacc = 0.f;
-    const int K = 27 * cin;
-    for (int64_t vs = v0; vs < v1; vs += kWgVox) {
-        for (int e = tid; e < kWgVox * 64; e += 256) {
-            const int vv = e >> 6, cc = e & 63;
-            const int64_t v = vs + vv;
-            const int co = co0 + cc;
-            As[vv][cc] = (v < v1 && co < cout) ? bf2f(dy[v * lddy + offdy + co]) : 0.f;
-            const int k = k0 + cc;
-            float xv = 0.f;
-            if (v < v1 && k < K) {
-                const int tap = k / cin, ci = k - tap * cin;
-                const int xx0 = (int)(v % nx);
-                const int64_t r = v / nx;
-                const int yy0 = (int)(r % ny), zz0 = (int)(r / ny);
-                const int zz = zz0 + tap / 9 - 1, yy = yy0 + (tap / 3) % 3 - 1, xx = xx0 + tap % 3 - 1;
-                if (zz >= 0 && zz < nz && yy >= 0 && yy < ny && xx >= 0 && xx < nx)
-                    xv = bf2f(x[(((int64_t)zz * ny + yy) * nx + xx) * ldx + offx + ci]);
+    const int m = lane & 15, q = lane >> 4;
+    for (int64_t vs = v0; vs < v1; vs += kWgStage) {
+        const int64_t v = vs + sv;
+        const bool vok = v < v1;
+        int xx = 0, yy = 0, zz = 0;
+        if (vok) {
+            xx = (int)(v % nx);
+            const int64_t r = v / nx;
+            yy = (int)(r % ny);
+            zz = (int)(r / ny);
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            uint4 val = make_uint4(0u, 0u, 0u, 0u);
+            const int z2 = zz + cdz[h], y2 = yy + cdy[h], x2 = xx + cdx[h];
+            if (vok && cok[h] && z2 >= 0 && z2 < nz && y2 >= 0 && y2 < ny && x2 >= 0 && x2 < nx) {
+                const int64_t nb = ((int64_t)z2 * ny + y2) * nx + x2;
+                val = *reinterpret_cast<const uint4 *>(x + nb * ldx + offx + cci[h]);
             }
-            Bs[vv][cc] = xv;
+            const uint16_t *e = reinterpret_cast<const uint16_t *>(&val);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) XT[ck[h] + i][sv] = e[i];
+        }
+        if (dact) {
+            uint4 val = make_uint4(0u, 0u, 0u, 0u);
+            if (vok) val = *reinterpret_cast<const uint4 *>(dy + v * lddy + offdy + co0 + 8 * sc);
+            const uint16_t *e = reinterpret_cast<const uint16_t *>(&val);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) DT[8 * sc + i][sv] = e[i];
         }
         __syncthreads();
+        bf16x8 A[NCO];
 #pragma unroll
-        for (int vv = 0; vv < kWgVox; ++vv) {
-            float a4[4], b4[4];
+        for (int c = 0; c < NCO; ++c)
+            A[c] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(&DT[16 * c + m][8 * q]));
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const bf16x8 B =
+                __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(&XT[16 * (2 * wave + t) + m][8 * q]));
+#pragma unroll
+            for (int c = 0; c < NCO; ++c) acc[c][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[c], B, acc[c][t], 0, 0, 0);
+        }
+        if (db && blockIdx.x == 0 && tid < 16 * NCO)
+            for (int i = 0; i < kWgStage; ++i) bacc += bf2f(DT[tid][i]);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int c = 0; c < NCO; ++c)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int k = k0 + 16 * (2 * wave + t) + m;
+            if (k >= K) continue;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                a4[i] = As[vv][tr * 4 + i];
-                b4[i] = Bs[vv][tc * 4 + i];
+                const int co = co0 + 16 * c + 4 * q + i;
+                const float v = acc[c][t][i];
+                if (v != 0.f) atomicAdd(&dw[(int64_t)co * kpad + k], v);
             }
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj) acc[i][jj] = fmaf(a4[i], b4[jj], acc[i][jj]);
         }
-        if (db && blockIdx.x == 0 && tid < 64)
-            for (int vv = 0; vv < kWgVox; ++vv) bacc += As[vv][tid];
-        __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int co = co0 + tr * 4 + i;
-        if (co >= cout) continue;
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-            const int k = k0 + tc * 4 + jj;
-            if (k < K && acc[i][jj] != 0.f) atomicAdd(&dw[(int64_t)co * kpad + k], acc[i][jj]);
-        }
-    }
-    if (db && blockIdx.x == 0 && tid < 64 && co0 + tid < cout) atomicAdd(&db[co0 + tid], bacc);
+    if (db && blockIdx.x == 0 && tid < 16 * NCO) atomicAdd(&db[co0 + tid], bacc);
 }
 
 // ------------------------------------------------------------------ elementwise layers
@@ -444,12 +483,24 @@ int unet_conv3d_wgrad(const uint16_t *x, int32_t ldx, int32_t offx, const uint16
                       void *stream) {
     if (!x || !dy || !dw || nz <= 0 || ny <= 0 || nx <= 0 || !ch_ok(ldx, offx, cin) || !ch_ok(lddy, offdy, cout))
         return -1;
+    if (cin % 16 || cout % 16 || ldx % 8 || offx % 8 || lddy % 8 || offdy % 8) return -1;
     const int64_t nvox = (int64_t)nz * ny * nx;
-    const int64_t vper = 4096;
-    const dim3 g((unsigned)((27 * cin + 63) / 64), (unsigned)((nvox + vper - 1) / vper), (unsigned)((cout + 63) / 64));
+    const int nco = cout % 64 == 0 ? 4 : (cout % 32 == 0 ? 2 : 1);
+    // enough workgroups to fill the device: the voxel range per workgroup shrinks
+    // for layers with few (k, channel) tiles
+    const int64_t tiles = (int64_t)((27 * cin + kWgK - 1) / kWgK) * (cout / (16 * nco));
+    int64_t vper = 4096;
+    while (vper > 512 && tiles * ((nvox + vper - 1) / vper) < 2048) vper >>= 1;
+    const dim3 g((unsigned)((27 * cin + kWgK - 1) / kWgK), (unsigned)((nvox + vper - 1) / vper),
+                 (unsigned)(cout / (16 * nco)));
     (void)hipGetLastError();
-    hipLaunchKernelGGL(k_wgrad, g, dim3(256), 0, static_cast<hipStream_t>(stream), x, ldx, offx, dy, lddy, offdy, nz,
-                       ny, nx, cin, cout, kpad_of(cin), vper, dw, db);
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    const int kp = kpad_of(cin);
+    switch (nco) {
+        case 4: hipLaunchKernelGGL(k_wgrad<4>, g, dim3(256), 0, st, x, ldx, offx, dy, lddy, offdy, nz, ny, nx, cin, cout, kp, vper, dw, db); break;
+        case 2: hipLaunchKernelGGL(k_wgrad<2>, g, dim3(256), 0, st, x, ldx, offx, dy, lddy, offdy, nz, ny, nx, cin, cout, kp, vper, dw, db); break;
+        default: hipLaunchKernelGGL(k_wgrad<1>, g, dim3(256), 0, st, x, ldx, offx, dy, lddy, offdy, nz, ny, nx, cin, cout, kp, vper, dw, db); break;
+    }
     return status(hipGetLastError());
 }
 
