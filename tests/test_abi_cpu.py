@@ -201,3 +201,22 @@ def test_pore_depth_matches_breadth_first_search(mode, seed):
     assert np.array_equal(depth.astype(np.int64), want)
     assert (depth[act.astype(bool)] < 255).any() and (depth[~act.astype(bool)] == 255).all()
     assert set(np.unique(depth[act.astype(bool)])) > {0, 1}
+
+
+def test_batch_entry_points_reject_bad_arguments():
+    """Host-side checks of the batched entry points (no device call is made)."""
+    phases = [sg.pt_cl(60 + i, shape=(4, 5, 20)) for i in range(2)]
+    params = [lbm.lbm_params_default(mode=lbm.MODE_REACT, k_lat=0.01) for _ in phases]
+    h = lbm.lbm_batch_create(phases, params)
+    lib = lbm.load()
+    assert lib.lbm_batch_set_group_bytes(h, -1) == lbm.ERR_INVALID_ARG
+    assert lib.lbm_batch_set_group_bytes(h, 0) == lbm.OK
+    assert lib.lbm_batch_set_group_bytes(h, 1 << 20) == lbm.OK
+    assert lib.lbm_batch_set_group_bytes(None, 1) == lbm.ERR_INVALID_ARG
+    assert lib.lbm_batch_advance(h, -5, None) == lbm.ERR_INVALID_ARG
+    assert lib.lbm_batch_advance(None, 5, None) == lbm.ERR_INVALID_ARG
+    # stepping before a workspace is bound is refused, not attempted
+    assert lib.lbm_batch_advance(h, 5, None) == lbm.ERR_UNBOUND
+    assert lib.lbm_batch_get_pore_depth(h, 2, np.zeros(1, np.uint8).ctypes.data_as(
+        __import__("ctypes").POINTER(__import__("ctypes").c_uint8))) == lbm.ERR_INVALID_ARG
+    lbm.lbm_batch_destroy(h)

@@ -285,3 +285,29 @@ def test_batch_groups_reach_the_same_answers(hip):
     assert st == 0
     for i in range(3):
         assert b.reaction_rate(i)[1] == pytest.approx(together.reaction_rate(i)[1], rel=1e-5)
+
+
+def test_pt_cl_64_matches_the_oracle_fixed_point(hip):
+    """Steady D_eff/D0 and reaction rate of 64^3 Pt catalyst layers (Knudsen,
+    ionomer 1e-3 D0) against the oracle's exact fixed point (BiCGStab to 1e-11,
+    stored in tests/golden/oracle_pt_cl_64.json by tests/golden/make_golden.py)."""
+    import json
+    import os
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_pt_cl_64.json")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle values not generated (python tests/golden/make_golden.py oracle_pt_cl_64.json)")
+    with open(path) as fh:
+        cases = json.load(fh)["cases"]
+    for c in cases:
+        ph = sg.pt_cl(c["seed"], shape=tuple(c["shape"]))
+        s = hip.Solver(ph, hip.lbm_params_default(mode=c["mode"], knudsen=1, k_lat=c["k_lat"]), voxel_m=2e-9)
+        st, info = s.run_to_steady()
+        assert st == 0
+        if c["mode"] == 0:
+            got, want = s.deff()[1], c["deff"]
+        else:
+            got, want = s.reaction_rate()[1], c["rate"]
+        print(f"[64^3] mode {c['mode']}: GPU {got:.10e} oracle {want:.10e} rel {got / want - 1:+.2e} "
+              f"({info.steps} steps)", flush=True)
+        assert got == pytest.approx(want, rel=STEADY_RTOL)
