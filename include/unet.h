@@ -77,7 +77,7 @@ int unet_up_bwd(const uint16_t *dy, int32_t ldy, int32_t offy, uint16_t *dx, int
 int unet_head_fwd(const uint16_t *x, int32_t ldx, const float *w, const float *b, const float *base, float *out,
                   int64_t nvox, int32_t c, void *stream);
 /* Head backward from dout (FP32): dx[v, c] = dout[v] w[c] (BF16), dw[c] += sum
- * dout[v] x[v, c], db += sum dout[v]. */
+ * dout[v] x[v, c], db += sum dout[v].  c <= 32. */
 int unet_head_bwd(const uint16_t *x, int32_t ldx, const float *w, const float *dout, uint16_t *dx, float *dw,
                   float *db, int64_t nvox, int32_t c, void *stream);
 

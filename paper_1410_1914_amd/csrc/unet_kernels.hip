@@ -311,19 +311,36 @@ __device__ __forceinline__ float block_sum(float v, float *red) {
     return t;
 }
 
-// one workgroup per 256 voxels: dx, and per-channel partials of dw, db added atomically
+constexpr int kHeadMaxC = 32;  // channels of the 1x1x1 head (the first U-Net level)
+
+// Grid-stride over the voxels with per-thread channel partials in registers, so
+// each workgroup reduces and adds to dw / db once (not once per 256 voxels).
 __global__ __launch_bounds__(256) void k_head_bwd(const uint16_t *x, int ldx, const float *w, const float *dout,
                                                   uint16_t *dx, float *dw, float *db, int64_t nvox, int c) {
     __shared__ float red[4];
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const float g = v < nvox ? dout[v] : 0.f;
-    for (int ch = 0; ch < c; ++ch) {
-        const float xv = v < nvox ? bf2f(x[v * ldx + ch]) : 0.f;
-        if (v < nvox) dx[v * c + ch] = f2bf(g * w[ch]);
-        const float s = block_sum(g * xv, red);
-        if (threadIdx.x == 0) atomicAdd(&dw[ch], s);
+    float part[kHeadMaxC];
+#pragma unroll
+    for (int ch = 0; ch < kHeadMaxC; ++ch) part[ch] = 0.f;
+    float gsum = 0.f;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nvox; v += (int64_t)gridDim.x * blockDim.x) {
+        const float g = dout[v];
+        gsum += g;
+#pragma unroll
+        for (int ch = 0; ch < kHeadMaxC; ++ch) {
+            if (ch < c) {
+                part[ch] += g * bf2f(x[v * ldx + ch]);
+                dx[v * c + ch] = f2bf(g * w[ch]);
+            }
+        }
     }
-    const float s = block_sum(g, red);
+#pragma unroll
+    for (int ch = 0; ch < kHeadMaxC; ++ch) {
+        if (ch < c) {
+            const float s = block_sum(part[ch], red);
+            if (threadIdx.x == 0) atomicAdd(&dw[ch], s);
+        }
+    }
+    const float s = block_sum(gsum, red);
     if (threadIdx.x == 0) atomicAdd(db, s);
 }
 
@@ -560,10 +577,11 @@ int unet_head_fwd(const uint16_t *x, int32_t ldx, const float *w, const float *b
 
 int unet_head_bwd(const uint16_t *x, int32_t ldx, const float *w, const float *dout, uint16_t *dx, float *dw,
                   float *db, int64_t nvox, int32_t c, void *stream) {
-    if (!x || !w || !dout || !dx || !dw || !db || nvox <= 0 || c <= 0 || ldx < c) return -1;
+    if (!x || !w || !dout || !dx || !dw || !db || nvox <= 0 || c <= 0 || c > kHeadMaxC || ldx < c) return -1;
     (void)hipGetLastError();
-    hipLaunchKernelGGL(k_head_bwd, grid1(nvox), dim3(256), 0, static_cast<hipStream_t>(stream), x, ldx, w, dout, dx,
-                       dw, db, nvox, c);
+    const dim3 g((unsigned)std::min<int64_t>((nvox + 255) / 256, 1024));
+    hipLaunchKernelGGL(k_head_bwd, g, dim3(256), 0, static_cast<hipStream_t>(stream), x, ldx, w, dout, dx, dw, db,
+                       nvox, c);
     return status(hipGetLastError());
 }
 
