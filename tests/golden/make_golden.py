@@ -31,26 +31,28 @@ def two_phase_32():
             "cases": out}
 
 
-def pt_cl_64():
+def pt_cl_slab():
     """Four-phase Pt catalyst layers at 2 nm (carbon + Pt 0.35, ionomer 0.20, pores
-    0.45), Knudsen pore diffusivity, ionomer 1e-3 D0: D_eff/D0 of a 64^3 structure and
-    the reaction rate (k = 1e-2 per Pt face, inlet reservoir plane) of a 64x64x63
-    structure, each at the exact fixed point (BiCGStab to 1e-11)."""
+    0.45), Knudsen pore diffusivity, ionomer 1e-3 D0, as 32 x 32 x 130 slabs (rows of
+    130 voxels along the transport axis x): D_eff/D0, and the reaction rate (k = 1e-2
+    per Pt face) with the inlet reservoir plane prepended to a 32 x 32 x 129 structure,
+    each at the exact fixed point (sparse LU)."""
     out = []
-    for mode, shape, k in ((O.MODE_DEFF, (64, 64, 64), 0.0), (O.MODE_REACT, (64, 64, 63), 1e-2)):
-        ph = sg.pt_cl(7, shape=shape)
-        t = time.time()
-        s = O.solve_fixed_point(O.prepare(ph, O.Params(mode=mode, knudsen=True, voxel_m=2e-9, k_lat=k)), "bicgstab",
-                                tol=1e-11)
-        out.append({"seed": 7, "shape": list(shape), "mode": mode, "k_lat": k, "deff": s.deff, "rate": s.rate,
-                    "j_in": s.fluxes.j_in, "seconds": round(time.time() - t, 1)})
-        print(out[-1], flush=True)
-    return {"workload": "Pt CL at 2 nm, Knudsen, ionomer 1e-3 D0; D_eff and reactive (k 1e-2) problems",
-            "generator": "structgen.pt_cl(7, shape=...)", "solver": "oracle.lbm.solve_fixed_point (BiCGStab, 1e-11)",
+    for seed in (7, 8):
+        for mode, shape, k in ((O.MODE_DEFF, (32, 32, 130), 0.0), (O.MODE_REACT, (32, 32, 129), 1e-2)):
+            ph = sg.pt_cl(seed, shape=shape)
+            t = time.time()
+            s = O.solve_fixed_point(O.prepare(ph, O.Params(mode=mode, knudsen=True, voxel_m=2e-9, k_lat=k)),
+                                    "direct")
+            out.append({"seed": seed, "shape": list(shape), "mode": mode, "k_lat": k, "deff": s.deff,
+                        "rate": s.rate, "j_in": s.fluxes.j_in, "seconds": round(time.time() - t, 1)})
+            print(out[-1], flush=True)
+    return {"workload": "Pt CL slabs at 2 nm, Knudsen, ionomer 1e-3 D0; D_eff and reactive (k 1e-2) problems",
+            "generator": "structgen.pt_cl(seed, shape=...)", "solver": "oracle.lbm.solve_fixed_point (sparse LU)",
             "cases": out}
 
 
-GOLDEN = {"oracle_two_phase_32.json": two_phase_32, "oracle_pt_cl_64.json": pt_cl_64}
+GOLDEN = {"oracle_two_phase_32.json": two_phase_32, "oracle_pt_cl_slab.json": pt_cl_slab}
 
 if __name__ == "__main__":
     names = sys.argv[1:] or list(GOLDEN)
