@@ -108,7 +108,7 @@ typedef struct {
     double est_error;   /* estimated remaining relative error of the output       */
     double kernel_ms;   /* HIP-event time of the stream-collide launches made by
                            the steady-state loop since the last initialisation    */
-    int64_t kernel_launches; /* stream-collide launches timed in kernel_ms        */
+    int64_t kernel_launches; /* steps timed in kernel_ms (a two-step launch: 2)  */
     int32_t status;     /* LBM_OK, LBM_NOT_CONVERGED or an error                  */
     int32_t checks;     /* number of convergence checks made                      */
 } lbm_run_info;
@@ -194,11 +194,23 @@ int lbm_run_to_steady(lbm_solver *s, lbm_run_info *info);
 
 /* Tiling of the stream-collide launch: segments per wave (1, 2, 4), waves per
  * workgroup (1, 2, 4, 8), XCD-aware workgroup order (0/1).  lbm_autotune times
- * every tiling for steps_per_trial steps on the live state (the trial steps are
- * ordinary solver steps) and keeps the fastest; ms_best receives its time per step. */
+ * every tiling, and every two-step form below, for steps_per_trial steps on the
+ * live state (the trial steps are ordinary solver steps) and keeps the fastest;
+ * ms_best receives its time per step. */
 int lbm_set_tiling(lbm_solver *s, int32_t segs_per_wave, int32_t waves_per_block, int32_t xcd_remap);
 int lbm_get_tiling(const lbm_solver *s, int32_t *segs_per_wave, int32_t *waves_per_block, int32_t *xcd_remap);
 int lbm_autotune(lbm_solver *s, int32_t steps_per_trial, double *ms_best);
+
+/* Two time steps per stream-collide launch (temporal blocking, Section 4's update
+ * applied twice with the intermediate populations kept on chip).  A workgroup owns
+ * one 64-voxel x range and rows_per_tile rows in y (4 or 8) and marches through
+ * planes_per_chunk planes in z (1 .. 4096); the populations between the two steps
+ * are rounded to FP32 exactly as a stored lattice is, so the results are
+ * bit-identical to two single-step launches.  rows_per_tile 0 returns to one step
+ * per launch (the default); an odd step count ends with one single-step launch.
+ * Returns LBM_ERR_INVALID_ARG for other values. */
+int lbm_set_temporal(lbm_solver *s, int32_t rows_per_tile, int32_t planes_per_chunk);
+int lbm_get_temporal(const lbm_solver *s, int32_t *rows_per_tile, int32_t *planes_per_chunk);
 
 /* The loop of lbm_run_to_steady with a budget: at most max_new_steps further
  * steps (whole windows of K steps; fewer than K steps of budget does nothing).

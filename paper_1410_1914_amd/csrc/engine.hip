@@ -79,6 +79,8 @@ struct Engine {
     int cur = 0;
 
     int waves = 4, spw = 1, xcd = 1;
+    // Two steps per launch (one instance only): rows per tile (0 = off), planes per chunk.
+    int t2_by = 0, t2_zc = 32;
     // Batches run as consecutive groups of instances whose combined working set
     // (both lattices, 1/tau, snapshot, records) fits this many bytes, so each group
     // stays in the 256 MB last-level cache (Infinity Cache) while it steps; 0 runs
@@ -341,9 +343,35 @@ struct Engine {
         return s;
     }
 
+    bool two_step() const { return t2_by > 0 && ninst == 1; }
+
+    Step2Launch step2_launch() const {
+        const Prepared &p = P[0];
+        Step2Launch s{};
+        s.by = t2_by;
+        s.zc = t2_zc;
+        s.nty = (p.ny + t2_by - 1) / t2_by;
+        s.ncz = (p.nz + t2_zc - 1) / t2_zc;
+        s.nblk = p.nsx * s.nty * s.ncz;
+        s.xcd = xcd;
+        return s;
+    }
+
+    // Lattice swaps made by n steps, mod 2: one per launch.
+    int flips(int64_t n) const { return (int)((two_step() ? n / 2 + (n & 1) : n) & 1); }
+
     hipError_t steps(int64_t n) {
+        int64_t k = 0;
+        if (two_step()) {
+            const Step2Launch s2 = step2_launch();
+            for (; k + 2 <= n; k += 2) {
+                hipError_t e = launch_step2(L, s2, knudsen, react, f[cur], f[cur ^ 1], st);
+                if (e != hipSuccess) return e;
+                cur ^= 1;
+            }
+        }
         const StepLaunch s = step_launch();
-        for (int64_t k = 0; k < n; ++k) {
+        for (; k < n; ++k) {
             hipError_t e = launch_step(L, s, knudsen, react, f[cur], f[cur ^ 1], st);
             if (e != hipSuccess) return e;
             cur ^= 1;
@@ -403,13 +431,13 @@ struct Engine {
         hipError_t e = note(hipEventRecord(ev0, st), "hipEventRecord");
         for (int64_t r = 0; r < reps && e == hipSuccess; ++r) {
             e = note(hipGraphLaunch(gexec, st), "hipGraphLaunch");
-            if (K0 & 1) cur ^= 1;
+            if (flips(K0)) cur ^= 1;
         }
         if (e == hipSuccess) e = note(hipEventRecord(ev1, st), "hipEventRecord");
         if (e != hipSuccess) return e;
         ev_pending = true;
         ev_launches = (int64_t)K0 * reps;
-        if (K0 & 1) g_valid = false;  // the next window starts from the other lattice
+        if (flips(K0)) g_valid = false;  // the next window starts from the other lattice
         return measure_enqueue(1);
     }
 
@@ -994,38 +1022,65 @@ static int autotune(cl::Engine &E, int32_t steps_per_trial, double *ms_best) {
     int64_t trial_steps = 0;
     hipEvent_t t0, t1;
     if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) return LBM_ERR_HIP;
+    double best = 1e300;
+    auto trial = [&]() -> bool {  // times the current form; true if it is the fastest so far
+        if ((e = E.upload_tables()) != hipSuccess) return false;
+        if ((e = E.steps(2)) != hipSuccess) return false;  // warm-up
+        if ((e = hipEventRecord(t0, E.st)) != hipSuccess) return false;
+        if ((e = E.steps(steps_per_trial)) != hipSuccess) return false;
+        trial_steps += steps_per_trial + 2;
+        if ((e = hipEventRecord(t1, E.st)) != hipSuccess) return false;
+        if ((e = hipEventSynchronize(t1)) != hipSuccess) return false;
+        float ms = 0.f;
+        if ((e = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess) return false;
+        const double per = ms / steps_per_trial;
+        if (per >= best) return false;
+        best = per;
+        return true;
+    };
+    // one step per launch: segments per wave x waves per workgroup x XCD order
     const int spws[3] = {1, 2, 4};
     const int wavs[4] = {1, 2, 4, 8};
-    double best = 1e300;
-    int bs = E.spw, bw = E.waves, bx = E.xcd;
+    int bs = E.spw, bw = E.waves, bx = E.xcd, bby = 0, bzc = E.t2_zc;
+    E.t2_by = 0;
     for (int xi = 0; xi < 2 && e == hipSuccess; ++xi)
         for (int si = 0; si < 3 && e == hipSuccess; ++si)
             for (int wi = 0; wi < 4 && e == hipSuccess; ++wi) {
                 E.spw = spws[si];
                 E.waves = wavs[wi];
                 E.xcd = xi;
-                if ((e = E.upload_tables()) != hipSuccess) break;
-                if ((e = E.steps(2)) != hipSuccess) break;  // warm-up
-                if ((e = hipEventRecord(t0, E.st)) != hipSuccess) break;
-                if ((e = E.steps(steps_per_trial)) != hipSuccess) break;
-                trial_steps += steps_per_trial + 2;
-                if ((e = hipEventRecord(t1, E.st)) != hipSuccess) break;
-                if ((e = hipEventSynchronize(t1)) != hipSuccess) break;
-                float ms = 0.f;
-                if ((e = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess) break;
-                const double per = ms / steps_per_trial;
-                if (per < best) {
-                    best = per;
+                if (trial()) {
                     bs = E.spw;
                     bw = E.waves;
                     bx = E.xcd;
                 }
             }
+    // two steps per launch (one instance): rows per tile x planes per chunk x XCD order
+    if (E.ninst == 1) {
+        E.spw = bs;
+        E.waves = bw;
+        const int bys[2] = {4, 8};
+        const int zcs[4] = {8, 16, 32, 64};
+        for (int xi = 0; xi < 2 && e == hipSuccess; ++xi)
+            for (int yi = 0; yi < 2 && e == hipSuccess; ++yi)
+                for (int zi = 0; zi < 4 && e == hipSuccess; ++zi) {
+                    E.xcd = xi;
+                    E.t2_by = bys[yi];
+                    E.t2_zc = zcs[zi];
+                    if (trial()) {
+                        bx = E.xcd;
+                        bby = E.t2_by;
+                        bzc = E.t2_zc;
+                    }
+                }
+    }
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
     E.spw = bs;
     E.waves = bw;
     E.xcd = bx;
+    E.t2_by = bby;
+    E.t2_zc = bzc;
     if (e == hipSuccess) e = E.upload_tables();
     for (int i : E.live) E.rs[i].info.steps += trial_steps;
     if (ms_best) *ms_best = best;
@@ -1051,6 +1106,23 @@ int lbm_set_tiling(lbm_solver *s, int32_t spw, int32_t waves, int32_t xcd) {
 
 int lbm_get_tiling(const lbm_solver *s, int32_t *spw, int32_t *waves, int32_t *xcd) {
     return s ? get_tiling(*s->E, spw, waves, xcd) : LBM_ERR_INVALID_ARG;
+}
+
+int lbm_set_temporal(lbm_solver *s, int32_t rows_per_tile, int32_t planes_per_chunk) {
+    if (!s || !(rows_per_tile == 0 || rows_per_tile == 4 || rows_per_tile == 8)) return LBM_ERR_INVALID_ARG;
+    if (rows_per_tile && (planes_per_chunk < 1 || planes_per_chunk > 4096)) return LBM_ERR_INVALID_ARG;
+    cl::Engine &E = *s->E;
+    E.t2_by = rows_per_tile;
+    if (rows_per_tile) E.t2_zc = planes_per_chunk;
+    E.g_valid = false;  // captured windows hold the previous form
+    return LBM_OK;
+}
+
+int lbm_get_temporal(const lbm_solver *s, int32_t *rows_per_tile, int32_t *planes_per_chunk) {
+    if (!s) return LBM_ERR_INVALID_ARG;
+    if (rows_per_tile) *rows_per_tile = s->E->t2_by;
+    if (planes_per_chunk) *planes_per_chunk = s->E->t2_zc;
+    return LBM_OK;
 }
 
 int lbm_autotune(lbm_solver *s, int32_t steps_per_trial, double *ms_best) {

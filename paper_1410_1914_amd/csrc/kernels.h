@@ -62,6 +62,19 @@ struct StepLaunch {
     int32_t single;           // 1: one instance (its constants load without waiting for the record)
 };
 
+// Two time steps per launch (one instance).  A workgroup owns one 64-voxel x range
+// (segment column s) and `by` consecutive rows in y, and marches through `zc`
+// consecutive planes in z: the first step of each plane (tile rows, the two rows
+// beside the tile in y, the voxel before and after the x range) lands in LDS, the
+// second step reads it there and writes the lattice.
+struct Step2Launch {
+    int32_t by;               // rows per tile: 4 or 8
+    int32_t zc;               // planes per chunk
+    int32_t nty, ncz;         // tiles in y, chunks in z
+    int32_t nblk;             // nsx * nty * ncz workgroups
+    int32_t xcd;              // XCD-aware block order
+};
+
 struct MeasureLaunch {
     int32_t nblk;
     const int4 *blk;          // per workgroup: {instance, block within instance, blocks of instance, partial slot}
@@ -72,6 +85,9 @@ struct MeasureLaunch {
 
 hipError_t launch_step(const Lattice &L, const StepLaunch &S, bool knudsen, bool react, const float *fin,
                        float *fout, hipStream_t st);
+// Two steps from fin to fout (instance 0 of L only).
+hipError_t launch_step2(const Lattice &L, const Step2Launch &S, bool knudsen, bool react, const float *fin,
+                        float *fout, hipStream_t st);
 hipError_t launch_measure(const Lattice &L, const MeasureLaunch &M, bool react, const float *f, hipStream_t st);
 // results[i*NQ + q] from partials of blocks [base_i, base_i + count_i): ranges[i] = {base, count}
 hipError_t launch_finish(const double *partial, const int2 *ranges, int32_t ninst, double *results, hipStream_t st);

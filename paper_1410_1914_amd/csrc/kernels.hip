@@ -104,43 +104,57 @@ __device__ __forceinline__ void gather(const SegRec &R, __amdgpu_buffer_rsrc_t r
     r[4] = ld(rin, act ? o4 : kOutOfRange, 0);
     r[5] = ld(rin, act ? o5 : kOutOfRange, 0);
     r[6] = ld(rin, act ? o6 : kOutOfRange, 0);
-    if (KNUDSEN) r[7] = ld(rom, act ? 4u * j : kOutOfRange, 0);
+    r[7] = KNUDSEN ? ld(rom, act ? 4u * j : kOutOfRange, 0) : 0.f;
 }
 
-// Collide phase of one segment: FP64 collision with the sink, seven FP32 stores.
-template <bool KNUDSEN, bool REACT>
-__device__ __forceinline__ void collide_store(const SegRec &R, const InstDev &I, __amdgpu_buffer_rsrc_t rout,
-                                              int lane, const float (&r)[8], uint32_t j4) {
-    const int x = (int)R.s * 64 + lane;
-    double om;
-    if (KNUDSEN)
-        om = (double)r[7];
-    else
-        om = (double)__uint_as_float(lane_sel(R.ion, __float_as_uint(I.om_ion), __float_as_uint(I.om_pore)));
+// Collision of one voxel in FP64 from its seven pulled stored values: x faces
+// (anti-bounce-back Dirichlet at the inlet; Dirichlet or zero-gradient outlet),
+// re-referencing of the +-x pulls to this voxel's shift, the sink -k n C, and the
+// seven post-collision values rounded once to FP32.  left/right: the x -+ 1
+// neighbour is fluid; n: catalyst face-neighbour count of a reacting voxel.
+template <bool REACT>
+__device__ __forceinline__ void collide7(const InstDev &I, int x, bool left, bool right, double om, int n,
+                                         const float (&r)[8], float (&o)[7]) {
     const double p0 = r[0], p3 = r[3], p4 = r[4], p5 = r[5], p6 = r[6];
-    // +-x: re-reference to this voxel's shift; x faces: anti-bounce-back Dirichlet at
-    // the inlet, Dirichlet (anti-bounce-back) or zero-gradient (bounce-back) outlet
-    double p1 = bit(R.left, lane) ? (double)r[1] + I.pull_dx : (double)r[1];
-    double p2 = bit(R.right, lane) ? (double)r[2] - I.pull_dx : (double)r[2];
+    double p1 = left ? (double)r[1] + I.pull_dx : (double)r[1];
+    double p2 = right ? (double)r[2] - I.pull_dx : (double)r[2];
     if (x == 0) p1 = I.abb_in - (double)r[1];
     if (!REACT && x == I.nx - 1) p2 = I.abb_out - (double)r[2];
 
     const double Cs = ((p0 + p1) + (p2 + p3)) + ((p4 + p5) + p6);  // C - c_sh(x), exact
     double s0 = 0.0, s1 = 0.0;
     if (REACT) {
-        const double kn = I.k * (double)react_n(R, lane);
+        const double kn = I.k * (double)n;
         const double sink = -kn * (Cs + (I.sh0 - I.slope * (double)x));
         s0 = I.w0 * sink;
         s1 = I.w1 * sink;
     }
     const double e0 = I.w0 * Cs, e1 = I.w1 * Cs;
-    st((float)(fma(om, e0 - p0, p0) + s0), rout, j4, 0u);
-    st((float)(fma(om, e1 - p1, p1) + s1), rout, j4, 256u);
-    st((float)(fma(om, e1 - p2, p2) + s1), rout, j4, 512u);
-    st((float)(fma(om, e1 - p3, p3) + s1), rout, j4, 768u);
-    st((float)(fma(om, e1 - p4, p4) + s1), rout, j4, 1024u);
-    st((float)(fma(om, e1 - p5, p5) + s1), rout, j4, 1280u);
-    st((float)(fma(om, e1 - p6, p6) + s1), rout, j4, 1536u);
+    o[0] = (float)(fma(om, e0 - p0, p0) + s0);
+    o[1] = (float)(fma(om, e1 - p1, p1) + s1);
+    o[2] = (float)(fma(om, e1 - p2, p2) + s1);
+    o[3] = (float)(fma(om, e1 - p3, p3) + s1);
+    o[4] = (float)(fma(om, e1 - p4, p4) + s1);
+    o[5] = (float)(fma(om, e1 - p5, p5) + s1);
+    o[6] = (float)(fma(om, e1 - p6, p6) + s1);
+}
+
+// Relaxation rate of a lane: stored per voxel (Knudsen) or from the phase.
+template <bool KNUDSEN>
+__device__ __forceinline__ double lane_omega(const SegRec &R, const InstDev &I, float stored) {
+    if (KNUDSEN) return (double)stored;
+    return (double)__uint_as_float(lane_sel(R.ion, __float_as_uint(I.om_ion), __float_as_uint(I.om_pore)));
+}
+
+// Collide phase of one segment: FP64 collision with the sink, seven FP32 stores.
+template <bool KNUDSEN, bool REACT>
+__device__ __forceinline__ void collide_store(const SegRec &R, const InstDev &I, __amdgpu_buffer_rsrc_t rout,
+                                              int lane, const float (&r)[8], uint32_t j4) {
+    float o[7];
+    collide7<REACT>(I, (int)R.s * 64 + lane, bit(R.left, lane), bit(R.right, lane), lane_omega<KNUDSEN>(R, I, r[7]),
+                    REACT ? react_n(R, lane) : 0, r, o);
+#pragma unroll
+    for (int i = 0; i < 7; ++i) st(o[i], rout, j4, 256u * i);
 }
 
 // Fused pull stream + collide.  Each wave takes SPW consecutive list entries (row
@@ -173,6 +187,142 @@ __global__ __launch_bounds__(WAVES * 64) void k_step(Lattice L, StepLaunch S, co
 #pragma unroll
     for (int k = 0; k < SPW; ++k) {
         if (act[k]) collide_store<KNUDSEN, REACT>(*R[k], *Ip[k], rout, lane, r[k], j4[k]);
+    }
+}
+
+// ------------------------------------------------------------------ two steps per pass
+
+// The voxel just outside a segment in x (lane 63 of segment s - 1, or lane 0 of
+// segment s + 1), one per lane: the gather and collision of one step with the
+// masks read per lane.  Returns the post-collision value that streams back into
+// segment s (+x population from the left voxel, -x from the right one).
+template <bool KNUDSEN, bool REACT>
+__device__ __forceinline__ float step1_edge(const SegRec *__restrict__ Rn, int side, int sn, const InstDev &I,
+                                            __amdgpu_buffer_rsrc_t rin, __amdgpu_buffer_rsrc_t rom) {
+    const int ln = side ? 0 : 63;
+    const uint64_t below = side ? 0ull : ~0ull >> 1;  // lanes under ln
+    const uint64_t m = Rn->m, left = Rn->left, right = Rn->right;
+    const uint32_t j = Rn->pre + (uint32_t)__popcll(m & below);
+    const uint32_t a = pbyte(j);
+    uint32_t o[7];
+    o[0] = a;
+    o[1] = bit(left, ln) ? pbyte(j - 1u) + 256u : a + 512u;
+    o[2] = bit(right, ln) ? pbyte(j + 1u) + 512u : a + 256u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint64_t nb = Rn->nb[k];
+        const uint32_t own = a + 256u * (uint32_t)(k ^ 1) + 768u;  // bounce-back: the opposite population
+        o[3 + k] = bit(nb, ln) ? pbyte(Rn->pnb[k] + (uint32_t)__popcll(nb & below)) + 768u + 256u * (uint32_t)k : own;
+    }
+    float r[8];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) r[i] = ld(rin, o[i], 0);
+    r[7] = KNUDSEN ? ld(rom, 4u * j, 0) : 0.f;
+    const double om = KNUDSEN ? (double)r[7] : (double)(bit(Rn->ion, ln) ? I.om_ion : I.om_pore);
+    const int n = REACT ? bit(Rn->n0, ln) + 2 * bit(Rn->n1, ln) + 4 * bit(Rn->n2, ln) : 0;
+    float out[7];
+    collide7<REACT>(I, sn * 64 + ln, bit(left, ln), bit(right, ln), om, n, r, out);
+    return side ? out[2] : out[1];
+}
+
+// Two steps per launch for one instance (see Step2Launch).  Block b (after the
+// XCD renumbering) owns segment column s = b % nsx, rows y0 .. y0 + nr - 1 and
+// planes z_lo .. z_hi - 1.  Iteration p computes the first step of plane p
+// (p = z_lo - 1 .. z_hi, planes wrap periodically) into LDS, then the second
+// step of plane p - 1 from LDS into fout.  Waves 0 .. BY - 1 own one tile row
+// each; wave BY takes the row before the tile and the x-edge voxels, wave
+// BY + 1 the row after it.  Every value entering the second step is the FP32
+// value the single-step kernel would have stored, so two launches of that
+// kernel and one of this one give bit-identical lattices.
+template <int BY, bool KNUDSEN, bool REACT>
+__global__ __launch_bounds__((BY + 2) * 64) void k_step2(Lattice L, Step2Launch S, const float *__restrict__ fin,
+                                                         float *__restrict__ fout) {
+    __shared__ float full[2][BY][8][64];  // first step of a plane: 7 populations (+ 1/tau) per tile row
+    __shared__ float zm[BY][64];          // +z population of the plane below the one in its second step
+    __shared__ float yh[2][2][64];        // +y population of row y0 - 1, -y population of row y0 + nr
+    __shared__ float xh[2][BY][2];        // +x population of x0 - 1, -x population of x0 + 64, per tile row
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const InstDev &I = L.inst[0];
+    const int nsx = I.nsx, ny = I.ny, nz = I.nz;
+    const int lb = logical_block(blockIdx.x, S.nblk, S.xcd);
+    const int s = lb % nsx, t = lb / nsx;
+    const int y0 = (t % S.nty) * BY, nr = min(BY, ny - y0);
+    const int z_lo = (t / S.nty) * S.zc, z_hi = min(z_lo + S.zc, nz);
+    const bool whole_y = nr == ny;  // the tile's own rows are its y neighbours
+    const uint32_t S4 = 4u * L.stride;
+    const __amdgpu_buffer_rsrc_t rin = rsrc(fin, 7u * S4), rout = rsrc(fout, 7u * S4);
+    const __amdgpu_buffer_rsrc_t rom = rsrc(L.omega, KNUDSEN ? S4 : 0u);
+    const int64_t row_stride = nsx, plane_stride = (int64_t)ny * nsx;
+
+    for (int p = z_lo - 1; p <= z_hi; ++p) {
+        const int ps = p & 1;
+        const int zp = p < 0 ? p + nz : (p >= nz ? p - nz : p);
+        // ---- first step of plane p
+        int row = -1;  // y of the row this wave steps, if any
+        if (wave < nr) row = y0 + wave;
+        else if (!whole_y && wave == BY) row = y0 == 0 ? ny - 1 : y0 - 1;
+        else if (!whole_y && wave == BY + 1) row = y0 + nr == ny ? 0 : y0 + nr;
+        if (row >= 0) {
+            const SegRec &R = L.rec[zp * plane_stride + row * row_stride + s];
+            const bool act = bit(R.m, lane);
+            float r[8];
+            uint32_t j4;
+            gather<KNUDSEN>(R, rin, rom, act, r, j4);
+            if (act) {
+                float o[7];
+                collide7<REACT>(I, s * 64 + lane, bit(R.left, lane), bit(R.right, lane),
+                                lane_omega<KNUDSEN>(R, I, r[7]), REACT ? react_n(R, lane) : 0, r, o);
+                if (wave < BY) {
+#pragma unroll
+                    for (int i = 0; i < 7; ++i) full[ps][wave][i][lane] = o[i];
+                    if (KNUDSEN) full[ps][wave][7][lane] = r[7];
+                } else {
+                    yh[ps][wave - BY][lane] = wave == BY ? o[3] : o[4];
+                }
+            }
+        }
+        if (wave == BY && lane < 2 * nr) {  // x-edge voxels of the tile rows: lane = 2 * tile row + side
+            const int tr = lane >> 1, side = lane & 1;
+            const int sn = side ? s + 1 : s - 1;
+            if (sn >= 0 && sn < nsx) {
+                const SegRec *Rn = &L.rec[zp * plane_stride + (y0 + tr) * row_stride + sn];
+                if (bit(Rn->m, side ? 0 : 63)) xh[ps][tr][side] = step1_edge<KNUDSEN, REACT>(Rn, side, sn, I, rin, rom);
+            }
+        }
+        __syncthreads();
+        // ---- second step of plane q = p - 1; then keep its +z population for plane q + 1
+        const int q = p - 1;
+        if (q >= z_lo - 1 && wave < nr) {
+            const int qs = q & 1;
+            const int zq = q < 0 ? q + nz : q;
+            const SegRec &R = L.rec[zq * plane_stride + (y0 + wave) * row_stride + s];
+            const bool act = bit(R.m, lane);
+            if (q >= z_lo && act) {
+                const float(&F)[BY][8][64] = full[qs];
+                float r[8];
+                r[0] = F[wave][0][lane];
+                r[1] = bit(R.left, lane) ? (lane > 0 ? F[wave][1][lane - 1] : xh[qs][wave][0]) : F[wave][2][lane];
+                r[2] = bit(R.right, lane) ? (lane < 63 ? F[wave][2][lane + 1] : xh[qs][wave][1]) : F[wave][1][lane];
+                r[3] = bit(R.nb[0], lane)
+                           ? (wave > 0 ? F[wave - 1][3][lane] : (whole_y ? F[nr - 1][3][lane] : yh[qs][0][lane]))
+                           : F[wave][4][lane];
+                r[4] = bit(R.nb[1], lane)
+                           ? (wave + 1 < nr ? F[wave + 1][4][lane] : (whole_y ? F[0][4][lane] : yh[qs][1][lane]))
+                           : F[wave][3][lane];
+                r[5] = bit(R.nb[2], lane) ? zm[wave][lane] : F[wave][6][lane];
+                r[6] = bit(R.nb[3], lane) ? full[ps][wave][6][lane] : F[wave][5][lane];
+                r[7] = KNUDSEN ? F[wave][7][lane] : 0.f;
+                float o[7];
+                collide7<REACT>(I, s * 64 + lane, bit(R.left, lane), bit(R.right, lane),
+                                lane_omega<KNUDSEN>(R, I, r[7]), REACT ? react_n(R, lane) : 0, r, o);
+                const uint32_t j4 = pbyte(R.pre + (uint32_t)mbcnt64(R.m));
+#pragma unroll
+                for (int i = 0; i < 7; ++i) st(o[i], rout, j4, 256u * i);
+            }
+            if (act) zm[wave][lane] = full[qs][wave][5][lane];
+        }
+        __syncthreads();
     }
 }
 
@@ -379,6 +529,35 @@ hipError_t launch_step(const Lattice &L, const StepLaunch &S, bool knudsen, bool
         case 2: return launch_step_w<2>(L, S, knudsen, react, fin, fout, st);
         case 4: return launch_step_w<4>(L, S, knudsen, react, fin, fout, st);
         case 8: return launch_step_w<8>(L, S, knudsen, react, fin, fout, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+namespace {
+template <int BY>
+hipError_t launch_step2_t(const Lattice &L, const Step2Launch &S, bool kn, bool re, const float *fin, float *fout,
+                          hipStream_t st) {
+    const dim3 grid(S.nblk), block((BY + 2) * 64);
+    (void)hipGetLastError();
+    if (kn && re) {
+        hipLaunchKernelGGL((k_step2<BY, true, true>), grid, block, 0, st, L, S, fin, fout);
+    } else if (kn) {
+        hipLaunchKernelGGL((k_step2<BY, true, false>), grid, block, 0, st, L, S, fin, fout);
+    } else if (re) {
+        hipLaunchKernelGGL((k_step2<BY, false, true>), grid, block, 0, st, L, S, fin, fout);
+    } else {
+        hipLaunchKernelGGL((k_step2<BY, false, false>), grid, block, 0, st, L, S, fin, fout);
+    }
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_step2(const Lattice &L, const Step2Launch &S, bool knudsen, bool react, const float *fin,
+                        float *fout, hipStream_t st) {
+    if (S.nblk <= 0) return hipSuccess;
+    switch (S.by) {
+        case 4: return launch_step2_t<4>(L, S, knudsen, react, fin, fout, st);
+        case 8: return launch_step2_t<8>(L, S, knudsen, react, fin, fout, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -91,6 +91,8 @@ SIGNATURES = {
     "lbm_set_tiling": ([_P, c_int32, c_int32, c_int32], c_int32),
     "lbm_get_tiling": ([_P, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32), ctypes.POINTER(c_int32)], c_int32),
     "lbm_autotune": ([_P, c_int32, ctypes.POINTER(c_double)], c_int32),
+    "lbm_set_temporal": ([_P, c_int32, c_int32], c_int32),
+    "lbm_get_temporal": ([_P, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32)], c_int32),
     "lbm_deff": ([_P, ctypes.POINTER(c_double)], c_int32),
     "lbm_reaction_rate": ([_P, ctypes.POINTER(c_double), ctypes.POINTER(c_double)], c_int32),
     "lbm_concentration": ([_P, _P], c_int32),
@@ -269,6 +271,16 @@ def lbm_autotune(h, steps_per_trial: int = 20):
     ms = c_double()
     _check("lbm_autotune", load().lbm_autotune(h, steps_per_trial, ctypes.byref(ms)))
     return ms.value
+
+
+def lbm_set_temporal(h, rows_per_tile, planes_per_chunk):
+    return _check("lbm_set_temporal", load().lbm_set_temporal(h, rows_per_tile, planes_per_chunk))
+
+
+def lbm_get_temporal(h):
+    a, b = c_int32(), c_int32()
+    _check("lbm_get_temporal", load().lbm_get_temporal(h, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
 
 
 def lbm_deff(h):
@@ -495,6 +507,13 @@ class Solver:
 
     def tiling(self):
         return lbm_get_tiling(self.h)
+
+    def set_temporal(self, rows_per_tile, planes_per_chunk=32):
+        """Two steps per launch (rows_per_tile 4 or 8), or one (0)."""
+        return lbm_set_temporal(self.h, rows_per_tile, planes_per_chunk)
+
+    def temporal(self):
+        return lbm_get_temporal(self.h)
 
     def autotune(self, steps_per_trial=20):
         return lbm_autotune(self.h, steps_per_trial)

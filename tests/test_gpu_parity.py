@@ -236,6 +236,37 @@ def test_every_tiling_gives_identical_steps(hip, kind, seed, shape, mode, kw):
             assert np.array_equal(got[:, act], ref[:, act]), t
 
 
+TEMPORAL = [(4, 1), (4, 3), (8, 2), (8, 5), (4, 64), (8, 4096)]
+
+
+@pytest.mark.parametrize("kind,seed,shape,mode,kw", STEP_CASES)
+def test_two_step_launches_match_single_steps(hip, kind, seed, shape, mode, kw):
+    """Two steps per launch (first step of each plane kept in LDS) against one step
+    per launch: bit-identical populations after even and odd step counts, for tiles
+    of 4 and 8 rows and chunks from one plane to the whole z extent (rows and planes
+    that wrap onto the tile itself, x ranges with and without neighbours)."""
+    import torch
+
+    ph = _phase(kind, seed, shape)
+    prob, s = _both(hip, ph, mode, **kw)
+    f0 = torch.from_numpy(O.collide(prob, _random_pre(prob, seed + 100)).astype(np.float32)).reshape((7,) + s.shape)
+    act = prob.active
+    ref = {}
+    s.set_temporal(0)
+    for n in (2, 5):
+        s.set_populations(f0)
+        s.step(n)
+        ref[n] = s.populations().cpu().numpy()
+    for by, zc in TEMPORAL:
+        s.set_temporal(by, zc)
+        assert s.temporal() == (by, zc)
+        for n in (2, 5):
+            s.set_populations(f0)
+            s.step(n)
+            got = s.populations().cpu().numpy()
+            assert np.array_equal(got[:, act], ref[n][:, act]), (by, zc, n)
+
+
 def _advance(prob, f, n):
     for _ in range(n):
         f = O.step(prob, f)
@@ -287,16 +318,17 @@ def test_batch_groups_reach_the_same_answers(hip):
         assert b.reaction_rate(i)[1] == pytest.approx(together.reaction_rate(i)[1], rel=1e-5)
 
 
-def test_pt_cl_64_matches_the_oracle_fixed_point(hip):
-    """Steady D_eff/D0 and reaction rate of 64^3 Pt catalyst layers (Knudsen,
-    ionomer 1e-3 D0) against the oracle's exact fixed point (BiCGStab to 1e-11,
-    stored in tests/golden/oracle_pt_cl_64.json by tests/golden/make_golden.py)."""
+def test_pt_cl_slab_matches_the_oracle_fixed_point(hip):
+    """Steady D_eff/D0 and reaction rate of four-phase Pt catalyst layers (Knudsen,
+    ionomer 1e-3 D0; 32 x 32 x 130 slabs, so every row spans two full 64-voxel
+    segments and a ragged tail) against the oracle's exact fixed point (sparse LU,
+    stored in tests/golden/oracle_pt_cl_slab.json by tests/golden/make_golden.py)."""
     import json
     import os
 
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_pt_cl_64.json")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_pt_cl_slab.json")
     if not os.path.exists(path):
-        pytest.skip("stored oracle values not generated (python tests/golden/make_golden.py oracle_pt_cl_64.json)")
+        pytest.skip("stored oracle values not generated (python tests/golden/make_golden.py oracle_pt_cl_slab.json)")
     with open(path) as fh:
         cases = json.load(fh)["cases"]
     for c in cases:
@@ -308,6 +340,6 @@ def test_pt_cl_64_matches_the_oracle_fixed_point(hip):
             got, want = s.deff()[1], c["deff"]
         else:
             got, want = s.reaction_rate()[1], c["rate"]
-        print(f"[64^3] mode {c['mode']}: GPU {got:.10e} oracle {want:.10e} rel {got / want - 1:+.2e} "
+        print(f"[slab] seed {c['seed']} mode {c['mode']}: GPU {got:.10e} oracle {want:.10e} rel {got / want - 1:+.2e} "
               f"({info.steps} steps)", flush=True)
         assert got == pytest.approx(want, rel=STEADY_RTOL)
