@@ -18,8 +18,9 @@ Also reported on the same JSON line:
     sequential single solves vs one batched solve, with the error against the
     stored oracle values;
   * warm_start: learned start vs cold start (C = 0) and vs a linear-profile start
-    on fresh 192^3 Pt catalyst layers (reactive problem; ``--warm-deff`` adds the
-    slower effective-diffusivity problem), when the trained networks exist;
+    on fresh Pt catalyst layers, when the trained networks exist: the reactive
+    problem at 192^3 and the effective-diffusivity problem at 96^3 (at 192^3, whose
+    cold solve alone takes ~2.5 M steps, with ``--warm-deff``);
   * batch64 (``--batch64``): 64 uneven reactive structures, one batched solve vs
     64 sequential single solves.
 """
@@ -50,7 +51,7 @@ def parse():
     ap.add_argument("--no-solves", action="store_true", help="skip the 32^3 solves/s legs")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-start leg")
     ap.add_argument("--warm-deff", action="store_true",
-                    help="also run the effective-diffusivity warm-start comparison (several minutes)")
+                    help="run the effective-diffusivity warm-start comparison at 192^3 instead of 96^3 (several minutes)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU time budget of the oracle sample")
     ap.add_argument("--no-tune", action="store_true", help="keep the default tiling (no autotuning)")
     ap.add_argument("--batch64", action="store_true",
@@ -287,13 +288,13 @@ def batch64_leg(lbm, insts):
 
 
 def warm_leg(args):
-    """Learned start vs cold start (and vs a linear-profile start) at 192^3: the
-    reactive workload by default; the effective-diffusivity workload, whose cold
-    solve alone takes ~2.5 M steps (minutes), with --warm-deff."""
+    """Learned start vs cold start (and vs a linear-profile start): the reactive
+    workload at 192^3, and the effective-diffusivity workload at 96^3, or at 192^3
+    (cold solve alone ~2.5 M steps, minutes) with --warm-deff."""
     from paper_1410_1914_amd import warmstart
 
-    names = ("react", "deff") if args.warm_deff else ("react",)
-    return warmstart.bench_warm_vs_cold(names)
+    shapes = {} if args.warm_deff else {"deff": (96, 96, 96)}
+    return warmstart.bench_warm_vs_cold(("react", "deff"), shapes)
 
 
 def main():
