@@ -192,48 +192,90 @@ __global__ __launch_bounds__(WAVES * 64) void k_step(Lattice L, StepLaunch S, co
 
 // ------------------------------------------------------------------ two steps per pass
 
-// The voxel just outside a segment in x (lane 63 of segment s - 1, or lane 0 of
-// segment s + 1), one per lane: the gather and collision of one step with the
-// masks read per lane.  Returns the post-collision value that streams back into
-// segment s (+x population from the left voxel, -x from the right one).
-template <bool KNUDSEN, bool REACT>
-__device__ __forceinline__ float step1_edge(const SegRec *__restrict__ Rn, int side, int sn, const InstDev &I,
-                                            __amdgpu_buffer_rsrc_t rin, __amdgpu_buffer_rsrc_t rom) {
-    const int ln = side ? 0 : 63;
-    const uint64_t below = side ? 0ull : ~0ull >> 1;  // lanes under ln
-    const uint64_t m = Rn->m, left = Rn->left, right = Rn->right;
-    const uint32_t j = Rn->pre + (uint32_t)__popcll(m & below);
+// Per-lane bits of one voxel kept between issuing its loads and its collisions.
+enum : uint32_t { F_ACT = 1u, F_LEFT = 2u, F_RIGHT = 4u, F_NB = 8u /* 4 bits */, F_ION = 128u, F_N = 8u /* shift */ };
+
+__device__ __forceinline__ uint32_t lane_flags(const SegRec &R, int lane) {
+    return (uint32_t)bit(R.m, lane) | (uint32_t)bit(R.left, lane) << 1 | (uint32_t)bit(R.right, lane) << 2 |
+           (uint32_t)bit(R.nb[0], lane) << 3 | (uint32_t)bit(R.nb[1], lane) << 4 | (uint32_t)bit(R.nb[2], lane) << 5 |
+           (uint32_t)bit(R.nb[3], lane) << 6 | (uint32_t)bit(R.ion, lane) << 7 | (uint32_t)react_n(R, lane) << F_N;
+}
+
+__device__ __forceinline__ double flag_omega(uint32_t fl, const InstDev &I, float stored, bool knudsen) {
+    return knudsen ? (double)stored : (double)((fl & F_ION) ? I.om_ion : I.om_pore);
+}
+
+// Workgroup barrier ordering LDS only: this wave's LDS accesses are complete,
+// its global loads and stores may still be in flight.
+__device__ __forceinline__ void sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Words of a segment record that locate lane LN's seven pulled values: read per
+// lane (each lane its own record) and issued together before any is used.
+struct EdgeRec {
+    uint64_t m, left, right, nb[4], ion, n0, n1, n2;
+    uint32_t pre, pnb[4];
+};
+
+__device__ __forceinline__ EdgeRec load_edge(const SegRec *R) {
+    EdgeRec e;
+    e.m = R->m;
+    e.left = R->left;
+    e.right = R->right;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        e.nb[k] = R->nb[k];
+        e.pnb[k] = R->pnb[k];
+    }
+    e.ion = R->ion;
+    e.n0 = R->n0;
+    e.n1 = R->n1;
+    e.n2 = R->n2;
+    e.pre = R->pre;
+    return e;
+}
+
+// Gather of lane LN (63: the voxel before a segment's x range, 0: the one after
+// it) of the record e, one record per lane; returns the lane's flags (0: none).
+template <bool KNUDSEN, int LN>
+__device__ __forceinline__ uint32_t gather_edge(const EdgeRec &e, bool valid, __amdgpu_buffer_rsrc_t rin,
+                                                __amdgpu_buffer_rsrc_t rom, float (&r)[8]) {
+    constexpr uint64_t below = LN ? ~0ull >> (64 - LN) : 0ull;  // lanes under LN
+    const bool act = valid && bit(e.m, LN);
+    const uint32_t j = e.pre + (uint32_t)__popcll(e.m & below);
     const uint32_t a = pbyte(j);
     uint32_t o[7];
     o[0] = a;
-    o[1] = bit(left, ln) ? pbyte(j - 1u) + 256u : a + 512u;
-    o[2] = bit(right, ln) ? pbyte(j + 1u) + 512u : a + 256u;
+    o[1] = bit(e.left, LN) ? pbyte(j - 1u) + 256u : a + 512u;
+    o[2] = bit(e.right, LN) ? pbyte(j + 1u) + 512u : a + 256u;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const uint64_t nb = Rn->nb[k];
         const uint32_t own = a + 256u * (uint32_t)(k ^ 1) + 768u;  // bounce-back: the opposite population
-        o[3 + k] = bit(nb, ln) ? pbyte(Rn->pnb[k] + (uint32_t)__popcll(nb & below)) + 768u + 256u * (uint32_t)k : own;
+        o[3 + k] = bit(e.nb[k], LN) ? pbyte(e.pnb[k] + (uint32_t)__popcll(e.nb[k] & below)) + 768u + 256u * (uint32_t)k
+                                    : own;
     }
-    float r[8];
 #pragma unroll
-    for (int i = 0; i < 7; ++i) r[i] = ld(rin, o[i], 0);
-    r[7] = KNUDSEN ? ld(rom, 4u * j, 0) : 0.f;
-    const double om = KNUDSEN ? (double)r[7] : (double)(bit(Rn->ion, ln) ? I.om_ion : I.om_pore);
-    const int n = REACT ? bit(Rn->n0, ln) + 2 * bit(Rn->n1, ln) + 4 * bit(Rn->n2, ln) : 0;
-    float out[7];
-    collide7<REACT>(I, sn * 64 + ln, bit(left, ln), bit(right, ln), om, n, r, out);
-    return side ? out[2] : out[1];
+    for (int i = 0; i < 7; ++i) r[i] = ld(rin, act ? o[i] : kOutOfRange, 0);
+    r[7] = KNUDSEN ? ld(rom, act ? 4u * j : kOutOfRange, 0) : 0.f;
+    const uint32_t fl = F_ACT | (uint32_t)bit(e.left, LN) << 1 | (uint32_t)bit(e.right, LN) << 2 |
+                        (uint32_t)bit(e.ion, LN) << 7 |
+                        (uint32_t)(bit(e.n0, LN) + 2 * bit(e.n1, LN) + 4 * bit(e.n2, LN)) << F_N;
+    return act ? fl : 0u;
 }
 
 // Two steps per launch for one instance (see Step2Launch).  Block b (after the
 // XCD renumbering) owns segment column s = b % nsx, rows y0 .. y0 + nr - 1 and
-// planes z_lo .. z_hi - 1.  Iteration p computes the first step of plane p
-// (p = z_lo - 1 .. z_hi, planes wrap periodically) into LDS, then the second
-// step of plane p - 1 from LDS into fout.  Waves 0 .. BY - 1 own one tile row
-// each; wave BY takes the row before the tile and the x-edge voxels, wave
-// BY + 1 the row after it.  Every value entering the second step is the FP32
-// value the single-step kernel would have stored, so two launches of that
-// kernel and one of this one give bit-identical lattices.
+// planes z_lo .. z_hi - 1.  Iteration p completes the first step of plane p
+// (p = z_lo - 1 .. z_hi; planes wrap periodically) into LDS, issues the loads of
+// plane p + 1, and performs the second step of plane p - 1 from LDS into fout.
+// Waves 0 .. BY - 1 own one tile row each; wave BY steps the row before the
+// tile and the voxel before each tile row's x range, wave BY + 1 the row after
+// the tile and the voxel after each x range.  Every value entering the second
+// step is the FP32 value the single-step kernel would have stored, so one launch
+// of this kernel and two of that one give bit-identical lattices.
 template <int BY, bool KNUDSEN, bool REACT>
 __global__ __launch_bounds__((BY + 2) * 64) void k_step2(Lattice L, Step2Launch S, const float *__restrict__ fin,
                                                          float *__restrict__ fout) {
@@ -250,79 +292,102 @@ __global__ __launch_bounds__((BY + 2) * 64) void k_step2(Lattice L, Step2Launch 
     const int y0 = (t % S.nty) * BY, nr = min(BY, ny - y0);
     const int z_lo = (t / S.nty) * S.zc, z_hi = min(z_lo + S.zc, nz);
     const bool whole_y = nr == ny;  // the tile's own rows are its y neighbours
+    const bool has_l = s > 0, has_r = s + 1 < nsx;
     const uint32_t S4 = 4u * L.stride;
     const __amdgpu_buffer_rsrc_t rin = rsrc(fin, 7u * S4), rout = rsrc(fout, 7u * S4);
     const __amdgpu_buffer_rsrc_t rom = rsrc(L.omega, KNUDSEN ? S4 : 0u);
-    const int64_t row_stride = nsx, plane_stride = (int64_t)ny * nsx;
+    const int64_t plane_stride = (int64_t)ny * nsx;
 
+    // This wave's row: 0 tile row, 1 the row before the tile, 2 the row after it, -1 none.
+    // Waves BY and BY + 1 also step the voxels just before (x0 - 1) and just after
+    // (x0 + 64) the x range of every tile row, lane tr for tile row tr.
+    int kind = -1, row = 0;
+    if (wave < nr) {
+        kind = 0;
+        row = y0 + wave;
+    } else if (!whole_y && wave == BY) {
+        kind = 1;
+        row = y0 == 0 ? ny - 1 : y0 - 1;
+    } else if (!whole_y && wave == BY + 1) {
+        kind = 2;
+        row = y0 + nr == ny ? 0 : y0 + nr;
+    }
+    const int side = wave - BY;  // 0 / 1 on the edge waves
+    const bool edge_wave = side >= 0 && (side ? has_r : has_l);
+    const bool edge_lane = edge_wave && lane < nr;
+    const SegRec *Rrow = L.rec + (int64_t)row * nsx + s;
+    const SegRec *Redge = L.rec + (int64_t)(y0 + (edge_lane ? lane : 0)) * nsx + (side == 1 ? s + 1 : s - 1);
+
+    // loads in flight for the first step of the next plane
+    float g[8], ge[8];
+    uint32_t fl = 0, fle = 0, j4 = kOutOfRange;
+    auto issue = [&](int p) {
+        const int zp = p < 0 ? p + nz : (p >= nz ? p - nz : p);
+        EdgeRec e{};
+        if (edge_lane) e = load_edge(Redge + zp * plane_stride);
+        if (kind >= 0) {
+            const SegRec &R = Rrow[zp * plane_stride];
+            fl = lane_flags(R, lane);
+            gather<KNUDSEN>(R, rin, rom, (fl & F_ACT) != 0, g, j4);
+        }
+        if (edge_wave)
+            fle = side ? gather_edge<KNUDSEN, 0>(e, edge_lane, rin, rom, ge)
+                       : gather_edge<KNUDSEN, 63>(e, edge_lane, rin, rom, ge);
+    };
+    if (kind >= 0 || edge_wave) issue(z_lo - 1);
+
+    uint32_t flq = 0, j4q = kOutOfRange;  // the plane in its second step
     for (int p = z_lo - 1; p <= z_hi; ++p) {
         const int ps = p & 1;
-        const int zp = p < 0 ? p + nz : (p >= nz ? p - nz : p);
-        // ---- first step of plane p
-        int row = -1;  // y of the row this wave steps, if any
-        if (wave < nr) row = y0 + wave;
-        else if (!whole_y && wave == BY) row = y0 == 0 ? ny - 1 : y0 - 1;
-        else if (!whole_y && wave == BY + 1) row = y0 + nr == ny ? 0 : y0 + nr;
-        if (row >= 0) {
-            const SegRec &R = L.rec[zp * plane_stride + row * row_stride + s];
-            const bool act = bit(R.m, lane);
-            float r[8];
-            uint32_t j4;
-            gather<KNUDSEN>(R, rin, rom, act, r, j4);
-            if (act) {
-                float o[7];
-                collide7<REACT>(I, s * 64 + lane, bit(R.left, lane), bit(R.right, lane),
-                                lane_omega<KNUDSEN>(R, I, r[7]), REACT ? react_n(R, lane) : 0, r, o);
-                if (wave < BY) {
+        // ---- first step of plane p, from the loads issued one iteration ago
+        if (kind >= 0 && (fl & F_ACT)) {
+            float o[7];
+            collide7<REACT>(I, s * 64 + lane, (fl & F_LEFT) != 0, (fl & F_RIGHT) != 0,
+                            flag_omega(fl, I, g[7], KNUDSEN), REACT ? (int)(fl >> F_N) : 0, g, o);
+            if (kind == 0) {
 #pragma unroll
-                    for (int i = 0; i < 7; ++i) full[ps][wave][i][lane] = o[i];
-                    if (KNUDSEN) full[ps][wave][7][lane] = r[7];
-                } else {
-                    yh[ps][wave - BY][lane] = wave == BY ? o[3] : o[4];
-                }
+                for (int i = 0; i < 7; ++i) full[ps][wave][i][lane] = o[i];
+                if (KNUDSEN) full[ps][wave][7][lane] = g[7];
+            } else {
+                yh[ps][kind - 1][lane] = kind == 1 ? o[3] : o[4];
             }
         }
-        if (wave == BY && lane < 2 * nr) {  // x-edge voxels of the tile rows: lane = 2 * tile row + side
-            const int tr = lane >> 1, side = lane & 1;
-            const int sn = side ? s + 1 : s - 1;
-            if (sn >= 0 && sn < nsx) {
-                const SegRec *Rn = &L.rec[zp * plane_stride + (y0 + tr) * row_stride + sn];
-                if (bit(Rn->m, side ? 0 : 63)) xh[ps][tr][side] = step1_edge<KNUDSEN, REACT>(Rn, side, sn, I, rin, rom);
-            }
+        if (fle) {  // x0 - 1 streams +x into its tile row, x0 + 64 streams -x
+            float o[7];
+            collide7<REACT>(I, side ? (s + 1) * 64 : s * 64 - 1, (fle & F_LEFT) != 0, (fle & F_RIGHT) != 0,
+                            flag_omega(fle, I, ge[7], KNUDSEN), REACT ? (int)(fle >> F_N) : 0, ge, o);
+            xh[ps][lane][side] = side ? o[2] : o[1];
         }
-        __syncthreads();
+        const uint32_t flp = fl, j4p = j4;
+        if ((kind >= 0 || edge_wave) && p < z_hi) issue(p + 1);
+        sync_lds();
         // ---- second step of plane q = p - 1; then keep its +z population for plane q + 1
-        const int q = p - 1;
-        if (q >= z_lo - 1 && wave < nr) {
-            const int qs = q & 1;
-            const int zq = q < 0 ? q + nz : q;
-            const SegRec &R = L.rec[zq * plane_stride + (y0 + wave) * row_stride + s];
-            const bool act = bit(R.m, lane);
-            if (q >= z_lo && act) {
-                const float(&F)[BY][8][64] = full[qs];
-                float r[8];
-                r[0] = F[wave][0][lane];
-                r[1] = bit(R.left, lane) ? (lane > 0 ? F[wave][1][lane - 1] : xh[qs][wave][0]) : F[wave][2][lane];
-                r[2] = bit(R.right, lane) ? (lane < 63 ? F[wave][2][lane + 1] : xh[qs][wave][1]) : F[wave][1][lane];
-                r[3] = bit(R.nb[0], lane)
-                           ? (wave > 0 ? F[wave - 1][3][lane] : (whole_y ? F[nr - 1][3][lane] : yh[qs][0][lane]))
-                           : F[wave][4][lane];
-                r[4] = bit(R.nb[1], lane)
-                           ? (wave + 1 < nr ? F[wave + 1][4][lane] : (whole_y ? F[0][4][lane] : yh[qs][1][lane]))
-                           : F[wave][3][lane];
-                r[5] = bit(R.nb[2], lane) ? zm[wave][lane] : F[wave][6][lane];
-                r[6] = bit(R.nb[3], lane) ? full[ps][wave][6][lane] : F[wave][5][lane];
-                r[7] = KNUDSEN ? F[wave][7][lane] : 0.f;
-                float o[7];
-                collide7<REACT>(I, s * 64 + lane, bit(R.left, lane), bit(R.right, lane),
-                                lane_omega<KNUDSEN>(R, I, r[7]), REACT ? react_n(R, lane) : 0, r, o);
-                const uint32_t j4 = pbyte(R.pre + (uint32_t)mbcnt64(R.m));
+        const int q = p - 1, qs = q & 1;
+        if (kind == 0 && q >= z_lo && (flq & F_ACT)) {
+            const float(&F)[BY][8][64] = full[qs];
+            float r[8];
+            r[0] = F[wave][0][lane];
+            r[1] = (flq & F_LEFT) ? (lane > 0 ? F[wave][1][lane - 1] : xh[qs][wave][0]) : F[wave][2][lane];
+            r[2] = (flq & F_RIGHT) ? (lane < 63 ? F[wave][2][lane + 1] : xh[qs][wave][1]) : F[wave][1][lane];
+            r[3] = (flq & (F_NB << 0))
+                       ? (wave > 0 ? F[wave - 1][3][lane] : (whole_y ? F[nr - 1][3][lane] : yh[qs][0][lane]))
+                       : F[wave][4][lane];
+            r[4] = (flq & (F_NB << 1))
+                       ? (wave + 1 < nr ? F[wave + 1][4][lane] : (whole_y ? F[0][4][lane] : yh[qs][1][lane]))
+                       : F[wave][3][lane];
+            r[5] = (flq & (F_NB << 2)) ? zm[wave][lane] : F[wave][6][lane];
+            r[6] = (flq & (F_NB << 3)) ? full[ps][wave][6][lane] : F[wave][5][lane];
+            r[7] = KNUDSEN ? F[wave][7][lane] : 0.f;
+            float o[7];
+            collide7<REACT>(I, s * 64 + lane, (flq & F_LEFT) != 0, (flq & F_RIGHT) != 0,
+                            flag_omega(flq, I, r[7], KNUDSEN), REACT ? (int)(flq >> F_N) : 0, r, o);
 #pragma unroll
-                for (int i = 0; i < 7; ++i) st(o[i], rout, j4, 256u * i);
-            }
-            if (act) zm[wave][lane] = full[qs][wave][5][lane];
+            for (int i = 0; i < 7; ++i) st(o[i], rout, j4q, 256u * i);
         }
-        __syncthreads();
+        if (kind == 0 && q >= z_lo - 1 && (flq & F_ACT)) zm[wave][lane] = full[qs][wave][5][lane];
+        flq = flp;
+        j4q = j4p;
+        sync_lds();
     }
 }
 
