@@ -125,8 +125,10 @@ def headline(args, lbm, structgen):
     log(f"[bench] {n}^3 NPMC: generated in {t_gen:.1f}s, preprocessed+bound in {t_prep:.1f}s, "
         f"{info.n_active} fluid voxels, {info.n_segments} segments")
     tune_ms = s.autotune(10) if not args.no_tune else float("nan")
-    tiling = s.tiling()
-    log(f"[bench] autotuned tiling (segments/wave, waves/workgroup, xcd) = {tiling}: {tune_ms*1e3:.1f} us/step")
+    tiling, temporal = s.tiling(), s.temporal()
+    spl = 2 if temporal[0] else 1  # LBM steps per stream-collide launch
+    log(f"[bench] autotuned tiling (segments/wave, waves/workgroup, xcd) = {tiling}, two-step tile "
+        f"(rows, planes) = {temporal if spl == 2 else 'off'}: {tune_ms*1e3:.1f} us/step")
     _, r0 = s.advance(0)
     for _ in range(args.warmup):
         _, r0 = s.advance(args.lbm_steps)
@@ -138,30 +140,52 @@ def headline(args, lbm, structgen):
         _, r = s.advance(args.lbm_steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    launches = r.kernel_launches - l0
+    steps_timed = r.kernel_launches - l0  # counts LBM steps
     kms = r.kernel_ms - ms0
-    updates = info.n_active * launches
+    updates = info.n_active * steps_timed
     mlups = updates / wall / 1e6
-    per_launch_s = kms / 1e3 / launches
+    per_launch_s = kms / 1e3 / steps_timed * spl
+    # one launch, of either form, must read and write the lattice once
     alg = algorithmic_bytes(info, knudsen=True, n_listed=listed_segments(s.host_fields()[0]))
     achieved = alg / per_launch_s / 1e9
-    log(f"[bench] {launches} LBM steps in {wall:.3f}s: {mlups:.0f} MLUPS; kernel mean {per_launch_s*1e6:.1f} us, "
-        f"{achieved:.0f} GB/s algorithmic")
+    log(f"[bench] {steps_timed} LBM steps in {wall:.3f}s: {mlups:.0f} MLUPS; kernel mean {per_launch_s*1e6:.1f} us "
+        f"per launch ({spl} step(s)), {achieved:.0f} GB/s algorithmic")
+    other = other_form(s, args, temporal if spl == 2 else (0, 0))
     workload = f"npmc_cl_{n}^3_react_knudsen"
     sha = kernel_source_hash()
-    tb = traffic_from_profiles(sha, workload)
+    tb = traffic_from_profiles(sha, workload) if spl == 1 else None
+    kname = (f"k_step2<{temporal[0]},true,true> (two steps per launch, Knudsen, reactive)" if spl == 2 else
+             f"k_step<{tiling[1]},{tiling[0]},true,true,true> (fused pull stream-collide, Knudsen, reactive)")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": (round(tb / per_launch_s / 1e9, 1) if tb else None),
-            "kernel": f"k_step<{tiling[1]},{tiling[0]},true,true> (fused pull stream-collide, Knudsen, reactive)",
-            "tiling": {"segs_per_wave": tiling[0], "waves_per_block": tiling[1], "xcd_remap": tiling[2]},
+            "kernel": kname, "steps_per_launch": spl,
+            "tiling": {"segs_per_wave": tiling[0], "waves_per_block": tiling[1], "xcd_remap": tiling[2],
+                       "two_step_rows": temporal[0] if spl == 2 else 0,
+                       "two_step_planes": temporal[1] if spl == 2 else 0},
             "alg_bytes_per_launch": int(alg), "mean_launch_us": round(per_launch_s * 1e6, 2),
             "kernel_source_sha": sha}
     res = {"mlups": mlups, "ms_per_step": 1e3 * wall / args.steps, "roofline": roof, "workload": workload,
+           "other_form": other,
            "n_active": info.n_active, "n_voxels": n ** 3, "prep_s": round(t_prep, 2), "gen_s": round(t_gen, 2),
-           "kernel_mlups": info.n_active / per_launch_s / 1e6,
+           "kernel_mlups": info.n_active * spl / per_launch_s / 1e6,
            "rate_per_area_after": r.rate, "steps_taken": r.steps}
     return res, ph
+
+
+def other_form(s, args, chosen):
+    """Kernel time per LBM step of the form the autotuner did not keep (two steps per
+    launch with an 8-row, 16-plane tile, or one step per launch), on the same state;
+    the chosen form is restored afterwards."""
+    alt = (0, 0) if chosen[0] else (8, 16)
+    s.set_temporal(*alt)
+    _, r0 = s.advance(args.lbm_steps)
+    _, r1 = s.advance(4 * args.lbm_steps)
+    us = (r1.kernel_ms - r0.kernel_ms) * 1e3 / (r1.kernel_launches - r0.kernel_launches)
+    s.set_temporal(*chosen)
+    form = f"two steps per launch, tile {alt[0]} rows x {alt[1]} planes" if alt[0] else "one step per launch"
+    log(f"[bench] other form ({form}): {us:.1f} us per step")
+    return {"form": form, "kernel_us_per_step": round(us, 2)}
 
 
 def cpu_baseline(args, ph, structgen):
@@ -338,6 +362,7 @@ def main():
                    "fluid_voxels": head["n_active"], "k_lat": 1e-4, "parallelism": "single GPU"},
         "roofline": head["roofline"],
         "kernel_mlups": round(head["kernel_mlups"], 1),
+        "other_form": head["other_form"],
         "prep_s": head["prep_s"],
     }
     if not args.no_cpu:
