@@ -203,8 +203,8 @@ int lbm_autotune(lbm_solver *s, int32_t steps_per_trial, double *ms_best);
 
 /* Two time steps per stream-collide launch (temporal blocking, Section 4's update
  * applied twice with the intermediate populations kept on chip).  A workgroup owns
- * one 64-voxel x range and rows_per_tile rows in y (4 or 8) and marches through
- * planes_per_chunk planes in z (1 .. 4096); the populations between the two steps
+ * one 64-voxel x range and rows_per_tile rows in y (4, 6 or 8) and marches through
+ * planes_per_chunk planes in z (1 .. 64); the populations between the two steps
  * are rounded to FP32 exactly as a stored lattice is, so the results are
  * bit-identical to two single-step launches.  rows_per_tile 0 returns to one step
  * per launch (the default); an odd step count ends with one single-step launch.

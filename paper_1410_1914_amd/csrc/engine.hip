@@ -1059,10 +1059,10 @@ static int autotune(cl::Engine &E, int32_t steps_per_trial, double *ms_best) {
     if (E.ninst == 1) {
         E.spw = bs;
         E.waves = bw;
-        const int bys[2] = {4, 8};
+        const int bys[3] = {4, 6, 8};
         const int zcs[4] = {8, 16, 32, 64};
         for (int xi = 0; xi < 2 && e == hipSuccess; ++xi)
-            for (int yi = 0; yi < 2 && e == hipSuccess; ++yi)
+            for (int yi = 0; yi < 3 && e == hipSuccess; ++yi)
                 for (int zi = 0; zi < 4 && e == hipSuccess; ++zi) {
                     E.xcd = xi;
                     E.t2_by = bys[yi];
@@ -1109,8 +1109,9 @@ int lbm_get_tiling(const lbm_solver *s, int32_t *spw, int32_t *waves, int32_t *x
 }
 
 int lbm_set_temporal(lbm_solver *s, int32_t rows_per_tile, int32_t planes_per_chunk) {
-    if (!s || !(rows_per_tile == 0 || rows_per_tile == 4 || rows_per_tile == 8)) return LBM_ERR_INVALID_ARG;
-    if (rows_per_tile && (planes_per_chunk < 1 || planes_per_chunk > 4096)) return LBM_ERR_INVALID_ARG;
+    if (!s || !(rows_per_tile == 0 || rows_per_tile == 4 || rows_per_tile == 6 || rows_per_tile == 8))
+        return LBM_ERR_INVALID_ARG;
+    if (rows_per_tile && (planes_per_chunk < 1 || planes_per_chunk > 64)) return LBM_ERR_INVALID_ARG;
     cl::Engine &E = *s->E;
     E.t2_by = rows_per_tile;
     if (rows_per_tile) E.t2_zc = planes_per_chunk;

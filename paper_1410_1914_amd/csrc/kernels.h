@@ -68,7 +68,7 @@ struct StepLaunch {
 // beside the tile in y, the voxel before and after the x range) lands in LDS, the
 // second step reads it there and writes the lattice.
 struct Step2Launch {
-    int32_t by;               // rows per tile: 4 or 8
+    int32_t by;               // rows per tile: 4, 6 or 8
     int32_t zc;               // planes per chunk
     int32_t nty, ncz;         // tiles in y, chunks in z
     int32_t nblk;             // nsx * nty * ncz workgroups

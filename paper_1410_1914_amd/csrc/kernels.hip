@@ -107,6 +107,31 @@ __device__ __forceinline__ void gather(const SegRec &R, __amdgpu_buffer_rsrc_t r
     r[7] = KNUDSEN ? ld(rom, act ? 4u * j : kOutOfRange, 0) : 0.f;
 }
 
+// The same pulls as byte offsets (the relaxation rate's last), computed apart
+// from the loads; past every buffer for lanes with nothing to do.
+__device__ __forceinline__ void pull_offsets(const SegRec &R, bool act, uint32_t (&o)[8], uint32_t &j4) {
+    const uint32_t j = R.pre + (uint32_t)mbcnt64(R.m);
+    const uint32_t a = pbyte(j);
+    j4 = act ? a : kOutOfRange;
+    o[0] = j4;
+    o[1] = act ? lane_sel(R.left, pbyte(j - 1u) + 256u, a + 512u) : kOutOfRange;
+    o[2] = act ? lane_sel(R.right, pbyte(j + 1u) + 512u, a + 256u) : kOutOfRange;
+    o[3] = act ? lane_sel(R.nb[0], pbyte(R.pnb[0] + (uint32_t)mbcnt64(R.nb[0])) + 768u, a + 1024u) : kOutOfRange;
+    o[4] = act ? lane_sel(R.nb[1], pbyte(R.pnb[1] + (uint32_t)mbcnt64(R.nb[1])) + 1024u, a + 768u) : kOutOfRange;
+    o[5] = act ? lane_sel(R.nb[2], pbyte(R.pnb[2] + (uint32_t)mbcnt64(R.nb[2])) + 1280u, a + 1536u) : kOutOfRange;
+    o[6] = act ? lane_sel(R.nb[3], pbyte(R.pnb[3] + (uint32_t)mbcnt64(R.nb[3])) + 1536u, a + 1280u) : kOutOfRange;
+    o[7] = act ? 4u * j : kOutOfRange;
+}
+
+// The eight loads of pull_offsets, issued without waiting.
+template <bool KNUDSEN>
+__device__ __forceinline__ void pull_loads(__amdgpu_buffer_rsrc_t rin, __amdgpu_buffer_rsrc_t rom,
+                                           const uint32_t (&o)[8], float (&r)[8]) {
+#pragma unroll
+    for (int i = 0; i < 7; ++i) r[i] = ld(rin, o[i], 0);
+    r[7] = KNUDSEN ? ld(rom, o[7], 0) : 0.f;
+}
+
 // Collision of one voxel in FP64 from its seven pulled stored values: x faces
 // (anti-bounce-back Dirichlet at the inlet; Dirichlet or zero-gradient outlet),
 // re-referencing of the +-x pulls to this voxel's shift, the sink -k n C, and the
@@ -213,76 +238,75 @@ __device__ __forceinline__ void sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Words of a segment record that locate lane LN's seven pulled values: read per
-// lane (each lane its own record) and issued together before any is used.
-struct EdgeRec {
-    uint64_t m, left, right, nb[4], ion, n0, n1, n2;
-    uint32_t pre, pnb[4];
-};
-
-__device__ __forceinline__ EdgeRec load_edge(const SegRec *R) {
-    EdgeRec e;
-    e.m = R->m;
-    e.left = R->left;
-    e.right = R->right;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        e.nb[k] = R->nb[k];
-        e.pnb[k] = R->pnb[k];
-    }
-    e.ion = R->ion;
-    e.n0 = R->n0;
-    e.n1 = R->n1;
-    e.n2 = R->n2;
-    e.pre = R->pre;
-    return e;
-}
-
-// Gather of lane LN (63: the voxel before a segment's x range, 0: the one after
-// it) of the record e, one record per lane; returns the lane's flags (0: none).
-template <bool KNUDSEN, int LN>
-__device__ __forceinline__ uint32_t gather_edge(const EdgeRec &e, bool valid, __amdgpu_buffer_rsrc_t rin,
-                                                __amdgpu_buffer_rsrc_t rom, float (&r)[8]) {
-    constexpr uint64_t below = LN ? ~0ull >> (64 - LN) : 0ull;  // lanes under LN
-    const bool act = valid && bit(e.m, LN);
-    const uint32_t j = e.pre + (uint32_t)__popcll(e.m & below);
+// One step of the voxel just outside a segment's x range, one voxel per lane with
+// its own record R: lane 63 of segment sn when side is 0 (the voxel before the
+// range), lane 0 of segment sn when side is 1 (the voxel after it).  Returns the
+// post-collision value that streams back into the range (+x, or -x), or 0 when the
+// voxel is not simulated.
+template <bool KNUDSEN, bool REACT>
+__device__ __forceinline__ float edge_value(const SegRec *__restrict__ R, int side, int sn, const InstDev &I,
+                                            __amdgpu_buffer_rsrc_t rin, __amdgpu_buffer_rsrc_t rom) {
+    const int ln = side ? 0 : 63;
+    const uint64_t below = side ? 0ull : ~0ull >> 1;  // lanes under ln
+    const uint64_t m = R->m, left = R->left, right = R->right, ion = R->ion;
+    const uint64_t nb0 = R->nb[0], nb1 = R->nb[1], nb2 = R->nb[2], nb3 = R->nb[3];
+    const uint64_t n0 = R->n0, n1 = R->n1, n2 = R->n2;
+    const uint32_t pre = R->pre, q0 = R->pnb[0], q1 = R->pnb[1], q2 = R->pnb[2], q3 = R->pnb[3];
+    if (!bit(m, ln)) return 0.f;
+    const uint32_t j = pre + (uint32_t)__popcll(m & below);
     const uint32_t a = pbyte(j);
+    const uint64_t nb[4] = {nb0, nb1, nb2, nb3};
+    const uint32_t pq[4] = {q0, q1, q2, q3};
     uint32_t o[7];
     o[0] = a;
-    o[1] = bit(e.left, LN) ? pbyte(j - 1u) + 256u : a + 512u;
-    o[2] = bit(e.right, LN) ? pbyte(j + 1u) + 512u : a + 256u;
+    o[1] = bit(left, ln) ? pbyte(j - 1u) + 256u : a + 512u;
+    o[2] = bit(right, ln) ? pbyte(j + 1u) + 512u : a + 256u;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const uint32_t own = a + 256u * (uint32_t)(k ^ 1) + 768u;  // bounce-back: the opposite population
-        o[3 + k] = bit(e.nb[k], LN) ? pbyte(e.pnb[k] + (uint32_t)__popcll(e.nb[k] & below)) + 768u + 256u * (uint32_t)k
-                                    : own;
+        o[3 + k] = bit(nb[k], ln) ? pbyte(pq[k] + (uint32_t)__popcll(nb[k] & below)) + 768u + 256u * (uint32_t)k : own;
     }
+    float r[8];
 #pragma unroll
-    for (int i = 0; i < 7; ++i) r[i] = ld(rin, act ? o[i] : kOutOfRange, 0);
-    r[7] = KNUDSEN ? ld(rom, act ? 4u * j : kOutOfRange, 0) : 0.f;
-    const uint32_t fl = F_ACT | (uint32_t)bit(e.left, LN) << 1 | (uint32_t)bit(e.right, LN) << 2 |
-                        (uint32_t)bit(e.ion, LN) << 7 |
-                        (uint32_t)(bit(e.n0, LN) + 2 * bit(e.n1, LN) + 4 * bit(e.n2, LN)) << F_N;
-    return act ? fl : 0u;
+    for (int i = 0; i < 7; ++i) r[i] = ld(rin, o[i], 0);
+    r[7] = KNUDSEN ? ld(rom, 4u * j, 0) : 0.f;
+    const double om = KNUDSEN ? (double)r[7] : (double)(bit(ion, ln) ? I.om_ion : I.om_pore);
+    const int n = REACT ? bit(n0, ln) + 2 * bit(n1, ln) + 4 * bit(n2, ln) : 0;
+    float out[7];
+    collide7<REACT>(I, sn * 64 + ln, bit(left, ln), bit(right, ln), om, n, r, out);
+    return side ? out[2] : out[1];
 }
+
+// Loads of one row's first step in flight: the pulled values, the lane's flags and
+// its own byte offset.
+struct Pending {
+    float g[8];
+    uint32_t fl, j4;
+};
+
+constexpr int kStep2MaxPlanes = 64;  // planes per chunk (the x-edge table lives in LDS)
 
 // Two steps per launch for one instance (see Step2Launch).  Block b (after the
 // XCD renumbering) owns segment column s = b % nsx, rows y0 .. y0 + nr - 1 and
-// planes z_lo .. z_hi - 1.  Iteration p completes the first step of plane p
-// (p = z_lo - 1 .. z_hi; planes wrap periodically) into LDS, issues the loads of
-// plane p + 1, and performs the second step of plane p - 1 from LDS into fout.
-// Waves 0 .. BY - 1 own one tile row each; wave BY steps the row before the
-// tile and the voxel before each tile row's x range, wave BY + 1 the row after
-// the tile and the voxel after each x range.  Every value entering the second
-// step is the FP32 value the single-step kernel would have stored, so one launch
-// of this kernel and two of that one give bit-identical lattices.
+// planes z_lo .. z_hi - 1.
+//   * First, every thread steps voxels just outside the x range (x0 - 1 and x0 + 64
+//     of each tile row, planes z_lo - 1 .. z_hi) into an LDS table.
+//   * Then iteration p (p = z_lo - 1 .. z_hi; planes wrap periodically) completes
+//     the first step of plane p into LDS from loads issued two iterations earlier,
+//     issues the loads of plane p + 2, and performs the second step of plane p - 1
+//     from LDS into fout.
+// Waves 0 .. BY - 1 own one tile row each; wave BY steps the row before the tile,
+// wave BY + 1 the row after it.  Every value entering the second step is the FP32
+// value the single-step kernel would have stored, so one launch of this kernel and
+// two of that one give bit-identical lattices.
+// At most 72 VGPRs (7 waves per SIMD): three 6-row or four 4-row workgroups per CU.
 template <int BY, bool KNUDSEN, bool REACT>
-__global__ __launch_bounds__((BY + 2) * 64) void k_step2(Lattice L, Step2Launch S, const float *__restrict__ fin,
-                                                         float *__restrict__ fout) {
+__global__ __launch_bounds__((BY + 2) * 64) __attribute__((amdgpu_waves_per_eu(7))) void k_step2(
+    Lattice L, Step2Launch S, const float *__restrict__ fin, float *__restrict__ fout) {
     __shared__ float full[2][BY][8][64];  // first step of a plane: 7 populations (+ 1/tau) per tile row
     __shared__ float zm[BY][64];          // +z population of the plane below the one in its second step
     __shared__ float yh[2][2][64];        // +y population of row y0 - 1, -y population of row y0 + nr
-    __shared__ float xh[2][BY][2];        // +x population of x0 - 1, -x population of x0 + 64, per tile row
+    __shared__ float xe[kStep2MaxPlanes + 2][BY][2];  // +x from x0 - 1, -x from x0 + 64, per plane and tile row
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const InstDev &I = L.inst[0];
@@ -292,15 +316,27 @@ __global__ __launch_bounds__((BY + 2) * 64) void k_step2(Lattice L, Step2Launch 
     const int y0 = (t % S.nty) * BY, nr = min(BY, ny - y0);
     const int z_lo = (t / S.nty) * S.zc, z_hi = min(z_lo + S.zc, nz);
     const bool whole_y = nr == ny;  // the tile's own rows are its y neighbours
-    const bool has_l = s > 0, has_r = s + 1 < nsx;
     const uint32_t S4 = 4u * L.stride;
     const __amdgpu_buffer_rsrc_t rin = rsrc(fin, 7u * S4), rout = rsrc(fout, 7u * S4);
     const __amdgpu_buffer_rsrc_t rom = rsrc(L.omega, KNUDSEN ? S4 : 0u);
     const int64_t plane_stride = (int64_t)ny * nsx;
 
+    // ---- x-edge voxels of every plane of the chunk (task = (plane, tile row, side))
+    const int ntask = (z_hi - z_lo + 2) * nr * 2;
+    for (int task = (int)threadIdx.x; task < ntask; task += (BY + 2) * 64) {
+        const int side = task & 1, tr = (task >> 1) % nr, pi = (task >> 1) / nr;
+        const int sn = side ? s + 1 : s - 1;
+        float v = 0.f;
+        if (sn >= 0 && sn < nsx) {
+            const int p = z_lo - 1 + pi;
+            const int zp = p < 0 ? p + nz : (p >= nz ? p - nz : p);
+            v = edge_value<KNUDSEN, REACT>(L.rec + zp * plane_stride + (int64_t)(y0 + tr) * nsx + sn, side, sn, I, rin,
+                                           rom);
+        }
+        xe[pi][tr][side] = v;
+    }
+
     // This wave's row: 0 tile row, 1 the row before the tile, 2 the row after it, -1 none.
-    // Waves BY and BY + 1 also step the voxels just before (x0 - 1) and just after
-    // (x0 + 64) the x range of every tile row, lane tr for tile row tr.
     int kind = -1, row = 0;
     if (wave < nr) {
         kind = 0;
@@ -312,63 +348,56 @@ __global__ __launch_bounds__((BY + 2) * 64) void k_step2(Lattice L, Step2Launch 
         kind = 2;
         row = y0 + nr == ny ? 0 : y0 + nr;
     }
-    const int side = wave - BY;  // 0 / 1 on the edge waves
-    const bool edge_wave = side >= 0 && (side ? has_r : has_l);
-    const bool edge_lane = edge_wave && lane < nr;
     const SegRec *Rrow = L.rec + (int64_t)row * nsx + s;
-    const SegRec *Redge = L.rec + (int64_t)(y0 + (edge_lane ? lane : 0)) * nsx + (side == 1 ? s + 1 : s - 1);
-
-    // loads in flight for the first step of the next plane
-    float g[8], ge[8];
-    uint32_t fl = 0, fle = 0, j4 = kOutOfRange;
-    auto issue = [&](int p) {
-        const int zp = p < 0 ? p + nz : (p >= nz ? p - nz : p);
-        EdgeRec e{};
-        if (edge_lane) e = load_edge(Redge + zp * plane_stride);
-        if (kind >= 0) {
+    // Every wave issues the same eight loads and seven stores in every iteration
+    // (offsets past the buffers where there is nothing to do), so the compiler's
+    // wait counts stay exact across the loop and the next planes' loads stay in
+    // flight while a plane is consumed.
+    auto issue = [&](int p, Pending &P) {
+        uint32_t o[8];
+        if (kind >= 0 && p <= z_hi) {
+            const int zp = p < 0 ? p + nz : (p >= nz ? p - nz : p);
             const SegRec &R = Rrow[zp * plane_stride];
-            fl = lane_flags(R, lane);
-            gather<KNUDSEN>(R, rin, rom, (fl & F_ACT) != 0, g, j4);
+            P.fl = lane_flags(R, lane);
+            pull_offsets(R, (P.fl & F_ACT) != 0, o, P.j4);
+        } else {
+            P.fl = 0;
+            P.j4 = kOutOfRange;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) o[i] = kOutOfRange;
         }
-        if (edge_wave)
-            fle = side ? gather_edge<KNUDSEN, 0>(e, edge_lane, rin, rom, ge)
-                       : gather_edge<KNUDSEN, 63>(e, edge_lane, rin, rom, ge);
+        pull_loads<KNUDSEN>(rin, rom, o, P.g);
     };
-    if (kind >= 0 || edge_wave) issue(z_lo - 1);
-
     uint32_t flq = 0, j4q = kOutOfRange;  // the plane in its second step
-    for (int p = z_lo - 1; p <= z_hi; ++p) {
+    // iteration p: first step of plane p from P, loads of plane p + 2 into P, second
+    // step of plane p - 1
+    auto iterate = [&](int p, Pending &P) {
         const int ps = p & 1;
-        // ---- first step of plane p, from the loads issued one iteration ago
-        if (kind >= 0 && (fl & F_ACT)) {
+        if (kind >= 0 && (P.fl & F_ACT)) {
             float o[7];
-            collide7<REACT>(I, s * 64 + lane, (fl & F_LEFT) != 0, (fl & F_RIGHT) != 0,
-                            flag_omega(fl, I, g[7], KNUDSEN), REACT ? (int)(fl >> F_N) : 0, g, o);
+            collide7<REACT>(I, s * 64 + lane, (P.fl & F_LEFT) != 0, (P.fl & F_RIGHT) != 0,
+                            flag_omega(P.fl, I, P.g[7], KNUDSEN), REACT ? (int)(P.fl >> F_N) : 0, P.g, o);
             if (kind == 0) {
 #pragma unroll
                 for (int i = 0; i < 7; ++i) full[ps][wave][i][lane] = o[i];
-                if (KNUDSEN) full[ps][wave][7][lane] = g[7];
+                if (KNUDSEN) full[ps][wave][7][lane] = P.g[7];
             } else {
                 yh[ps][kind - 1][lane] = kind == 1 ? o[3] : o[4];
             }
         }
-        if (fle) {  // x0 - 1 streams +x into its tile row, x0 + 64 streams -x
-            float o[7];
-            collide7<REACT>(I, side ? (s + 1) * 64 : s * 64 - 1, (fle & F_LEFT) != 0, (fle & F_RIGHT) != 0,
-                            flag_omega(fle, I, ge[7], KNUDSEN), REACT ? (int)(fle >> F_N) : 0, ge, o);
-            xh[ps][lane][side] = side ? o[2] : o[1];
-        }
-        const uint32_t flp = fl, j4p = j4;
-        if ((kind >= 0 || edge_wave) && p < z_hi) issue(p + 1);
+        const uint32_t flp = P.fl, j4p = P.j4;
+        issue(p + 2, P);
         sync_lds();
-        // ---- second step of plane q = p - 1; then keep its +z population for plane q + 1
         const int q = p - 1, qs = q & 1;
-        if (kind == 0 && q >= z_lo && (flq & F_ACT)) {
+        const bool second = kind == 0 && q >= z_lo && (flq & F_ACT);
+        float o[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (second) {
             const float(&F)[BY][8][64] = full[qs];
+            const int qi = q - (z_lo - 1);
             float r[8];
             r[0] = F[wave][0][lane];
-            r[1] = (flq & F_LEFT) ? (lane > 0 ? F[wave][1][lane - 1] : xh[qs][wave][0]) : F[wave][2][lane];
-            r[2] = (flq & F_RIGHT) ? (lane < 63 ? F[wave][2][lane + 1] : xh[qs][wave][1]) : F[wave][1][lane];
+            r[1] = (flq & F_LEFT) ? (lane > 0 ? F[wave][1][lane - 1] : xe[qi][wave][0]) : F[wave][2][lane];
+            r[2] = (flq & F_RIGHT) ? (lane < 63 ? F[wave][2][lane + 1] : xe[qi][wave][1]) : F[wave][1][lane];
             r[3] = (flq & (F_NB << 0))
                        ? (wave > 0 ? F[wave - 1][3][lane] : (whole_y ? F[nr - 1][3][lane] : yh[qs][0][lane]))
                        : F[wave][4][lane];
@@ -378,17 +407,36 @@ __global__ __launch_bounds__((BY + 2) * 64) void k_step2(Lattice L, Step2Launch 
             r[5] = (flq & (F_NB << 2)) ? zm[wave][lane] : F[wave][6][lane];
             r[6] = (flq & (F_NB << 3)) ? full[ps][wave][6][lane] : F[wave][5][lane];
             r[7] = KNUDSEN ? F[wave][7][lane] : 0.f;
-            float o[7];
             collide7<REACT>(I, s * 64 + lane, (flq & F_LEFT) != 0, (flq & F_RIGHT) != 0,
                             flag_omega(flq, I, r[7], KNUDSEN), REACT ? (int)(flq >> F_N) : 0, r, o);
-#pragma unroll
-            for (int i = 0; i < 7; ++i) st(o[i], rout, j4q, 256u * i);
         }
+        const uint32_t jst = second ? j4q : kOutOfRange;
+#pragma unroll
+        for (int i = 0; i < 7; ++i) st(o[i], rout, jst, 256u * i);
         if (kind == 0 && q >= z_lo - 1 && (flq & F_ACT)) zm[wave][lane] = full[qs][wave][5][lane];
         flq = flp;
         j4q = j4p;
         sync_lds();
+    };
+
+    // the prologue issues the loop's sequence of memory operations: the loads, then
+    // seven (dropped) stores, per plane
+    auto no_stores = [&]() {
+#pragma unroll
+        for (int i = 0; i < 7; ++i) st(0.f, rout, kOutOfRange, 256u * i);
+    };
+    Pending A, B;
+    issue(z_lo - 1, A);
+    no_stores();
+    issue(z_lo, B);  // z_lo < z_hi
+    no_stores();
+    sync_lds();  // the x-edge table is complete
+    int p = z_lo - 1;
+    for (; p + 1 <= z_hi; p += 2) {  // both halves unconditional: exact wait counts at the back-edge
+        iterate(p, A);
+        iterate(p + 1, B);
     }
+    if (p <= z_hi) iterate(p, A);
 }
 
 // ------------------------------------------------------------------ FP64 reductions
@@ -619,9 +667,11 @@ hipError_t launch_step2_t(const Lattice &L, const Step2Launch &S, bool kn, bool 
 
 hipError_t launch_step2(const Lattice &L, const Step2Launch &S, bool knudsen, bool react, const float *fin,
                         float *fout, hipStream_t st) {
+    if (S.zc < 1 || S.zc > kStep2MaxPlanes) return hipErrorInvalidValue;  // the x-edge table's planes
     if (S.nblk <= 0) return hipSuccess;
     switch (S.by) {
         case 4: return launch_step2_t<4>(L, S, knudsen, react, fin, fout, st);
+        case 6: return launch_step2_t<6>(L, S, knudsen, react, fin, fout, st);
         case 8: return launch_step2_t<8>(L, S, knudsen, react, fin, fout, st);
         default: return hipErrorInvalidValue;
     }

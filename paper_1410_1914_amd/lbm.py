@@ -509,7 +509,7 @@ class Solver:
         return lbm_get_tiling(self.h)
 
     def set_temporal(self, rows_per_tile, planes_per_chunk=32):
-        """Two steps per launch (rows_per_tile 4 or 8), or one (0)."""
+        """Two steps per launch (rows_per_tile 4, 6 or 8; 1..64 planes per chunk), or one (0)."""
         return lbm_set_temporal(self.h, rows_per_tile, planes_per_chunk)
 
     def temporal(self):

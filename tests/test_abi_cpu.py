@@ -223,19 +223,19 @@ def test_batch_entry_points_reject_bad_arguments():
 
 
 def test_temporal_blocking_arguments():
-    """Two-step launch settings are checked on the host: 4 or 8 rows per tile (0 is
-    one step per launch), 1 .. 4096 planes per chunk."""
+    """Two-step launch settings are checked on the host: 4, 6 or 8 rows per tile (0
+    is one step per launch), 1 .. 64 planes per chunk."""
     import ctypes
 
     h = lbm.lbm_create(sg.pt_cl(61, shape=(4, 5, 20)), lbm.lbm_params_default(mode=lbm.MODE_DEFF))
     lib = lbm.load()
-    for by, zc in ((3, 8), (16, 8), (-1, 8), (4, 0), (8, 4097)):
+    for by, zc in ((3, 8), (5, 8), (16, 8), (-1, 8), (4, 0), (8, 65)):
         assert lib.lbm_set_temporal(h, by, zc) == lbm.ERR_INVALID_ARG, (by, zc)
     assert lib.lbm_set_temporal(None, 4, 8) == lbm.ERR_INVALID_ARG
     a, b = ctypes.c_int32(), ctypes.c_int32()
     assert lib.lbm_get_temporal(h, ctypes.byref(a), ctypes.byref(b)) == lbm.OK and a.value == 0
-    assert lib.lbm_set_temporal(h, 8, 4096) == lbm.OK
-    assert lbm.lbm_get_temporal(h) == (8, 4096)
+    assert lib.lbm_set_temporal(h, 8, 64) == lbm.OK
+    assert lbm.lbm_get_temporal(h) == (8, 64)
     assert lib.lbm_set_temporal(h, 0, 0) == lbm.OK  # off; the chunk size is kept
-    assert lbm.lbm_get_temporal(h) == (0, 4096)
+    assert lbm.lbm_get_temporal(h) == (0, 64)
     lbm.lbm_destroy(h)
