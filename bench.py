@@ -175,9 +175,9 @@ def headline(args, lbm, structgen):
 
 def other_form(s, args, chosen):
     """Kernel time per LBM step of the form the autotuner did not keep (two steps per
-    launch with an 8-row, 16-plane tile, or one step per launch), on the same state;
+    launch with a 6-row, 16-plane tile, or one step per launch), on the same state;
     the chosen form is restored afterwards."""
-    alt = (0, 0) if chosen[0] else (8, 16)
+    alt = (0, 0) if chosen[0] else (6, 16)
     s.set_temporal(*alt)
     _, r0 = s.advance(args.lbm_steps)
     _, r1 = s.advance(4 * args.lbm_steps)
