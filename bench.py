@@ -54,6 +54,9 @@ def parse():
                     help="run the effective-diffusivity warm-start comparison at 192^3 instead of 96^3 (several minutes)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU time budget of the oracle sample")
     ap.add_argument("--no-tune", action="store_true", help="keep the default tiling (no autotuning)")
+    ap.add_argument("--tiling", default=None,
+                    help="segments/wave,waves/workgroup,xcd: use this one-step launch instead of autotuning "
+                         "(profiles pin the form the autotuner keeps at 256^3: 1,1,1)")
     ap.add_argument("--batch64", action="store_true",
                     help="also time the uneven 64-structure reactive batch: batched vs sequential solves")
     ap.add_argument("--batch-count", type=int, default=64)
@@ -124,7 +127,11 @@ def headline(args, lbm, structgen):
     info = s.info
     log(f"[bench] {n}^3 NPMC: generated in {t_gen:.1f}s, preprocessed+bound in {t_prep:.1f}s, "
         f"{info.n_active} fluid voxels, {info.n_segments} segments")
-    tune_ms = s.autotune(10) if not args.no_tune else float("nan")
+    if args.tiling:
+        s.set_tiling(*(int(v) for v in args.tiling.split(",")))
+        tune_ms = float("nan")
+    else:
+        tune_ms = s.autotune(10) if not args.no_tune else float("nan")
     tiling, temporal = s.tiling(), s.temporal()
     spl = 2 if temporal[0] else 1  # LBM steps per stream-collide launch
     log(f"[bench] autotuned tiling (segments/wave, waves/workgroup, xcd) = {tiling}, two-step tile "
