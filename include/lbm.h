@@ -283,6 +283,34 @@ int lbm_batch_get_host_fields(const lbm_batch *b, int32_t i, uint8_t *active_hos
                               float *omega_host);
 void lbm_batch_destroy(lbm_batch *b);
 
+/* ---- Structure characterisation on the device (Section 2.1.3)
+ *
+ * The two preprocessing steps whose cost grows with the voxel count, for phase
+ * maps already in device memory.  Arrays are device pointers to nz*ny*nx voxels,
+ * x fastest; y and z are periodic and x is bounded, as in lbm_create.  stream is
+ * a hipStream_t (NULL: the null stream); both calls synchronise it before
+ * returning.  Errors: LBM_ERR_INVALID_ARG for NULL pointers, non-positive sizes
+ * or (reach) faces outside 1..3; LBM_ERR_HIP for a failed launch (lbm_last_error
+ * names it).
+ *
+ * lbm_pore_size_device: the pore size of Section 2.1.3 (the d_p of Eqs. 8-9, in
+ * voxel edges).  For a voxel with pore_dev[v] != 0, dp_dev[v] (FP64) is the mean
+ * over the 13 directions d of the length, in voxels, of the run of pore voxels
+ * through v along d, times |d|. A run along a direction without an x component
+ * that closes on itself under the wrap counts its loop once. Other voxels get 0.
+ * The sum runs in lbm_create's direction order with round-to-nearest products
+ * and sums, so the values are bit-identical to the host's.
+ *
+ * lbm_reach_device: hit_dev[v] = 1 for every voxel with pass_dev[v] != 0 that is
+ * 6-neighbour connected through such voxels to one on the x = 0 face (faces & 1)
+ * or the x = nx - 1 face (faces & 2); 0 elsewhere.  This is lbm_create's
+ * simulated-voxel mask when pass is the transport phase and faces are the
+ * Dirichlet faces.  *cycles (may be NULL) receives the number of sweep cycles
+ * (three line sweeps each) until nothing changed. */
+int lbm_pore_size_device(const uint8_t *pore_dev, int32_t nx, int32_t ny, int32_t nz, double *dp_dev, void *stream);
+int lbm_reach_device(const uint8_t *pass_dev, int32_t nx, int32_t ny, int32_t nz, int32_t faces, uint8_t *hit_dev,
+                     int32_t *cycles, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -729,6 +729,9 @@ int make_engine(int n, const lbm_grid *grids, const uint8_t *const *phases, cons
 }
 
 }  // namespace
+
+int record_error(hipError_t e, const char *where) { return hip_status_at(e, where); }
+
 }  // namespace cl
 
 struct lbm_solver {

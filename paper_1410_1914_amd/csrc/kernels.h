@@ -103,4 +103,7 @@ hipError_t launch_get_pop(const Lattice &L, int32_t nblk, const int2 *blk, const
 hipError_t launch_conc(const Lattice &L, int32_t nblk, const int2 *blk, bool react, const float *f,
                        const int64_t *dense_base, float *c_dense, hipStream_t st);
 
+// LBM_OK, or LBM_ERR_HIP with the failing call kept for lbm_last_error.
+int record_error(hipError_t e, const char *where);
+
 }  // namespace cl

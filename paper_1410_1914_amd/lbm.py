@@ -79,6 +79,8 @@ SIGNATURES = {
     "lbm_get_info": ([_P, ctypes.POINTER(lbm_info)], c_int32),
     "lbm_get_host_fields": ([_P, ctypes.POINTER(c_uint8), ctypes.POINTER(c_uint8), ctypes.POINTER(c_float)], c_int32),
     "lbm_get_pore_depth": ([_P, ctypes.POINTER(c_uint8)], c_int32),
+    "lbm_pore_size_device": ([_P, c_int32, c_int32, c_int32, _P, _P], c_int32),
+    "lbm_reach_device": ([_P, c_int32, c_int32, c_int32, c_int32, _P, ctypes.POINTER(c_int32), _P], c_int32),
     "lbm_workspace_bytes": ([_P, ctypes.POINTER(ctypes.c_size_t)], c_int32),
     "lbm_bind": ([_P, _P, ctypes.c_size_t, _P], c_int32),
     "lbm_set_initial_concentration": ([_P, _P], c_int32),
@@ -152,6 +154,46 @@ def _check(fn, st):
     if st < 0:
         raise LbmError(fn, st)
     return st
+
+
+def _device_map(a):
+    """A contiguous uint8 (nz, ny, nx) tensor on the GPU (copied there if needed)."""
+    import torch
+
+    t = torch.as_tensor(a)
+    if t.dim() != 3:
+        raise ValueError("map must be (nz, ny, nx)")
+    return t.to(device="cuda", dtype=torch.uint8).contiguous()
+
+
+def pore_size_device(pore):
+    """13-direction pore size (Section 2.1.3) of every voxel of a pore mask, on the
+    GPU: FP64 (nz, ny, nx) tensor, 0 off pore (lbm_pore_size_device)."""
+    import torch
+
+    require_gpu()
+    m = _device_map(pore)
+    nz, ny, nx = m.shape
+    out = torch.empty(m.shape, dtype=torch.float64, device="cuda")
+    st = torch.cuda.current_stream().cuda_stream
+    _check("lbm_pore_size_device", load().lbm_pore_size_device(m.data_ptr(), nx, ny, nz, out.data_ptr(), st))
+    return out
+
+
+def reach_device(pass_mask, faces=3):
+    """Voxels of ``pass_mask`` 6-connected to its x = 0 face (faces & 1) and/or
+    x = nx - 1 face (faces & 2), on the GPU (lbm_reach_device): (uint8 tensor, sweep cycles)."""
+    import torch
+
+    require_gpu()
+    m = _device_map(pass_mask)
+    nz, ny, nx = m.shape
+    out = torch.empty(m.shape, dtype=torch.uint8, device="cuda")
+    cycles = c_int32()
+    st = torch.cuda.current_stream().cuda_stream
+    _check("lbm_reach_device", load().lbm_reach_device(m.data_ptr(), nx, ny, nz, int(faces), out.data_ptr(),
+                                                       ctypes.byref(cycles), st))
+    return out, cycles.value
 
 
 def lbm_status_string(status: int) -> str:

@@ -239,3 +239,16 @@ def test_temporal_blocking_arguments():
     assert lib.lbm_set_temporal(h, 0, 0) == lbm.OK  # off; the chunk size is kept
     assert lbm.lbm_get_temporal(h) == (0, 64)
     lbm.lbm_destroy(h)
+
+
+def test_device_characterisation_rejects_bad_arguments():
+    """Host-side checks of the device characterisation calls (no device call is made)."""
+    lib = lbm.load()
+    fake = 1  # never dereferenced: the checks come first
+    assert lib.lbm_pore_size_device(None, 4, 4, 4, fake, None) == lbm.ERR_INVALID_ARG
+    assert lib.lbm_pore_size_device(fake, 0, 4, 4, fake, None) == lbm.ERR_INVALID_ARG
+    assert lib.lbm_pore_size_device(fake, 4, 4, 4, None, None) == lbm.ERR_INVALID_ARG
+    for faces in (0, 4, -1):
+        assert lib.lbm_reach_device(fake, 4, 4, 4, faces, fake, None, None) == lbm.ERR_INVALID_ARG
+    assert lib.lbm_reach_device(None, 4, 4, 4, 1, fake, None, None) == lbm.ERR_INVALID_ARG
+    assert lib.lbm_reach_device(fake, 4, -2, 4, 1, fake, None, None) == lbm.ERR_INVALID_ARG
