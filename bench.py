@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-solves", action="store_true", help="skip the 32^3 solves/s legs")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-start leg")
+    ap.add_argument("--no-charz", action="store_true", help="skip the device structure-characterisation leg")
     ap.add_argument("--warm-deff", action="store_true",
                     help="run the effective-diffusivity warm-start comparison at 192^3 instead of 96^3 (several minutes)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU time budget of the oracle sample")
@@ -193,6 +194,36 @@ def other_form(s, args, chosen):
     form = f"two steps per launch, tile {alt[0]} rows x {alt[1]} planes" if alt[0] else "one step per launch"
     log(f"[bench] other form ({form}): {us:.1f} us per step")
     return {"form": form, "kernel_us_per_step": round(us, 2)}
+
+
+def charz_leg(lbm, ph):
+    """Structure characterisation of the headline structure on the device (pore
+    size by 13-direction chords, reach of the transport phases from both x faces),
+    against the host preprocessing of lbm_create on the same structure."""
+    import numpy as np
+    import torch
+
+    pore = torch.from_numpy((ph == lbm.PORE).astype(np.uint8)).cuda()
+    transport = torch.from_numpy(((ph == lbm.PORE) | (ph == lbm.IONOMER)).astype(np.uint8)).cuda()
+    lbm.pore_size_device(pore)  # first launch
+    lbm.reach_device(transport, 3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lbm.pore_size_device(pore)
+    t1 = time.perf_counter()
+    _, cycles = lbm.reach_device(transport, 3)
+    t2 = time.perf_counter()
+    p = lbm.lbm_params_default(mode=lbm.MODE_DEFF, knudsen=1)
+    t3 = time.perf_counter()
+    h = lbm.lbm_create(ph, p, 1e-9)
+    t4 = time.perf_counter()
+    lbm.lbm_destroy(h)
+    log(f"[bench] device characterisation: pore size {1e3 * (t1 - t0):.1f} ms, reach {1e3 * (t2 - t1):.1f} ms "
+        f"({cycles} cycles); host lbm_create {t4 - t3:.2f} s")
+    return {"workload": "pore size (13 directions) and face reach of the headline structure",
+            "gpu_pore_size_ms": round(1e3 * (t1 - t0), 2), "gpu_reach_ms": round(1e3 * (t2 - t1), 2),
+            "reach_cycles": cycles, "host_lbm_create_s": round(t4 - t3, 3),
+            "host_note": "the whole host preprocessing (chords, reach, tau, segment tables), D_eff problem"}
 
 
 def cpu_baseline(args, ph, structgen):
@@ -375,6 +406,8 @@ def main():
     if not args.no_cpu:
         log("[bench] CPU oracle baseline ...")
         out["cpu_baseline"] = cpu_baseline(args, ph, structgen)
+    if not args.no_charz:
+        out["characterise"] = charz_leg(lbm, ph)
     del ph
     if not args.no_solves:
         log("[bench] 32^3 solves/s legs ...")
