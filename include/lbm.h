@@ -172,7 +172,10 @@ int lbm_set_initial_concentration(lbm_solver *s, const float *c_dev);
 int lbm_set_populations(lbm_solver *s, const float *f_dev);
 
 /* Copy the stored post-collision distributions to a dense FP32 [7][N] array
- * (non-simulated voxels receive 0). */
+ * (non-simulated voxels receive 0).  The values are the unshifted f_i = g_i +
+ * w_i c_sh(x), each rounded once to FP32 from the stored FP32 g_i, so writing them
+ * back with lbm_set_populations reproduces the stored state only up to that
+ * rounding. */
 int lbm_get_populations(const lbm_solver *s, float *f_dev);
 
 /* Advance nsteps >= 0 fused stream-collide steps (Eq. 21) without checks. */

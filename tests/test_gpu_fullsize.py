@@ -94,3 +94,30 @@ def test_batched_instances_match_single_solves(hip):
         assert r_batch == pytest.approx(r_single, rel=2e-5)
         cb = b.concentration(i)
         assert torch.allclose(cb, s.concentration(), rtol=0, atol=2e-4)
+
+
+@pytest.mark.parametrize("name,make,voxel,kw", CASES, ids=[c[0] for c in CASES])
+def test_full_size_two_step_launch_is_bit_identical(hip, name, make, voxel, kw):
+    """One launch of the two-step kernel (the autotuner's other form) against two
+    single-step launches, from a developed state of the full-size structure.  Both
+    runs start from the same dense state written with lbm_set_populations (the
+    dense read-out is unshifted, so writing it back is not a bit-exact round trip
+    of the solver's own state)."""
+    import torch
+
+    ph = make()
+    s = hip.Solver(ph, hip.lbm_params_default(check_every=100, **kw), voxel_m=voxel)
+    s.advance(300)
+    f0 = s.populations()
+    s.set_temporal(0)
+    s.set_populations(f0)
+    s.step(2)
+    ref = s.populations()
+    for by, zc in ((6, 16), (8, 64)):
+        s.set_populations(f0)
+        s.set_temporal(by, zc)
+        s.step(2)
+        got = s.populations()
+        print(f"[fullsize] {name}: two-step tile {by}x{zc} bit-identical: {bool(torch.equal(got, ref))}", flush=True)
+        assert torch.equal(got, ref)
+    s.set_temporal(0)
