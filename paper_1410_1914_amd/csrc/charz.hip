@@ -130,6 +130,55 @@ __global__ __launch_bounds__(256) void k_reach_sweep(const uint8_t *__restrict__
     if (any) *changed = 1;
 }
 
+// Bits of p in a run (maximal block of consecutive set bits) that holds a bit of
+// h (h within p): adding h to p carries from the lowest such bit to the run's end,
+// the same on reversed bits covers the run's start.
+__device__ __forceinline__ uint64_t fill_runs(uint64_t p, uint64_t h) {
+    const uint64_t up = ((p + h) ^ p) & p;
+    const uint64_t pr = __brevll(p), hr = __brevll(h);
+    const uint64_t down = __brevll(((pr + hr) ^ pr) & pr);
+    return up | down | h;
+}
+
+// The x sweep with one wave per x line: 64 voxels at a time as bit masks (pass,
+// reach including the four neighbours across the line), runs filled with
+// fill_runs, and reach carried across 64-voxel chunks forward and then backward.
+__global__ __launch_bounds__(256) void k_reach_sweep_x(const uint8_t *__restrict__ pass, uint8_t *hit, int nx,
+                                                       int ny, int nz, int *changed) {
+    const int lane = threadIdx.x & 63;
+    const int64_t line = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (line >= (int64_t)ny * nz) return;  // whole waves leave together
+    const int y = (int)(line % ny), z = (int)(line / ny);
+    const int64_t base = line * nx;
+    const int64_t ym = ((int64_t)z * ny + wrap1(y - 1, ny)) * nx, yp = ((int64_t)z * ny + wrap1(y + 1, ny)) * nx;
+    const int64_t zm = ((int64_t)wrap1(z - 1, nz) * ny + y) * nx, zp = ((int64_t)wrap1(z + 1, nz) * ny + y) * nx;
+    const int nch = (nx + 63) / 64;
+    bool any = false;
+    for (int dir = 0; dir < 2; ++dir) {
+        bool carry = false;  // the voxel next to this chunk, on the side already swept, is reached
+        for (int k = 0; k < nch; ++k) {
+            const int c = dir ? nch - 1 - k : k;
+            const int x = c * 64 + lane;
+            const bool in = x < nx;
+            const bool ps = in && pass[base + x];
+            const bool h0 = ps && hit[base + x];
+            const bool ac = ps && (hit[ym + x] || hit[yp + x] || hit[zm + x] || hit[zp + x]);
+            const uint64_t P = __ballot(ps);
+            uint64_t H = __ballot(h0 || ac);
+            if (carry) H |= dir ? (P & (1ull << 63)) : (P & 1ull);
+            const uint64_t R = P ? fill_runs(P, H) : 0ull;
+            const bool now = (R >> lane) & 1ull;
+            if (now && !h0) {
+                hit[base + x] = 1;
+                any = true;
+            }
+            const int edge = dir ? 0 : 63;  // the chunk's last voxel in sweep order
+            carry = ((R >> edge) & 1ull) != 0 && (dir ? c * 64 : c * 64 + 63) < nx;
+        }
+    }
+    if (any) *changed = 1;
+}
+
 }  // namespace
 
 extern "C" {
@@ -173,8 +222,14 @@ int lbm_reach_device(const uint8_t *pass_dev, int32_t nx, int32_t ny, int32_t nz
     int32_t n_cycles = 0;
     for (int64_t cyc = 0; e == hipSuccess && cyc <= N; ++cyc) {
         *changed = 0;
-        for (int axis = 0; axis < 3 && e == hipSuccess; ++axis) {
-            const int64_t lines = axis == 0 ? (int64_t)ny * nz : (axis == 1 ? (int64_t)nx * nz : (int64_t)nx * ny);
+        {
+            const int64_t lines = (int64_t)ny * nz;  // x: one wave per line
+            hipLaunchKernelGGL(k_reach_sweep_x, dim3((unsigned)((lines + 3) / 4)), dim3(256), 0, st, pass_dev, hit_dev,
+                               nx, ny, nz, changed_dev);
+            e = hipGetLastError();
+        }
+        for (int axis = 1; axis < 3 && e == hipSuccess; ++axis) {  // y, z: one thread per line
+            const int64_t lines = axis == 1 ? (int64_t)nx * nz : (int64_t)nx * ny;
             hipLaunchKernelGGL(k_reach_sweep, dim3((unsigned)((lines + 255) / 256)), dim3(256), 0, st, pass_dev, hit_dev,
                                nx, ny, nz, axis, changed_dev);
             e = hipGetLastError();
