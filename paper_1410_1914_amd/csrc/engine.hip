@@ -79,6 +79,8 @@ struct Engine {
     int cur = 0;
 
     int waves = 4, spw = 1, xcd = 1;
+    // Alternate the direction in which one-step launches walk the segment list.
+    int alt_order = 1;
     // Two steps per launch (one instance only): rows per tile (0 = off), planes per chunk.
     int t2_by = 0, t2_zc = 32;
     // Batches run as consecutive groups of instances whose combined working set
@@ -370,8 +372,9 @@ struct Engine {
                 cur ^= 1;
             }
         }
-        const StepLaunch s = step_launch();
+        StepLaunch s = step_launch();
         for (; k < n; ++k) {
+            s.reverse = alt_order ? (int)(k & 1) : 0;
             hipError_t e = launch_step(L, s, knudsen, react, f[cur], f[cur ^ 1], st);
             if (e != hipSuccess) return e;
             cur ^= 1;

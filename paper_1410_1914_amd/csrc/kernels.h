@@ -60,6 +60,8 @@ struct StepLaunch {
     const uint32_t *list_inst;// instance of each list entry (several instances), so a wave can load
                               // its instance constants in parallel with its segment record
     int32_t single;           // 1: one instance (its constants load without waiting for the record)
+    int32_t reverse;          // 1: walk each XCD's part of the list from its end (alternate steps, so each
+                              // step starts on the segments the previous one touched last, still cached)
 };
 
 // Two time steps per launch (one instance).  A workgroup owns one 64-voxel x range

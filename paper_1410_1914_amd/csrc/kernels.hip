@@ -71,6 +71,16 @@ __device__ __forceinline__ int logical_block(int b, int nblk, int remap) {
     return x * q + min(x, r) + (b >> 3);
 }
 
+// The same renumbering with each XCD walking its eighth backwards.  Steps
+// alternate between the two, so a step starts on the segments the previous step
+// touched last: their lines are still in that XCD's L2 and in the last-level cache.
+__device__ __forceinline__ int logical_block_reversed(int b, int nblk, int remap) {
+    if (!remap || nblk < 8) return nblk - 1 - b;
+    const int q = nblk >> 3, r = nblk & 7;
+    const int x = b & 7, len = q + (x < r ? 1 : 0);
+    return x * q + min(x, r) + (len - 1 - (b >> 3));
+}
+
 // catalyst face-neighbour count of reacting lanes, from the record's bit planes
 __device__ __forceinline__ int react_n(const SegRec &R, int lane) {
     return bit(R.n0, lane) + 2 * bit(R.n1, lane) + 4 * bit(R.n2, lane);
@@ -190,7 +200,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_step(Lattice L, StepLaunch S, co
                                                     float *__restrict__ fout) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int b = logical_block(blockIdx.x, S.nblk, S.xcd);
+    const int b = S.reverse ? logical_block_reversed(blockIdx.x, S.nblk, S.xcd) : logical_block(blockIdx.x, S.nblk, S.xcd);
     const uint32_t S4 = 4u * L.stride;
     const __amdgpu_buffer_rsrc_t rin = rsrc(fin, 7u * S4), rout = rsrc(fout, 7u * S4);
     const __amdgpu_buffer_rsrc_t rom = rsrc(L.omega, KNUDSEN ? S4 : 0u);
