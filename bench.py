@@ -13,7 +13,11 @@ HBM before timing starts.
 Also reported on the same JSON line:
   * roofline: algorithmic bytes per stream-collide launch / its mean duration
     (HIP events on the solver stream), against the 8 TB/s HBM peak;
+  * other_form: kernel time per step of the launch form the autotuner did not
+    keep (one step per launch, or two steps per launch with a 6 x 16 tile);
   * cpu_baseline: the FP64 oracle's step rate on a slab of the same structure;
+  * characterise: pore size (13 directions) and face reach of the same structure
+    on the device, against the host preprocessing of lbm_create;
   * solves: solves/s to D_eff on the 32^3 two-phase workload (seeds 1..10),
     sequential single solves vs one batched solve, with the error against the
     stored oracle values;
