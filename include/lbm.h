@@ -314,6 +314,72 @@ int lbm_pore_size_device(const uint8_t *pore_dev, int32_t nx, int32_t ny, int32_
 int lbm_reach_device(const uint8_t *pass_dev, int32_t nx, int32_t ny, int32_t nz, int32_t faces, uint8_t *hit_dev,
                      int32_t *cycles, void *stream);
 
+/* ---- D3Q19 solver (Section 4, Eqs. 21-24: the paper's own lattice)
+ *
+ * The same problems as lbm_create (modes, phases, Knudsen diffusivity, sink,
+ * boundary conditions of Section 3.5, stop rule parameters) on the 19-velocity
+ * lattice of Eq. (22) with the weights of Eq. (23): a_0 = 1/3, 1/18 for the six
+ * face velocities, 1/36 for the twelve edge velocities, c_s^2 = 1/3 and
+ * D = (tau - 1/2)/3 in lattice units (Eq. 24).  lbm_params.w0 is ignored.
+ *
+ * Direction order (the populations' order in device arrays): 0 rest; 1 +x,
+ * 2 -x, 3 +y, 4 -y, 5 +z, 6 -z; 7..10 (x,y) = (+,+), (+,-), (-,+), (-,-);
+ * 11..14 (x,z) in the same pattern; 15..18 (y,z) in the same pattern.
+ *
+ * Boundaries: half-way bounce-back toward voxels that are not simulated;
+ * periodic y and z; at x = 0 (and at x = nx - 1 outside LBM_MODE_REACT) a
+ * population entering from the reservoir takes the anti-bounce-back Dirichlet
+ * value when the voxel of the face plane it passes (shifted by its y and z
+ * components) is simulated, and bounces back otherwise.  The reactive outlet is
+ * zero-gradient (bounce-back).
+ *
+ * Memory: dense over the simulated grid.  lbm19_workspace_bytes gives the size
+ * of the caller-owned device workspace (two FP32 lattices of 19 N values plus
+ * 16 N bytes of per-voxel data and small reduction buffers, N = nx ny nz of the
+ * simulated grid); lbm19_bind takes it (256-byte aligned) with a hipStream_t
+ * (NULL: the null stream) on which all work is queued, uploads the per-voxel
+ * data and sets the cold start (C = 0).  The workspace must outlive the solver's
+ * use of it.  Calls that return host values synchronise the stream.  One solver
+ * per thread.
+ *
+ * lbm19_create: as lbm_create.  Also LBM_ERR_INVALID_ARG when the simulated grid
+ *   has more than 2^31 - 1 voxels.
+ * lbm19_set_initial_concentration: stored state f_i = a_i C0 with C0 a device
+ *   FP32 array of N values (NULL: C0 = 0); resets the step count.
+ * lbm19_step: nsteps steps of Eq. (21).
+ * lbm19_measure: one step that also measures; *info (may be NULL) receives the
+ *   fluxes of the links crossed during that step (j_in, j_out, j_vol per unit
+ *   area), rate and mass of the new state; LBM_ERR_DIVERGED on NaN.
+ * lbm19_run_to_steady: windows of check_every steps; stops when max|dC| per step
+ *   over a window is below tol_change max|C|, the output (j_vol, or the rate
+ *   when reacting) is within tol_flux of its limit as estimated from the ratio
+ *   of successive window changes, on two checks in a row, and
+ *   |J_in - J_out - R| <= tol_balance |J_in|; LBM_NOT_CONVERGED at max_steps;
+ *   LBM_ERR_NO_PERCOLATION at once when no transport path joins the Dirichlet
+ *   faces.  kernel_ms and kernel_launches are not filled.
+ * lbm19_deff / lbm19_reaction_rate: as lbm_deff / lbm_reaction_rate, from the
+ *   last measurement, with D0 in lattice units (tau_ref - 1/2) D0 / (3 D_ref).
+ * lbm19_get_populations: f_dev (device, FP64, 19 N values in the direction
+ *   order above, x fastest) receives the unshifted post-collision populations of
+ *   the current state; 0 off the simulated voxels.
+ * lbm19_concentration: c_dev (device, FP32, N values) receives C of the current
+ *   state; 0 off the simulated voxels.
+ * lbm19_get_info: as lbm_get_info (n_segments = 0). */
+typedef struct lbm19_solver lbm19_solver;
+int lbm19_create(const lbm_grid *g, const uint8_t *phase_host, const lbm_params *p, lbm19_solver **out);
+int lbm19_get_info(const lbm19_solver *s, lbm_info *info);
+int lbm19_workspace_bytes(const lbm19_solver *s, size_t *bytes);
+int lbm19_bind(lbm19_solver *s, void *workspace_dev, size_t bytes, void *hip_stream);
+int lbm19_set_initial_concentration(lbm19_solver *s, const float *c_dev);
+int lbm19_step(lbm19_solver *s, int64_t nsteps);
+int lbm19_measure(lbm19_solver *s, lbm_run_info *info);
+int lbm19_run_to_steady(lbm19_solver *s, lbm_run_info *info);
+int lbm19_deff(const lbm19_solver *s, double *deff_over_d0);
+int lbm19_reaction_rate(const lbm19_solver *s, double *rate_per_area, double *j_in);
+int lbm19_get_populations(const lbm19_solver *s, double *f_dev);
+int lbm19_concentration(const lbm19_solver *s, float *c_dev);
+void lbm19_destroy(lbm19_solver *s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,577 @@
+// D3Q19 variant of the solver: the lattice the paper itself uses (Chen et al.,
+// arXiv 1410.1914, Section 4, Eqs. 21-24), beside the D3Q7 production path.
+//
+// Storage is dense over the simulated grid, population-major: f[i * N + v] with
+// v = (z * ny + y) * nx + x, FP32, holding the post-collision value shifted by
+// a_i * c_sh(x) (c_sh = sh0 - slope * x, the empty-box profile between Dirichlet
+// faces, or half the inlet value when reacting), two lattices A/B.  Per voxel a
+// 32-bit word says which pull sources are missing (bits 0-18), which face links
+// are open at x = 0 (bits 19-23, the five directions with c_x = +1) and at
+// x = nx - 1 (bits 24-28, the five with c_x = -1), and whether the voxel is
+// simulated (bit 31).  One thread per voxel, 256 per block, blocks dealt to the
+// XCDs in contiguous eighths of the grid so that neighbouring planes share an L2.
+// The collision is evaluated in FP64 and rounded once to FP32.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <memory>
+#include <vector>
+
+#include "kernels.h"
+#include "prep.h"
+
+namespace {
+
+constexpr int kQ = 19;
+constexpr int kBlock = 256;
+constexpr int kRed = 8;  // j_in, j_out, sum of interior face fluxes, rate, mass, max|dC|, max|C|, NaN count
+
+// Eq. (22), in the order the public header documents: rest; +x, -x, +y, -y, +z,
+// -z; the xy, xz and yz edges, each (+,+), (+,-), (-,+), (-,-).
+constexpr int CX[kQ] = {0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1, 0, 0, 0, 0};
+constexpr int CY[kQ] = {0, 0, 0, 1, -1, 0, 0, 1, -1, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1};
+constexpr int CZ[kQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1};
+constexpr int OPP[kQ] = {0, 2, 1, 4, 3, 6, 5, 10, 9, 8, 7, 14, 13, 12, 11, 18, 17, 16, 15};
+// slot of a c_x = +1 direction among bits 19-23, of a c_x = -1 one among 24-28
+constexpr int FACE_SLOT[kQ] = {-1, 0, 0, -1, -1, -1, -1, 1, 2, 1, 2, 3, 4, 3, 4, -1, -1, -1, -1};
+constexpr uint32_t kActive = 1u << 31;
+
+__host__ __device__ constexpr double weight(int i) { return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
+
+struct D19Args {
+    const float *__restrict__ fin;
+    float *__restrict__ fout;
+    const uint32_t *__restrict__ mask;
+    const float *__restrict__ omega;
+    const float *__restrict__ kn;  // k n per voxel (reactive problem only)
+    float *__restrict__ csnap;     // C at the previous measured step
+    double *__restrict__ part;     // per-block partial sums (measured steps)
+    int64_t N;
+    int nx, ny, nz, nblk;
+    double sh0, slope;             // shift of the stored populations
+    double ab_in, ab_out;          // anti-bounce-back constants in the shifted form
+    double c_in, c_out;
+};
+
+// Blocks are dealt round-robin to the 8 XCDs; give XCD k the k-th contiguous
+// eighth of the voxel range instead.
+__device__ __forceinline__ int64_t xcd_block(int b, int nblk) {
+    if (nblk < 8) return b;
+    const int q = nblk >> 3, r = nblk & 7, x = b & 7;
+    return (int64_t)x * q + min(x, r) + (b >> 3);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+
+// One step of Eq. (21) in pull form: gather the post-collision populations of the
+// previous step (half-way bounce-back, anti-bounce-back at open face links,
+// periodic y and z), relax toward a_i C with the sink a_i S, store.  MEASURE also
+// sums the fluxes of the links just crossed and the C, k n C of the new state.
+template <bool REACT, bool MEASURE>
+__global__ __launch_bounds__(kBlock) void k_d3q19(D19Args a) {
+    const int64_t v = xcd_block(blockIdx.x, a.nblk) * kBlock + threadIdx.x;
+    double acc[kRed] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const uint32_t m = v < a.N ? a.mask[v] : 0u;
+    if (m & kActive) {
+        const uint32_t vv = (uint32_t)v, r = vv / (uint32_t)a.nx;
+        const int x = (int)(vv - r * (uint32_t)a.nx);
+        const int z = (int)(r / (uint32_t)a.ny), y = (int)(r - (uint32_t)z * (uint32_t)a.ny);
+        const int ym = y == 0 ? a.ny - 1 : y - 1, yp = y == a.ny - 1 ? 0 : y + 1;
+        const int zm = z == 0 ? a.nz - 1 : z - 1, zp = z == a.nz - 1 ? 0 : z + 1;
+        const double csh = a.sh0 - a.slope * x;
+        double g[kQ];
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) {
+            const double w = weight(i);
+            if (!((m >> i) & 1u)) {
+                const int sy = CY[i] == 1 ? ym : (CY[i] == -1 ? yp : y);
+                const int sz = CZ[i] == 1 ? zm : (CZ[i] == -1 ? zp : z);
+                const int64_t src = ((int64_t)sz * a.ny + sy) * a.nx + (x - CX[i]);
+                g[i] = (double)a.fin[(int64_t)i * a.N + src] + w * CX[i] * a.slope;
+            } else {
+                const double own = (double)a.fin[(int64_t)OPP[i] * a.N + v];
+                bool anti = false;
+                double ab = 0.0;
+                if (CX[i] == 1 && x == 0) {
+                    anti = (m >> (19 + FACE_SLOT[i])) & 1u;
+                    ab = a.ab_in;
+                } else if (CX[i] == -1 && x == a.nx - 1) {
+                    anti = (m >> (24 + FACE_SLOT[i])) & 1u;
+                    ab = a.ab_out;
+                }
+                g[i] = anti ? -own + w * ab : own;
+            }
+        }
+        double sum = 0.0;
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) sum += g[i];
+        const double C = csh + sum;
+        const double om = (double)a.omega[v];
+        const double knv = REACT ? (double)a.kn[v] : 0.0;
+        const double b = (om - knv) * C - om * csh;
+        const double keep = 1.0 - om;
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) a.fout[(int64_t)i * a.N + v] = (float)(keep * g[i] + weight(i) * b);
+        if constexpr (MEASURE) {
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) {
+                if (CX[i] == 0) continue;
+                const double f = g[i] + weight(i) * csh;
+                if (!((m >> i) & 1u)) acc[2] += CX[i] * f;
+                if (CX[i] == 1 && x == 0 && ((m >> (19 + FACE_SLOT[i])) & 1u))
+                    acc[0] += 2.0 * f - 2.0 * weight(i) * a.c_in;
+                if (!REACT && CX[i] == -1 && x == a.nx - 1 && ((m >> (24 + FACE_SLOT[i])) & 1u))
+                    acc[1] += 2.0 * weight(i) * a.c_out - 2.0 * f;
+            }
+            acc[3] = knv * C;
+            acc[4] = C;
+            acc[5] = fabs(C - (double)a.csnap[v]);
+            a.csnap[v] = (float)C;
+            acc[6] = fabs(C);
+            acc[7] = (C == C) ? 0.0 : 1.0;
+        }
+    }
+    if constexpr (MEASURE) {
+        __shared__ double red[kBlock / 64][kRed];
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+        for (int k = 0; k < kRed; ++k) {
+            const double s = (k == 5 || k == 6) ? wave_max(acc[k]) : wave_sum(acc[k]);
+            if (lane == 0) red[wv][k] = s;
+        }
+        __syncthreads();
+        if (threadIdx.x < kRed) {
+            const int k = threadIdx.x;
+            double s = red[0][k];
+            for (int w = 1; w < kBlock / 64; ++w) s = (k == 5 || k == 6) ? fmax(s, red[w][k]) : s + red[w][k];
+            a.part[(int64_t)blockIdx.x * kRed + k] = s;
+        }
+    }
+}
+
+// Fixed-order final reduction of the per-block partials (one block).
+__global__ __launch_bounds__(kBlock) void k_d3q19_reduce(const double *__restrict__ part, int nblk,
+                                                         double *__restrict__ out) {
+    __shared__ double red[kBlock / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int k = 0; k < kRed; ++k) {
+        const bool mx = k == 5 || k == 6;
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += kBlock) {
+            const double p = part[(int64_t)b * kRed + k];
+            s = mx ? fmax(s, p) : s + p;
+        }
+        s = mx ? wave_max(s) : wave_sum(s);
+        if (lane == 0) red[wv] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = red[0];
+            for (int w = 1; w < kBlock / 64; ++w) t = mx ? fmax(t, red[w]) : t + red[w];
+            out[k] = t;
+        }
+        __syncthreads();
+    }
+}
+
+// Stored state from a concentration field (f_i = a_i C0, NULL: C0 = 0), and the
+// snapshot C used by the first window residual.  Entries off the simulated
+// voxels are never read by the step.
+__global__ __launch_bounds__(kBlock) void k_d3q19_init(float *__restrict__ f, const uint32_t *__restrict__ mask,
+                                                       const float *__restrict__ c0, float *__restrict__ csnap,
+                                                       int64_t N, int nx, double sh0, double slope) {
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v >= N) return;
+    const bool act = (mask[v] & kActive) != 0;
+    const double C = act && c0 ? (double)c0[v] : 0.0;
+    const double csh = sh0 - slope * (double)(v % nx);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) f[(int64_t)i * N + v] = act ? (float)(weight(i) * (C - csh)) : 0.f;
+    csnap[v] = (float)C;
+}
+
+// Unshifted FP64 populations of the stored (post-collision) state.
+__global__ __launch_bounds__(kBlock) void k_d3q19_unshift(const float *__restrict__ f, const uint32_t *__restrict__ mask,
+                                                          double *__restrict__ out, int64_t N, int nx, double sh0,
+                                                          double slope) {
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v >= N) return;
+    const bool act = (mask[v] & kActive) != 0;
+    const double csh = sh0 - slope * (double)(v % nx);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i)
+        out[(int64_t)i * N + v] = act ? (double)f[(int64_t)i * N + v] + weight(i) * csh : 0.0;
+}
+
+// C of the state: the stored populations sum to (1 - k n) C after the collision.
+__global__ __launch_bounds__(kBlock) void k_d3q19_conc(const float *__restrict__ f, const uint32_t *__restrict__ mask,
+                                                       const float *__restrict__ kn, float *__restrict__ c, int64_t N,
+                                                       int nx, double sh0, double slope) {
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v >= N) return;
+    if (!(mask[v] & kActive)) {
+        c[v] = 0.f;
+        return;
+    }
+    double s = sh0 - slope * (double)(v % nx);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) s += (double)f[(int64_t)i * N + v];
+    c[v] = (float)(kn ? s / (1.0 - (double)kn[v]) : s);
+}
+
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+int wrapi(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+}  // namespace
+
+struct lbm19_solver {
+    cl::Prepared P;
+    bool react = false;
+    int64_t N = 0;
+    int nblk = 0;
+    double d0_lat = 0, ab_in = 0, ab_out = 0;
+    std::vector<uint32_t> mask;
+    std::vector<float> kn;
+    // workspace carve-up
+    size_t off_f[2] = {0, 0}, off_mask = 0, off_om = 0, off_kn = 0, off_cs = 0, off_part = 0, off_red = 0, need = 0;
+    char *ws = nullptr;
+    hipStream_t st = nullptr;
+    int device = 0;
+    int cur = 0;
+    int64_t steps = 0;
+    int measured = 0;
+    lbm_run_info last{};
+    double red[kRed] = {};
+
+    template <class T>
+    T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
+
+    D19Args args(bool measure) {
+        D19Args a{};
+        a.fin = at<float>(off_f[cur]);
+        a.fout = at<float>(off_f[cur ^ 1]);
+        a.mask = at<uint32_t>(off_mask);
+        a.omega = at<float>(off_om);
+        a.kn = react ? at<float>(off_kn) : nullptr;
+        a.csnap = at<float>(off_cs);
+        a.part = measure ? at<double>(off_part) : nullptr;
+        a.N = N;
+        a.nx = P.nx;
+        a.ny = P.ny;
+        a.nz = P.nz;
+        a.nblk = nblk;
+        a.sh0 = P.sh0;
+        a.slope = P.slope;
+        a.ab_in = ab_in;
+        a.ab_out = ab_out;
+        a.c_in = P.params.c_in;
+        a.c_out = P.params.c_out;
+        return a;
+    }
+
+    hipError_t launch(bool measure) {
+        const D19Args a = args(measure);
+        if (react) {
+            if (measure)
+                k_d3q19<true, true><<<nblk, kBlock, 0, st>>>(a);
+            else
+                k_d3q19<true, false><<<nblk, kBlock, 0, st>>>(a);
+        } else {
+            if (measure)
+                k_d3q19<false, true><<<nblk, kBlock, 0, st>>>(a);
+            else
+                k_d3q19<false, false><<<nblk, kBlock, 0, st>>>(a);
+        }
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess && measure) {
+            k_d3q19_reduce<<<1, kBlock, 0, st>>>(at<double>(off_part), nblk, at<double>(off_red));
+            e = hipGetLastError();
+        }
+        cur ^= 1;
+        ++steps;
+        return e;
+    }
+
+    // one measured step; fills `last` from the reduction
+    int measure_step(int64_t window) {
+        hipError_t e = launch(true);
+        if (e == hipSuccess) e = hipMemcpyAsync(red, at<double>(off_red), sizeof(red), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return cl::record_error(e, "lbm19 measure");
+        const double A = (double)P.ny * P.nz;
+        last.steps = steps;
+        last.j_in = red[0] / A;
+        last.j_out = red[1] / A;
+        last.j_vol = P.nx > 1 ? red[2] / (P.nx - 1) / A : red[0] / A;
+        last.rate = red[3] / A;
+        last.mass = red[4];
+        last.residual = red[6] > 0 ? red[5] / ((double)std::max<int64_t>(window, 1) * red[6]) : 0.0;
+        measured = 1;
+        if (red[7] != 0.0 || !std::isfinite(red[4])) return LBM_ERR_DIVERGED;
+        return LBM_OK;
+    }
+};
+
+extern "C" {
+
+int lbm19_create(const lbm_grid *g, const uint8_t *phase, const lbm_params *p, lbm19_solver **out) {
+    try {
+        if (!g || !phase || !p || !out) return LBM_ERR_INVALID_ARG;
+        *out = nullptr;
+        auto s = std::make_unique<lbm19_solver>();
+        const int st = cl::prepare(*g, phase, *p, s->P);
+        if (st != LBM_OK) return st;
+        cl::Prepared &P = s->P;
+        if ((int64_t)kQ * P.nx * P.ny * P.nz > ((int64_t)1 << 40)) return LBM_ERR_INVALID_ARG;
+        s->react = P.mode == LBM_MODE_REACT;
+        s->N = (int64_t)P.nx * P.ny * P.nz;
+        if (s->N > (int64_t)INT32_MAX) return LBM_ERR_INVALID_ARG;  // voxel index in 32 bits
+        s->nblk = (int)((s->N + kBlock - 1) / kBlock);
+        s->d0_lat = (P.params.tau_ref - 0.5) * P.d0 / (3.0 * P.d_ref);
+        s->ab_in = 2.0 * (P.params.c_in - P.sh0);
+        s->ab_out = 2.0 * (P.params.c_out - (P.sh0 - P.slope * (P.nx - 1)));
+        const int nx = P.nx, ny = P.ny, nz = P.nz;
+        s->mask.assign(s->N, 0u);
+        s->kn.assign(s->react ? s->N : 0, 0.f);
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    const int64_t v = ((int64_t)z * ny + y) * nx + x;
+                    if (!P.active[v]) continue;
+                    uint32_t m = kActive;
+                    for (int i = 0; i < kQ; ++i) {
+                        const int sx = x - CX[i], sy = wrapi(y - CY[i], ny), sz = wrapi(z - CZ[i], nz);
+                        const int64_t plane = ((int64_t)sz * ny + sy) * nx;
+                        if (sx < 0 || sx >= nx || !P.active[plane + sx]) m |= 1u << i;
+                        // a face link is open when the boundary-plane voxel it passes is simulated
+                        if (CX[i] == 1 && x == 0 && P.active[plane]) m |= 1u << (19 + FACE_SLOT[i]);
+                        if (CX[i] == -1 && x == nx - 1 && !s->react && P.active[plane + nx - 1])
+                            m |= 1u << (24 + FACE_SLOT[i]);
+                    }
+                    s->mask[v] = m;
+                    if (s->react && ((P.params.reactive_fluids >> P.phase[v]) & 1u))
+                        s->kn[v] = (float)(P.params.k_lat * P.n_cat[v]);
+                }
+        // workspace: two lattices, mask, omega, k n, C snapshot, partials, result
+        size_t o = 0;
+        const size_t fb = align256(sizeof(float) * kQ * (size_t)s->N), nb4 = align256(4 * (size_t)s->N);
+        s->off_f[0] = o;
+        o += fb;
+        s->off_f[1] = o;
+        o += fb;
+        s->off_mask = o;
+        o += nb4;
+        s->off_om = o;
+        o += nb4;
+        s->off_kn = o;
+        o += s->react ? nb4 : 0;
+        s->off_cs = o;
+        o += nb4;
+        s->off_part = o;
+        o += align256(sizeof(double) * kRed * (size_t)s->nblk);
+        s->off_red = o;
+        o += align256(sizeof(double) * kRed);
+        s->need = o;
+        *out = s.release();
+        return LBM_OK;
+    } catch (...) {
+        return LBM_ERR_INVALID_ARG;
+    }
+}
+
+int lbm19_get_info(const lbm19_solver *s, lbm_info *info) {
+    if (!s || !info) return LBM_ERR_INVALID_ARG;
+    std::memset(info, 0, sizeof(*info));
+    const cl::Prepared &P = s->P;
+    info->nx = P.nx;
+    info->ny = P.ny;
+    info->nz = P.nz;
+    info->nx_struct = P.nx_struct;
+    int64_t n = 0;
+    for (uint8_t a : P.active) n += a ? 1 : 0;
+    info->n_active = n;
+    info->n_segments = 0;
+    info->d0 = P.d0;
+    info->d_ref = P.d_ref;
+    info->d0_lat = s->d0_lat;
+    info->percolates = P.percolates ? 1 : 0;
+    info->mode = P.mode;
+    return LBM_OK;
+}
+
+int lbm19_workspace_bytes(const lbm19_solver *s, size_t *bytes) {
+    if (!s || !bytes) return LBM_ERR_INVALID_ARG;
+    *bytes = s->need;
+    return LBM_OK;
+}
+
+int lbm19_bind(lbm19_solver *s, void *ws, size_t bytes, void *stream) {
+    if (!s || !ws || (reinterpret_cast<uintptr_t>(ws) & 255u)) return LBM_ERR_WORKSPACE;
+    if (bytes < s->need) return LBM_ERR_WORKSPACE;
+    s->ws = static_cast<char *>(ws);
+    s->st = static_cast<hipStream_t>(stream);
+    hipError_t e = hipGetDevice(&s->device);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->at<uint32_t>(s->off_mask), s->mask.data(), 4 * (size_t)s->N, hipMemcpyHostToDevice, s->st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->at<float>(s->off_om), s->P.omega_dense.data(), 4 * (size_t)s->N, hipMemcpyHostToDevice,
+                           s->st);
+    if (e == hipSuccess && s->react)
+        e = hipMemcpyAsync(s->at<float>(s->off_kn), s->kn.data(), 4 * (size_t)s->N, hipMemcpyHostToDevice, s->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+    if (e != hipSuccess) {
+        s->ws = nullptr;
+        return cl::record_error(e, "lbm19_bind");
+    }
+    return lbm19_set_initial_concentration(s, nullptr);
+}
+
+int lbm19_set_initial_concentration(lbm19_solver *s, const float *c_dev) {
+    if (!s) return LBM_ERR_INVALID_ARG;
+    if (!s->ws) return LBM_ERR_UNBOUND;
+    const int nb = (int)((s->N + kBlock - 1) / kBlock);
+    s->cur = 0;
+    k_d3q19_init<<<nb, kBlock, 0, s->st>>>(s->at<float>(s->off_f[0]), s->at<uint32_t>(s->off_mask), c_dev,
+                                           s->at<float>(s->off_cs), s->N, s->P.nx, s->P.sh0, s->P.slope);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+    s->steps = 0;
+    s->measured = 0;
+    std::memset(&s->last, 0, sizeof(s->last));
+    return e == hipSuccess ? LBM_OK : cl::record_error(e, "lbm19_set_initial_concentration");
+}
+
+int lbm19_step(lbm19_solver *s, int64_t nsteps) {
+    if (!s || nsteps < 0) return LBM_ERR_INVALID_ARG;
+    if (!s->ws) return LBM_ERR_UNBOUND;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        const hipError_t e = s->launch(false);
+        if (e != hipSuccess) return cl::record_error(e, "lbm19_step");
+    }
+    return LBM_OK;
+}
+
+int lbm19_measure(lbm19_solver *s, lbm_run_info *info) {
+    if (!s) return LBM_ERR_INVALID_ARG;
+    if (!s->ws) return LBM_ERR_UNBOUND;
+    const int st = s->measure_step(1);
+    s->last.status = st;
+    if (info) *info = s->last;
+    return st;
+}
+
+int lbm19_run_to_steady(lbm19_solver *s, lbm_run_info *info) {
+    if (!s) return LBM_ERR_INVALID_ARG;
+    if (!s->ws) return LBM_ERR_UNBOUND;
+    const lbm_params &p = s->P.params;
+    if (!s->react && !s->P.percolates) {
+        s->last.status = LBM_ERR_NO_PERCOLATION;
+        if (info) *info = s->last;
+        return LBM_ERR_NO_PERCOLATION;
+    }
+    const int64_t K = std::max<int64_t>(2, p.check_every);
+    // Stop when, over windows of K steps, (i) the C field moves by less than
+    // tol_change per step relative to max C, (ii) the output (mean interior flux,
+    // or the total sink when reacting) is within tol_flux of its limit, estimated
+    // from the ratio rho of successive window changes as |d| max(1, rho/(1-rho)),
+    // on two checks in a row, and (iii) the mass balance J_in - J_out - R closes
+    // to tol_balance of J_in.
+    double q[3] = {0, 0, 0};
+    int nq = 0, good = 0, st = LBM_NOT_CONVERGED;
+    s->last.checks = 0;
+    while (s->steps < p.max_steps) {
+        const int64_t w = std::min<int64_t>(K, p.max_steps - s->steps);
+        int rc = lbm19_step(s, w - 1);
+        if (rc == LBM_OK) rc = s->measure_step(w);
+        if (rc != LBM_OK) {
+            st = rc;
+            break;
+        }
+        ++s->last.checks;
+        const double qk = s->react ? s->last.rate : s->last.j_vol;
+        q[0] = q[1];
+        q[1] = q[2];
+        q[2] = qk;
+        nq = std::min(nq + 1, 3);
+        double est = INFINITY;
+        if (nq == 3 && qk != 0.0) {
+            const double d1 = q[2] - q[1], d0 = q[1] - q[0];
+            const double rho = d0 != 0.0 ? d1 / d0 : 0.0;
+            if (rho < 1.0) est = std::fabs(d1) / std::fabs(qk) * std::max(1.0, rho > 0 ? rho / (1.0 - rho) : 0.0);
+        }
+        s->last.est_error = est;
+        const double bal = s->last.j_in != 0.0
+                               ? std::fabs(s->last.j_in - s->last.j_out - s->last.rate) / std::fabs(s->last.j_in)
+                               : INFINITY;
+        const bool ok = s->last.residual < p.tol_change && est < p.tol_flux && bal < p.tol_balance;
+        good = ok ? good + 1 : 0;
+        if (good >= 2) {
+            st = LBM_OK;
+            break;
+        }
+    }
+    s->last.status = st;
+    if (info) *info = s->last;
+    return st;
+}
+
+int lbm19_deff(const lbm19_solver *s, double *out) {
+    if (!s || !out) return LBM_ERR_INVALID_ARG;
+    if (s->react) return LBM_ERR_WRONG_MODE;
+    if (!s->P.percolates) {
+        *out = 0.0;
+        return LBM_ERR_NO_PERCOLATION;
+    }
+    if (!s->measured) return LBM_ERR_UNBOUND;
+    const double dc = s->P.params.c_in - s->P.params.c_out;
+    if (dc == 0.0) return LBM_ERR_INVALID_ARG;
+    *out = s->last.j_vol * s->P.nx / (dc * s->d0_lat);
+    return s->last.status == LBM_NOT_CONVERGED ? LBM_NOT_CONVERGED : LBM_OK;
+}
+
+int lbm19_reaction_rate(const lbm19_solver *s, double *rate, double *jin) {
+    if (!s) return LBM_ERR_INVALID_ARG;
+    if (!s->react) return LBM_ERR_WRONG_MODE;
+    if (!s->measured) return LBM_ERR_UNBOUND;
+    if (rate) *rate = s->last.rate;
+    if (jin) *jin = s->last.j_in;
+    return s->last.status == LBM_NOT_CONVERGED ? LBM_NOT_CONVERGED : LBM_OK;
+}
+
+int lbm19_get_populations(const lbm19_solver *s, double *f_dev) {
+    if (!s || !f_dev) return LBM_ERR_INVALID_ARG;
+    if (!s->ws) return LBM_ERR_UNBOUND;
+    const int nb = (int)((s->N + kBlock - 1) / kBlock);
+    k_d3q19_unshift<<<nb, kBlock, 0, s->st>>>(s->at<float>(s->off_f[s->cur]), s->at<uint32_t>(s->off_mask), f_dev,
+                                              s->N, s->P.nx, s->P.sh0, s->P.slope);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+    return e == hipSuccess ? LBM_OK : cl::record_error(e, "lbm19_get_populations");
+}
+
+int lbm19_concentration(const lbm19_solver *s, float *c_dev) {
+    if (!s || !c_dev) return LBM_ERR_INVALID_ARG;
+    if (!s->ws) return LBM_ERR_UNBOUND;
+    const int nb = (int)((s->N + kBlock - 1) / kBlock);
+    k_d3q19_conc<<<nb, kBlock, 0, s->st>>>(s->at<float>(s->off_f[s->cur]), s->at<uint32_t>(s->off_mask),
+                                           s->react ? s->at<float>(s->off_kn) : nullptr, c_dev, s->N, s->P.nx,
+                                           s->P.sh0, s->P.slope);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+    return e == hipSuccess ? LBM_OK : cl::record_error(e, "lbm19_concentration");
+}
+
+void lbm19_destroy(lbm19_solver *s) { delete s; }
+
+}  // extern "C"

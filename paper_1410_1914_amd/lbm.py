@@ -119,6 +119,19 @@ SIGNATURES = {
                                    ctypes.POINTER(c_float)], c_int32),
     "lbm_batch_get_pore_depth": ([_P, c_int32, ctypes.POINTER(c_uint8)], c_int32),
     "lbm_batch_destroy": ([_P], None),
+    "lbm19_create": ([ctypes.POINTER(lbm_grid), ctypes.POINTER(c_uint8), ctypes.POINTER(lbm_params), _PP], c_int32),
+    "lbm19_get_info": ([_P, ctypes.POINTER(lbm_info)], c_int32),
+    "lbm19_workspace_bytes": ([_P, ctypes.POINTER(ctypes.c_size_t)], c_int32),
+    "lbm19_bind": ([_P, _P, ctypes.c_size_t, _P], c_int32),
+    "lbm19_set_initial_concentration": ([_P, _P], c_int32),
+    "lbm19_step": ([_P, c_int64], c_int32),
+    "lbm19_measure": ([_P, ctypes.POINTER(lbm_run_info)], c_int32),
+    "lbm19_run_to_steady": ([_P, ctypes.POINTER(lbm_run_info)], c_int32),
+    "lbm19_deff": ([_P, ctypes.POINTER(c_double)], c_int32),
+    "lbm19_reaction_rate": ([_P, ctypes.POINTER(c_double), ctypes.POINTER(c_double)], c_int32),
+    "lbm19_get_populations": ([_P, _P], c_int32),
+    "lbm19_concentration": ([_P, _P], c_int32),
+    "lbm19_destroy": ([_P], None),
 }
 
 
@@ -580,6 +593,117 @@ class Solver:
         try:
             if getattr(self, "h", None):
                 lbm_destroy(self.h)
+        except Exception:
+            pass
+
+
+class Solver19:
+    """One structure on the D3Q19 lattice (Section 4, Eqs. 21-24); same problems
+    and parameters as Solver, dense storage in a torch-owned workspace."""
+
+    Q = 19
+
+    def __init__(self, phase: np.ndarray, params: lbm_params | None = None, voxel_m: float = 2e-9,
+                 device: str = "cuda", stream=None, **overrides):
+        import torch
+
+        require_gpu()
+        lib = load()
+        self.params = params if params is not None else lbm_params_default()
+        for k, v in overrides.items():
+            setattr(self.params, k, v)
+        ph = np.ascontiguousarray(phase, dtype=np.uint8)
+        if ph.ndim != 3:
+            raise ValueError("phase map must be (nz, ny, nx)")
+        nz, ny, nx = ph.shape
+        g = lbm_grid(nx, ny, nz, voxel_m)
+        self.h = ctypes.c_void_p()
+        _check("lbm19_create", lib.lbm19_create(ctypes.byref(g), ph.ctypes.data_as(ctypes.POINTER(c_uint8)),
+                                                ctypes.byref(self.params), ctypes.byref(self.h)))
+        self.info = lbm_info()
+        _check("lbm19_get_info", lib.lbm19_get_info(self.h, ctypes.byref(self.info)))
+        n = ctypes.c_size_t()
+        _check("lbm19_workspace_bytes", lib.lbm19_workspace_bytes(self.h, ctypes.byref(n)))
+        self.nbytes = n.value
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        self.ws = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
+        self.ws_ptr = (self.ws.data_ptr() + 255) // 256 * 256
+        torch.cuda.synchronize(self.device)
+        with torch.cuda.device(self.device):
+            _check("lbm19_bind", lib.lbm19_bind(self.h, self.ws_ptr, self.nbytes, self.stream.cuda_stream))
+
+    @property
+    def shape(self):
+        return (self.info.nz, self.info.ny, self.info.nx)
+
+    @property
+    def N(self):
+        return self.info.nx * self.info.ny * self.info.nz
+
+    def set_initial_concentration(self, c=None):
+        import torch
+
+        if c is None:
+            return _check("lbm19_set_initial_concentration", load().lbm19_set_initial_concentration(self.h, None))
+        c = torch.as_tensor(c, dtype=torch.float32, device=self.device).contiguous()
+        assert c.numel() == self.N
+        torch.cuda.current_stream(self.device).synchronize()
+        return _check("lbm19_set_initial_concentration",
+                      load().lbm19_set_initial_concentration(self.h, c.data_ptr()))
+
+    def step(self, n=1):
+        return _check("lbm19_step", load().lbm19_step(self.h, n))
+
+    def measure(self) -> lbm_run_info:
+        r = lbm_run_info()
+        _check("lbm19_measure", load().lbm19_measure(self.h, ctypes.byref(r)))
+        return r
+
+    def run_to_steady(self):
+        r = lbm_run_info()
+        st = load().lbm19_run_to_steady(self.h, ctypes.byref(r))
+        if st < 0 and st != ERR_NO_PERCOLATION:
+            raise LbmError("lbm19_run_to_steady", st)
+        return st, r
+
+    def deff(self):
+        d = c_double()
+        st = load().lbm19_deff(self.h, ctypes.byref(d))
+        if st < 0 and st != ERR_NO_PERCOLATION:
+            raise LbmError("lbm19_deff", st)
+        return st, d.value
+
+    def reaction_rate(self):
+        r, j = c_double(), c_double()
+        st = _check("lbm19_reaction_rate", load().lbm19_reaction_rate(self.h, ctypes.byref(r), ctypes.byref(j)))
+        return st, r.value, j.value
+
+    def populations(self):
+        """Unshifted FP64 post-collision populations, (19, nz, ny, nx)."""
+        import torch
+
+        out = torch.empty((self.Q,) + self.shape, dtype=torch.float64, device=self.device)
+        torch.cuda.current_stream(self.device).synchronize()
+        _check("lbm19_get_populations", load().lbm19_get_populations(self.h, out.data_ptr()))
+        return out
+
+    def concentration(self):
+        import torch
+
+        out = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+        torch.cuda.current_stream(self.device).synchronize()
+        _check("lbm19_concentration", load().lbm19_concentration(self.h, out.data_ptr()))
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().lbm19_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
         except Exception:
             pass
 

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared(header):
     text = open(os.path.join(ROOT, "include", header)).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lbm_\w+|unet_\w+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(lbm(?:19)?_\w+|unet_\w+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -252,3 +252,57 @@ def test_device_characterisation_rejects_bad_arguments():
         assert lib.lbm_reach_device(fake, 4, 4, 4, faces, fake, None, None) == lbm.ERR_INVALID_ARG
     assert lib.lbm_reach_device(None, 4, 4, 4, 1, fake, None, None) == lbm.ERR_INVALID_ARG
     assert lib.lbm_reach_device(fake, 4, -2, 4, 1, fake, None, None) == lbm.ERR_INVALID_ARG
+
+
+def test_d3q19_entry_points_on_the_host():
+    """lbm19_*: creation, info (D0 in lattice units with c_s^2 = 1/3), workspace
+    size and the errors that need no device."""
+    L = lbm.load()
+    import ctypes
+
+    ph = np.zeros((4, 5, 8), np.uint8)
+    ph[:, 0, :] = lbm.CARBON
+
+    def create(phase, **kw):
+        p = lbm.lbm_params_default(**kw)
+        g = lbm.lbm_grid(phase.shape[2], phase.shape[1], phase.shape[0], 2e-9)
+        h = ctypes.c_void_p()
+        st = L.lbm19_create(ctypes.byref(g), np.ascontiguousarray(phase).ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                            ctypes.byref(p), ctypes.byref(h))
+        return st, h
+
+    st, h = create(ph, tau_ref=0.8)
+    assert st == 0
+    try:
+        info = lbm.lbm_info()
+        assert L.lbm19_get_info(h, ctypes.byref(info)) == 0
+        assert (info.nx, info.ny, info.nz, info.n_active) == (8, 5, 4, 4 * 4 * 8)
+        assert info.d0_lat == pytest.approx((0.8 - 0.5) / 3 * info.d0 / info.d_ref, rel=1e-15)
+        n = ctypes.c_size_t()
+        assert L.lbm19_workspace_bytes(h, ctypes.byref(n)) == 0
+        N = 8 * 5 * 4
+        assert n.value >= 2 * 19 * 4 * N + 3 * 4 * N
+        assert L.lbm19_step(h, 1) == lbm.ERR_UNBOUND
+        assert L.lbm19_step(h, -1) == lbm.ERR_INVALID_ARG
+        d = ctypes.c_double()
+        assert L.lbm19_deff(h, ctypes.byref(d)) == lbm.ERR_UNBOUND
+        r, j = ctypes.c_double(), ctypes.c_double()
+        assert L.lbm19_reaction_rate(h, ctypes.byref(r), ctypes.byref(j)) == lbm.ERR_WRONG_MODE
+        assert L.lbm19_bind(h, None, n.value, None) == -8  # LBM_ERR_WORKSPACE
+    finally:
+        L.lbm19_destroy(h)
+    # the same parameter checks as lbm_create
+    for kw in (dict(tau_ref=0.5), dict(k_lat=-1.0), dict(struct_size=4), dict(mode=7)):
+        assert create(ph, **kw)[0] == lbm.ERR_INVALID_ARG, kw
+    bad = ph.copy()
+    bad[0, 1, 1] = 9
+    assert create(bad)[0] == lbm.ERR_BAD_PHASE
+    # no transport path between the faces
+    blocked = ph.copy()
+    blocked[:, :, 3] = lbm.CARBON
+    st, h = create(blocked)
+    assert st == 0
+    d = ctypes.c_double()
+    assert L.lbm19_deff(h, ctypes.byref(d)) == lbm.ERR_NO_PERCOLATION and d.value == 0.0
+    L.lbm19_destroy(h)
+    L.lbm19_destroy(None)
