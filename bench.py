@@ -55,6 +55,7 @@ def parse():
     ap.add_argument("--no-solves", action="store_true", help="skip the 32^3 solves/s legs")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-start leg")
     ap.add_argument("--no-charz", action="store_true", help="skip the device structure-characterisation leg")
+    ap.add_argument("--no-d3q19", action="store_true", help="skip the D3Q19 (paper's lattice) leg")
     ap.add_argument("--warm-deff", action="store_true",
                     help="run the effective-diffusivity warm-start comparison at 192^3 instead of 96^3 (several minutes)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU time budget of the oracle sample")
@@ -183,6 +184,36 @@ def headline(args, lbm, structgen):
            "kernel_mlups": info.n_active * spl / per_launch_s / 1e6,
            "rate_per_area_after": r.rate, "steps_taken": r.steps}
     return res, ph
+
+
+def d3q19_leg(lbm, ph, args):
+    """The paper's own lattice (D3Q19, dense storage) on the headline structure and
+    problem: kernel time per step from HIP events on the solver's stream, and the
+    fraction of HBM peak its algorithmic bytes reach."""
+    import torch
+
+    p = lbm.lbm_params_default(mode=lbm.MODE_REACT, knudsen=1, k_lat=1e-4,
+                               catalyst_phases=(1 << lbm.CARBON) | (1 << lbm.PT))
+    s = lbm.Solver19(ph, p, voxel_m=1e-9)
+    n_act, N = s.info.n_active, s.N
+    s.step(50)
+    steps = 200
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s.stream)
+    s.step(steps)
+    e1.record(s.stream)
+    e1.synchronize()
+    per_step_s = e0.elapsed_time(e1) / 1e3 / steps
+    # per simulated voxel: 19 FP32 reads and writes, mask, omega, k n; mask alone elsewhere
+    alg = n_act * (19 * 4 * 2 + 4 + 4 + 4) + (N - n_act) * 4
+    gbs = alg / per_step_s / 1e9
+    out = {"kernel": "k_d3q19<true,false> (dense pull stream-collide, reactive)",
+           "mean_launch_us": round(per_step_s * 1e6, 2), "mlups": round(n_act / per_step_s / 1e6, 1),
+           "alg_bytes_per_launch": int(alg), "achieved_gbs": round(gbs, 1),
+           "frac": round(gbs / HBM_PEAK_GBS, 4), "steps_timed": steps}
+    log(f"[bench] D3Q19 leg: {out['mean_launch_us']} us per step, {out['mlups']} MLUPS, {out['frac']:.3f} of HBM peak")
+    s.close()
+    return out
 
 
 def other_form(s, args, chosen):
@@ -412,6 +443,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline(args, ph, structgen)
     if not args.no_charz:
         out["characterise"] = charz_leg(lbm, ph)
+    if not args.no_d3q19:
+        out["d3q19"] = d3q19_leg(lbm, ph, args)
     del ph
     if not args.no_solves:
         log("[bench] 32^3 solves/s legs ...")

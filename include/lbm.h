@@ -334,16 +334,17 @@ int lbm_reach_device(const uint8_t *pass_dev, int32_t nx, int32_t ny, int32_t nz
  * zero-gradient (bounce-back).
  *
  * Memory: dense over the simulated grid.  lbm19_workspace_bytes gives the size
- * of the caller-owned device workspace (two FP32 lattices of 19 N values plus
- * 16 N bytes of per-voxel data and small reduction buffers, N = nx ny nz of the
- * simulated grid); lbm19_bind takes it (256-byte aligned) with a hipStream_t
- * (NULL: the null stream) on which all work is queued, uploads the per-voxel
- * data and sets the cold start (C = 0).  The workspace must outlive the solver's
+ * of the caller-owned device workspace: two FP32 lattices of 19 planes of N
+ * values (each plane padded by at most 4.5 KB), 16 N bytes of per-voxel data
+ * and small reduction buffers, N = nx ny nz of the simulated grid.
+ * lbm19_bind takes it (256-byte aligned) with a hipStream_t (NULL: the null
+ * stream) on which all work is queued, uploads the per-voxel data and sets the
+ * cold start (C = 0).  The workspace must outlive the solver's
  * use of it.  Calls that return host values synchronise the stream.  One solver
  * per thread.
  *
- * lbm19_create: as lbm_create.  Also LBM_ERR_INVALID_ARG when the simulated grid
- *   has more than 2^31 - 1 voxels.
+ * lbm19_create: as lbm_create.  Also LBM_ERR_INVALID_ARG when one lattice would
+ *   reach 4 GiB (more than about 56 million simulated voxels, ~383^3).
  * lbm19_set_initial_concentration: stored state f_i = a_i C0 with C0 a device
  *   FP32 array of N values (NULL: C0 = 0); resets the step count.
  * lbm19_step: nsteps steps of Eq. (21).

@@ -1,8 +1,9 @@
 // D3Q19 variant of the solver: the lattice the paper itself uses (Chen et al.,
 // arXiv 1410.1914, Section 4, Eqs. 21-24), beside the D3Q7 production path.
 //
-// Storage is dense over the simulated grid, population-major: f[i * N + v] with
-// v = (z * ny + y) * nx + x, FP32, holding the post-collision value shifted by
+// Storage is dense over the simulated grid in blocks of 64 voxels (one wave):
+// f[(v >> 6) * 19 * 64 + i * 64 + (v & 63)] with v = (z * ny + y) * nx + x, so a
+// wave's nineteen populations are one contiguous 4864-byte block, FP32, holding the post-collision value shifted by
 // a_i * c_sh(x) (c_sh = sh0 - slope * x, the empty-box profile between Dirichlet
 // faces, or half the inlet value when reacting), two lattices A/B.  Per voxel a
 // 32-bit word says which pull sources are missing (bits 0-18), which face links
@@ -64,6 +65,23 @@ __device__ __forceinline__ int64_t xcd_block(int b, int nblk) {
     return (int64_t)x * q + min(x, r) + (b >> 3);
 }
 
+// position of population i of voxel v in a lattice
+__host__ __device__ __forceinline__ int64_t fidx(int i, int64_t v) { return (v >> 6) * (kQ * 64) + i * 64 + (v & 63); }
+
+// the same as a byte offset in 32 bits (a lattice is kept below 4 GiB), so that
+// loads and stores take the uniform base plus one 32-bit lane offset
+__device__ __forceinline__ uint32_t fbyte(int i, uint32_t v) {
+    return ((v >> 6) * (kQ * 64) + (uint32_t)i * 64 + (v & 63)) * 4u;
+}
+
+__device__ __forceinline__ float ld(const float *base, uint32_t byte) {
+    return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(base) + byte);
+}
+
+__device__ __forceinline__ void st(float *base, uint32_t byte, float val) {
+    *reinterpret_cast<float *>(reinterpret_cast<char *>(base) + byte) = val;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
@@ -82,36 +100,51 @@ template <bool REACT, bool MEASURE>
 __global__ __launch_bounds__(kBlock) void k_d3q19(D19Args a) {
     const int64_t v = xcd_block(blockIdx.x, a.nblk) * kBlock + threadIdx.x;
     double acc[kRed] = {0, 0, 0, 0, 0, 0, 0, 0};
-    const uint32_t m = v < a.N ? a.mask[v] : 0u;
-    if (m & kActive) {
-        const uint32_t vv = (uint32_t)v, r = vv / (uint32_t)a.nx;
-        const int x = (int)(vv - r * (uint32_t)a.nx);
-        const int z = (int)(r / (uint32_t)a.ny), y = (int)(r - (uint32_t)z * (uint32_t)a.ny);
-        const int ym = y == 0 ? a.ny - 1 : y - 1, yp = y == a.ny - 1 ? 0 : y + 1;
-        const int zm = z == 0 ? a.nz - 1 : z - 1, zp = z == a.nz - 1 ? 0 : z + 1;
+    const uint32_t m0 = v < a.N ? a.mask[v] : 0u;
+    const bool act = (m0 & kActive) != 0;
+    // A wave with any simulated voxel stores every lane, so that the lattice's
+    // cache lines leave L2 whole: a lane off the simulated voxels takes all its
+    // populations from its own zeros, and its omega and k n are 0, so it stores
+    // 0 (entries there are never read).
+    const uint32_t m = act ? m0 : (1u << kQ) - 1u;
+    const bool wave_live = __ballot(act) != 0;
+    if (v < a.N && wave_live) {
+        const uint32_t vv = (uint32_t)v, nx = (uint32_t)a.nx, ny = (uint32_t)a.ny, r = vv / nx;
+        const int x = (int)(vv - r * nx);
+        const int z = (int)(r / ny), y = (int)(r - (uint32_t)z * ny);
+        const uint32_t ym = y == 0 ? ny - 1 : y - 1, yp = y == (int)ny - 1 ? 0 : y + 1;
+        const uint32_t zm = z == 0 ? a.nz - 1 : z - 1, zp = z == a.nz - 1 ? 0 : z + 1;
         const double csh = a.sh0 - a.slope * x;
+        // every lane loads each direction once, from its pull source or, when that
+        // source is missing, its own opposite population: one offset select per
+        // direction and no branch, so all nineteen loads are in flight together
+        const uint32_t plane = nx * ny;
+        const uint32_t z0 = (uint32_t)z * plane, zlo = zm * plane, zhi = zp * plane;
+        const uint32_t y0 = (uint32_t)y * nx, ylo = ym * nx, yhi = yp * nx;
+        float raw[kQ];
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) {
+            const uint32_t oy = CY[i] == 1 ? ylo : (CY[i] == -1 ? yhi : y0);
+            const uint32_t oz = CZ[i] == 1 ? zlo : (CZ[i] == -1 ? zhi : z0);
+            const uint32_t pull = fbyte(i, oz + oy + (uint32_t)(x - CX[i]));
+            const uint32_t own = fbyte(OPP[i], vv);
+            raw[i] = ld(a.fin, ((m >> i) & 1u) ? own : pull);
+        }
         double g[kQ];
 #pragma unroll
         for (int i = 0; i < kQ; ++i) {
-            const double w = weight(i);
-            if (!((m >> i) & 1u)) {
-                const int sy = CY[i] == 1 ? ym : (CY[i] == -1 ? yp : y);
-                const int sz = CZ[i] == 1 ? zm : (CZ[i] == -1 ? zp : z);
-                const int64_t src = ((int64_t)sz * a.ny + sy) * a.nx + (x - CX[i]);
-                g[i] = (double)a.fin[(int64_t)i * a.N + src] + w * CX[i] * a.slope;
-            } else {
-                const double own = (double)a.fin[(int64_t)OPP[i] * a.N + v];
-                bool anti = false;
-                double ab = 0.0;
-                if (CX[i] == 1 && x == 0) {
-                    anti = (m >> (19 + FACE_SLOT[i])) & 1u;
-                    ab = a.ab_in;
-                } else if (CX[i] == -1 && x == a.nx - 1) {
-                    anti = (m >> (24 + FACE_SLOT[i])) & 1u;
-                    ab = a.ab_out;
-                }
-                g[i] = anti ? -own + w * ab : own;
+            const double w = weight(i), r = (double)raw[i];
+            const bool blocked = (m >> i) & 1u;
+            bool anti = false;
+            double ab = 0.0;
+            if (CX[i] == 1) {
+                anti = x == 0 && ((m >> (19 + FACE_SLOT[i])) & 1u);
+                ab = a.ab_in;
+            } else if (CX[i] == -1) {
+                anti = x == a.nx - 1 && ((m >> (24 + FACE_SLOT[i])) & 1u);
+                ab = a.ab_out;
             }
+            g[i] = blocked ? (anti ? -r + w * ab : r) : r + w * CX[i] * a.slope;
         }
         double sum = 0.0;
 #pragma unroll
@@ -122,7 +155,7 @@ __global__ __launch_bounds__(kBlock) void k_d3q19(D19Args a) {
         const double b = (om - knv) * C - om * csh;
         const double keep = 1.0 - om;
 #pragma unroll
-        for (int i = 0; i < kQ; ++i) a.fout[(int64_t)i * a.N + v] = (float)(keep * g[i] + weight(i) * b);
+        for (int i = 0; i < kQ; ++i) st(a.fout, fbyte(i, vv), (float)(keep * g[i] + weight(i) * b));
         if constexpr (MEASURE) {
 #pragma unroll
             for (int i = 0; i < kQ; ++i) {
@@ -134,12 +167,16 @@ __global__ __launch_bounds__(kBlock) void k_d3q19(D19Args a) {
                 if (!REACT && CX[i] == -1 && x == a.nx - 1 && ((m >> (24 + FACE_SLOT[i])) & 1u))
                     acc[1] += 2.0 * weight(i) * a.c_out - 2.0 * f;
             }
-            acc[3] = knv * C;
-            acc[4] = C;
-            acc[5] = fabs(C - (double)a.csnap[v]);
-            a.csnap[v] = (float)C;
-            acc[6] = fabs(C);
-            acc[7] = (C == C) ? 0.0 : 1.0;
+            if (act) {
+                acc[3] = knv * C;
+                acc[4] = C;
+                acc[5] = fabs(C - (double)a.csnap[v]);
+                a.csnap[v] = (float)C;
+                acc[6] = fabs(C);
+                acc[7] = (C == C) ? 0.0 : 1.0;
+            } else {
+                acc[0] = acc[1] = acc[2] = 0.0;
+            }
         }
     }
     if constexpr (MEASURE) {
@@ -196,7 +233,7 @@ __global__ __launch_bounds__(kBlock) void k_d3q19_init(float *__restrict__ f, co
     const double C = act && c0 ? (double)c0[v] : 0.0;
     const double csh = sh0 - slope * (double)(v % nx);
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) f[(int64_t)i * N + v] = act ? (float)(weight(i) * (C - csh)) : 0.f;
+    for (int i = 0; i < kQ; ++i) f[fidx(i, v)] = act ? (float)(weight(i) * (C - csh)) : 0.f;
     csnap[v] = (float)C;
 }
 
@@ -210,7 +247,7 @@ __global__ __launch_bounds__(kBlock) void k_d3q19_unshift(const float *__restric
     const double csh = sh0 - slope * (double)(v % nx);
 #pragma unroll
     for (int i = 0; i < kQ; ++i)
-        out[(int64_t)i * N + v] = act ? (double)f[(int64_t)i * N + v] + weight(i) * csh : 0.0;
+        out[(int64_t)i * N + v] = act ? (double)f[fidx(i, v)] + weight(i) * csh : 0.0;
 }
 
 // C of the state: the stored populations sum to (1 - k n) C after the collision.
@@ -225,7 +262,7 @@ __global__ __launch_bounds__(kBlock) void k_d3q19_conc(const float *__restrict__
     }
     double s = sh0 - slope * (double)(v % nx);
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) s += (double)f[(int64_t)i * N + v];
+    for (int i = 0; i < kQ; ++i) s += (double)f[fidx(i, v)];
     c[v] = (float)(kn ? s / (1.0 - (double)kn[v]) : s);
 }
 
@@ -336,7 +373,8 @@ int lbm19_create(const lbm_grid *g, const uint8_t *phase, const lbm_params *p, l
         if ((int64_t)kQ * P.nx * P.ny * P.nz > ((int64_t)1 << 40)) return LBM_ERR_INVALID_ARG;
         s->react = P.mode == LBM_MODE_REACT;
         s->N = (int64_t)P.nx * P.ny * P.nz;
-        if (s->N > (int64_t)INT32_MAX) return LBM_ERR_INVALID_ARG;  // voxel index in 32 bits
+        // one lattice below 4 GiB: byte offsets in 32 bits
+        if ((s->N + 63) / 64 * 64 * kQ * 4 >= ((int64_t)1 << 32)) return LBM_ERR_INVALID_ARG;
         s->nblk = (int)((s->N + kBlock - 1) / kBlock);
         s->d0_lat = (P.params.tau_ref - 0.5) * P.d0 / (3.0 * P.d_ref);
         s->ab_in = 2.0 * (P.params.c_in - P.sh0);
@@ -365,7 +403,7 @@ int lbm19_create(const lbm_grid *g, const uint8_t *phase, const lbm_params *p, l
                 }
         // workspace: two lattices, mask, omega, k n, C snapshot, partials, result
         size_t o = 0;
-        const size_t fb = align256(sizeof(float) * kQ * (size_t)s->N), nb4 = align256(4 * (size_t)s->N);
+        const size_t fb = align256(sizeof(float) * kQ * 64 * (size_t)((s->N + 63) / 64)), nb4 = align256(4 * (size_t)s->N);
         s->off_f[0] = o;
         o += fb;
         s->off_f[1] = o;
@@ -565,8 +603,8 @@ int lbm19_concentration(const lbm19_solver *s, float *c_dev) {
     if (!s->ws) return LBM_ERR_UNBOUND;
     const int nb = (int)((s->N + kBlock - 1) / kBlock);
     k_d3q19_conc<<<nb, kBlock, 0, s->st>>>(s->at<float>(s->off_f[s->cur]), s->at<uint32_t>(s->off_mask),
-                                           s->react ? s->at<float>(s->off_kn) : nullptr, c_dev, s->N, s->P.nx,
-                                           s->P.sh0, s->P.slope);
+                                           s->react ? s->at<float>(s->off_kn) : nullptr, c_dev, s->N,
+                                           s->P.nx, s->P.sh0, s->P.slope);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s->st);
     return e == hipSuccess ? LBM_OK : cl::record_error(e, "lbm19_concentration");
