@@ -75,10 +75,23 @@ def equilibrium(prob: L.Problem, C) -> np.ndarray:
     return np.where(prob.active[None], f, 0.0)
 
 
+def dirichlet_faces(prob: L.Problem):
+    """(inlet, outlet): which x faces hold a Dirichlet value.  Effective
+    properties: both (Eq. 19); reactive problem: the inlet only (Eq. 20b); the
+    coupled potential problem: the membrane face x = L only."""
+    faces = getattr(prob, "faces", None)
+    if faces is not None:
+        return faces
+    return (True, prob.params.mode != L.MODE_REACT)
+
+
 def collide(prob: L.Problem, f: np.ndarray) -> np.ndarray:
-    """Post-collision f* = f - (f - a C)/tau + a S with S = -k n C (Eq. 21)."""
+    """Post-collision f* = f - (f - a C)/tau + a S with S = -k n C (Eq. 21), plus
+    a given per-voxel source where the problem carries one."""
     C = f.sum(axis=0)
     S = -prob.kn * C
+    if getattr(prob, "src", None) is not None:
+        S = S + prob.src
     w = W19[:, None, None, None]
     fs = f + prob.omega[None] * (w * C[None] - f) + w * S[None]
     return np.where(prob.active[None], fs, 0.0)
@@ -99,7 +112,8 @@ def pull_map(prob: L.Problem):
     idx = np.arange(nz * ny * nx).reshape(act.shape)
     kind = np.empty((Q,) + act.shape, np.int8)
     src = np.zeros((Q,) + act.shape, np.int64)
-    react = p.mode == L.MODE_REACT
+    d_in, d_out = dirichlet_faces(prob)
+    del p
     for i in range(Q):
         cx, cy, cz = C19[i]
         # voxel (z - cz, y - cy) of the same x plane, and whether it is simulated
@@ -113,9 +127,9 @@ def pull_map(prob: L.Problem):
         else:
             src[i][..., :-1], a[..., :-1] = s_idx[..., 1:], s_act[..., 1:]
         k = np.where(a, PULL, BOUNCE).astype(np.int8)
-        if cx == 1:
+        if cx == 1 and d_in:
             k[..., 0] = np.where(s_act[..., 0], ANTI, BOUNCE)
-        if cx == -1 and not react:
+        if cx == -1 and d_out:
             k[..., -1] = np.where(s_act[..., -1], ANTI, BOUNCE)
         kind[i] = k
     return kind, src
@@ -168,6 +182,7 @@ def fluxes(prob: L.Problem, f: np.ndarray) -> Fluxes:
     act = prob.active
     nz, ny, nx = act.shape
     A = ny * nz
+    d_in, d_out = dirichlet_faces(prob)
     fs = collide(prob, f)
     face = np.zeros(max(nx - 1, 0))
     j_in = j_out = 0.0
@@ -178,15 +193,19 @@ def fluxes(prob: L.Problem, f: np.ndarray) -> Fluxes:
         if cx == 1:
             face += (fs[i][..., :-1] * dest[..., 1:]).sum(axis=(0, 1))
             # leaving through the outlet face (x = nx - 1), where the link is open
-            if p.mode != L.MODE_REACT:
+            if d_out:
                 open_ = dest[..., -1] & act[..., -1]
                 j_out += np.sum((2.0 * fs[i][..., -1] - 2.0 * W19[i] * p.c_out) * open_)
         elif cx == -1:
             face -= (fs[i][..., 1:] * dest[..., :-1]).sum(axis=(0, 1))
-            open_ = dest[..., 0] & act[..., 0]
-            j_in += np.sum((2.0 * W19[i] * p.c_in - 2.0 * fs[i][..., 0]) * open_)
+            if d_in:
+                open_ = dest[..., 0] & act[..., 0]
+                j_in += np.sum((2.0 * W19[i] * p.c_in - 2.0 * fs[i][..., 0]) * open_)
     C = concentration(f)
+    # the net sink: k n C, less any given source
     rate = float(np.sum(prob.kn * C))
+    if getattr(prob, "src", None) is not None:
+        rate -= float(np.sum(prob.src * act))
     nf = nx - 1
     return Fluxes(j_in=j_in / A, j_out=j_out / A,
                   j_vol=(face.sum() / nf / A) if nf > 0 else j_in / A,
@@ -210,7 +229,7 @@ class Steady:
 
 def _finish(prob, f, steps=0) -> Steady:
     fl = fluxes(prob, f)
-    if prob.params.mode == L.MODE_REACT:
+    if prob.params.mode == L.MODE_REACT or getattr(prob, "faces", None) is not None:
         return Steady(f, fl, None, fl.rate, steps)
     return Steady(f, fl, deff_from_flux(prob, fl.j_vol) if prob.percolates else 0.0, None, steps)
 
@@ -263,6 +282,10 @@ def assemble(prob: L.Problem):
             cols.append(jj * N + vv)
             vals.append(ss * (om[vv] - kn[vv]) * W19[kk])
         b[i] = np.where(a_vox & (kd == ANTI), 2.0 * W19[i] * boundary_value(prob, i), 0.0)
+        if getattr(prob, "src", None) is not None:
+            # the source enters f*_k(v) as a_k S(v), carried with the link's sign
+            sv = prob.src.ravel()
+            b[i][vox[sel]] += ss * W19[kk] * sv[vv]
     A = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(Q * N, Q * N))
     return A, b.ravel()
 
