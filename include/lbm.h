@@ -381,6 +381,75 @@ int lbm19_get_populations(const lbm19_solver *s, double *f_dev);
 int lbm19_concentration(const lbm19_solver *s, float *c_dev);
 void lbm19_destroy(lbm19_solver *s);
 
+/* ---- Coupled oxygen / proton-potential problem on D3Q19 (Sections 3.2-3.4,
+ * Eqs. 15-18b with the Tafel rate of Eq. 17b)
+ *
+ * Two D3Q19 solvers on one structure, coupled by Picard iteration on the device:
+ *   O2: the reactive problem of lbm19_create (p->mode must be LBM_MODE_REACT;
+ *       reservoir plane, inlet C_in, zero-gradient outlet) whose sink sits on the
+ *       reaction sites only, with k n = k_ref n exp(beta (phi - phi_ref));
+ *   potential: D_phi lap(phi) = q on the ionomer joined to the membrane face
+ *       x = L through ionomer, phi = phi_m there (anti-bounce-back), zero proton
+ *       flux at x = 0 and every other boundary, D_phi from tau_phi, with the
+ *       proton source q = gamma n (C / C_in) exp(beta (phi - phi_ref)) (Eq. 18b).
+ * Reaction sites: ionomer voxels with n > 0 Pt face neighbours that both
+ * problems reach.  From phi = phi_m: solve O2, then the potential, then move phi
+ * by theta of the change; stop when the change is below tol_phi (volts) on every
+ * voxel (LBM_OK) or after max_iter iterations (LBM_NOT_CONVERGED).  Each inner
+ * solve is lbm19_run_to_steady with p's stop parameters, continuing from the
+ * previous iterate.  The paper itself presets a uniform phi (Section 3.5.2); the
+ * boundary values above are this library's reading, documented with the oracle.
+ *
+ * lbm_coupling_default: k_ref 1e-2, beta 21.3 1/V (alpha F / R T at alpha 0.61,
+ *   333 K), gamma 1e-3 V, phi_m = phi_ref = 0.6 V, tau_phi 1, theta 0.5,
+ *   tol_phi 1e-6 V, max_iter 200.
+ * lbm19_coupled_create: LBM_ERR_INVALID_ARG for NULL pointers, a struct_size
+ *   mismatch, k_ref <= 0, beta < 0, gamma < 0, tau_phi <= 1/2, theta outside
+ *   (0, 1], tol_phi <= 0, max_iter < 1, a mode other than LBM_MODE_REACT or
+ *   c_in <= 0; LBM_ERR_UNSTABLE when 6 k_ref exp(beta max(0, phi_m - phi_ref))
+ *   >= 1; otherwise the errors of lbm19_create.
+ * lbm19_coupled_workspace_bytes / lbm19_coupled_bind: as lbm19_*; the workspace
+ *   holds both solvers and five FP32 fields of the structure grid.
+ * lbm19_coupled_run: the iteration above; *info (may be NULL) receives the
+ *   iteration count, the last change of phi, the lowest phi, the O2 consumption
+ *   and the proton source per unit area, the membrane current per unit area and
+ *   the step counts of the two solvers.
+ * lbm19_coupled_fields: c_dev (O2 grid, reservoir plane included) and phi_dev
+ *   (structure grid; phi_m off the potential's voxels), device FP32; either may
+ *   be NULL. */
+typedef struct {
+    uint32_t struct_size; /* = sizeof(lbm_coupling)                              */
+    double k_ref;         /* O2 rate per Pt face at phi_ref, lattice units       */
+    double beta;          /* alpha F / (R T), 1/V                                */
+    double gamma;         /* proton source per Pt face at C_in and phi_ref, V    */
+    double phi_m;         /* potential at the membrane face x = L, V             */
+    double phi_ref;       /* potential at which k_ref and gamma hold, V          */
+    double tau_phi;       /* relaxation time of the potential lattice            */
+    double theta;         /* Picard under-relaxation, (0, 1]                     */
+    double tol_phi;       /* stop when phi changes by less than this, V          */
+    int32_t max_iter;
+} lbm_coupling;
+
+typedef struct {
+    int32_t iterations, status;
+    double dphi;          /* last change of phi, V                               */
+    double phi_min;       /* lowest phi, V                                       */
+    double rate;          /* O2 consumption per unit area (sum k n C / A)        */
+    double source;        /* proton source per unit area (sum q / A)             */
+    double proton_in;     /* current in through the membrane face, per area      */
+    int64_t o2_steps, phi_steps;
+} lbm_coupled_info;
+
+typedef struct lbm19_coupled lbm19_coupled;
+int lbm_coupling_default(lbm_coupling *c);
+int lbm19_coupled_create(const lbm_grid *g, const uint8_t *phase_host, const lbm_params *p, const lbm_coupling *cp,
+                         lbm19_coupled **out);
+int lbm19_coupled_workspace_bytes(const lbm19_coupled *c, size_t *bytes);
+int lbm19_coupled_bind(lbm19_coupled *c, void *workspace_dev, size_t bytes, void *hip_stream);
+int lbm19_coupled_run(lbm19_coupled *c, lbm_coupled_info *info);
+int lbm19_coupled_fields(const lbm19_coupled *c, float *c_dev, float *phi_dev);
+void lbm19_coupled_destroy(lbm19_coupled *c);
+
 #ifdef __cplusplus
 }
 #endif

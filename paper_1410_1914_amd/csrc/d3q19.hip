@@ -48,6 +48,7 @@ struct D19Args {
     const uint32_t *__restrict__ mask;
     const float *__restrict__ omega;
     const float *__restrict__ kn;  // k n per voxel (reactive problem only)
+    const float *__restrict__ src; // a given source per voxel, or null
     float *__restrict__ csnap;     // C at the previous measured step
     double *__restrict__ part;     // per-block partial sums (measured steps)
     int64_t N;
@@ -152,7 +153,8 @@ __global__ __launch_bounds__(kBlock) void k_d3q19(D19Args a) {
         const double C = csh + sum;
         const double om = (double)a.omega[v];
         const double knv = REACT ? (double)a.kn[v] : 0.0;
-        const double b = (om - knv) * C - om * csh;
+        const double sv = a.src ? (double)a.src[v] : 0.0;
+        const double b = (om - knv) * C - om * csh + sv;
         const double keep = 1.0 - om;
 #pragma unroll
         for (int i = 0; i < kQ; ++i) st(a.fout, fbyte(i, vv), (float)(keep * g[i] + weight(i) * b));
@@ -168,7 +170,7 @@ __global__ __launch_bounds__(kBlock) void k_d3q19(D19Args a) {
                     acc[1] += 2.0 * weight(i) * a.c_out - 2.0 * f;
             }
             if (act) {
-                acc[3] = knv * C;
+                acc[3] = knv * C - sv;  // the net sink
                 acc[4] = C;
                 acc[5] = fabs(C - (double)a.csnap[v]);
                 a.csnap[v] = (float)C;
@@ -250,9 +252,10 @@ __global__ __launch_bounds__(kBlock) void k_d3q19_unshift(const float *__restric
         out[(int64_t)i * N + v] = act ? (double)f[fidx(i, v)] + weight(i) * csh : 0.0;
 }
 
-// C of the state: the stored populations sum to (1 - k n) C after the collision.
+// C of the state: the stored populations sum to (1 - k n) C + S after the collision.
 __global__ __launch_bounds__(kBlock) void k_d3q19_conc(const float *__restrict__ f, const uint32_t *__restrict__ mask,
-                                                       const float *__restrict__ kn, float *__restrict__ c, int64_t N,
+                                                       const float *__restrict__ kn, const float *__restrict__ src,
+                                                       float *__restrict__ c, int64_t N,
                                                        int nx, double sh0, double slope) {
     const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (v >= N) return;
@@ -263,6 +266,7 @@ __global__ __launch_bounds__(kBlock) void k_d3q19_conc(const float *__restrict__
     double s = sh0 - slope * (double)(v % nx);
 #pragma unroll
     for (int i = 0; i < kQ; ++i) s += (double)f[fidx(i, v)];
+    if (src) s -= (double)src[v];
     c[v] = (float)(kn ? s / (1.0 - (double)kn[v]) : s);
 }
 
@@ -275,6 +279,8 @@ int wrapi(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 struct lbm19_solver {
     cl::Prepared P;
     bool react = false;
+    bool potential = false;        // the coupled potential problem (Dirichlet at x = L only)
+    const float *src = nullptr;    // a given per-voxel source (device), or null
     int64_t N = 0;
     int nblk = 0;
     double d0_lat = 0, ab_in = 0, ab_out = 0;
@@ -301,6 +307,7 @@ struct lbm19_solver {
         a.mask = at<uint32_t>(off_mask);
         a.omega = at<float>(off_om);
         a.kn = react ? at<float>(off_kn) : nullptr;
+        a.src = src;
         a.csnap = at<float>(off_cs);
         a.part = measure ? at<double>(off_part) : nullptr;
         a.N = N;
@@ -360,9 +367,12 @@ struct lbm19_solver {
     }
 };
 
-extern "C" {
-
-int lbm19_create(const lbm_grid *g, const uint8_t *phase, const lbm_params *p, lbm19_solver **out) {
+// The solver behind lbm19_create; `potential` builds the coupled potential
+// problem instead: transport on ionomer joined to the membrane face x = L,
+// Dirichlet there, zero flux at x = 0 (the caller passes a proton-mode problem
+// with c_in = c_out = the membrane potential).
+static int create19(const lbm_grid *g, const uint8_t *phase, const lbm_params *p, bool potential,
+                    lbm19_solver **out) {
     try {
         if (!g || !phase || !p || !out) return LBM_ERR_INVALID_ARG;
         *out = nullptr;
@@ -372,6 +382,42 @@ int lbm19_create(const lbm_grid *g, const uint8_t *phase, const lbm_params *p, l
         cl::Prepared &P = s->P;
         if ((int64_t)kQ * P.nx * P.ny * P.nz > ((int64_t)1 << 40)) return LBM_ERR_INVALID_ARG;
         s->react = P.mode == LBM_MODE_REACT;
+        s->potential = potential;
+        if (potential) {
+            // ionomer joined to the membrane face through ionomer (breadth-first, periodic y, z)
+            const int nx = P.nx, ny = P.ny, nz = P.nz;
+            const int64_t Nv = (int64_t)nx * ny * nz;
+            std::vector<uint8_t> reach(Nv, 0);
+            std::vector<int64_t> queue;
+            for (int z = 0; z < nz; ++z)
+                for (int y = 0; y < ny; ++y) {
+                    const int64_t v = ((int64_t)z * ny + y) * nx + nx - 1;
+                    if (P.phase[v] == LBM_IONOMER) {
+                        reach[v] = 1;
+                        queue.push_back(v);
+                    }
+                }
+            for (size_t h = 0; h < queue.size(); ++h) {
+                const int64_t v = queue[h];
+                const int x = (int)(v % nx), y = (int)((v / nx) % ny), z = (int)(v / ((int64_t)nx * ny));
+                const int64_t nb[6] = {x > 0 ? v - 1 : -1, x + 1 < nx ? v + 1 : -1,
+                                       ((int64_t)z * ny + wrapi(y - 1, ny)) * nx + x,
+                                       ((int64_t)z * ny + wrapi(y + 1, ny)) * nx + x,
+                                       ((int64_t)wrapi(z - 1, nz) * ny + y) * nx + x,
+                                       ((int64_t)wrapi(z + 1, nz) * ny + y) * nx + x};
+                for (int64_t u : nb)
+                    if (u >= 0 && !reach[u] && P.phase[u] == LBM_IONOMER) {
+                        reach[u] = 1;
+                        queue.push_back(u);
+                    }
+            }
+            P.percolates = false;
+            for (int64_t v = 0; v < Nv; ++v) {
+                if (!reach[v]) P.omega_dense[v] = 0.f;
+                else P.percolates = true;
+                P.active[v] = reach[v];
+            }
+        }
         s->N = (int64_t)P.nx * P.ny * P.nz;
         // one lattice below 4 GiB: byte offsets in 32 bits
         if ((s->N + 63) / 64 * 64 * kQ * 4 >= ((int64_t)1 << 32)) return LBM_ERR_INVALID_ARG;
@@ -393,7 +439,7 @@ int lbm19_create(const lbm_grid *g, const uint8_t *phase, const lbm_params *p, l
                         const int64_t plane = ((int64_t)sz * ny + sy) * nx;
                         if (sx < 0 || sx >= nx || !P.active[plane + sx]) m |= 1u << i;
                         // a face link is open when the boundary-plane voxel it passes is simulated
-                        if (CX[i] == 1 && x == 0 && P.active[plane]) m |= 1u << (19 + FACE_SLOT[i]);
+                        if (CX[i] == 1 && x == 0 && !potential && P.active[plane]) m |= 1u << (19 + FACE_SLOT[i]);
                         if (CX[i] == -1 && x == nx - 1 && !s->react && P.active[plane + nx - 1])
                             m |= 1u << (24 + FACE_SLOT[i]);
                     }
@@ -426,6 +472,105 @@ int lbm19_create(const lbm_grid *g, const uint8_t *phase, const lbm_params *p, l
     } catch (...) {
         return LBM_ERR_INVALID_ARG;
     }
+}
+
+
+namespace {
+
+// ---- coupled oxygen / proton-potential problem (Eqs. 15-18b, Tafel Eq. 17b)
+
+// O2 sink of each reaction site from the potential: k n = k_ref n exp(beta (phi - phi_ref))
+__global__ __launch_bounds__(kBlock) void k_cpl_rate(float *__restrict__ kn_o2, const float *__restrict__ n_site,
+                                                     const float *__restrict__ phi, int64_t Ns, int nx, int nx_o,
+                                                     int off, double k_ref, double beta, double phi_ref) {
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v >= Ns) return;
+    const int64_t row = v / nx, x = v - row * nx;
+    const double n = (double)n_site[v];
+    kn_o2[row * nx_o + x + off] = n > 0.0 ? (float)(k_ref * n * exp(beta * ((double)phi[v] - phi_ref))) : 0.f;
+}
+
+// proton source of each site (Eq. 18b) from C and the potential, as the LBM source
+// S = -gamma n (C / C_in) exp(beta (phi - phi_ref))
+__global__ __launch_bounds__(kBlock) void k_cpl_source(float *__restrict__ src, const float *__restrict__ n_site,
+                                                       const float *__restrict__ phi, const float *__restrict__ c_o2,
+                                                       int64_t Ns, int nx, int nx_o, int off, double gamma,
+                                                       double beta, double phi_ref, double c_in) {
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v >= Ns) return;
+    const int64_t row = v / nx, x = v - row * nx;
+    const double n = (double)n_site[v];
+    const double C = (double)c_o2[row * nx_o + x + off];
+    src[v] = n > 0.0 ? (float)(-gamma * n * (C / c_in) * exp(beta * ((double)phi[v] - phi_ref))) : 0.f;
+}
+
+// phi <- phi + theta (phi_solved - phi) on the potential's voxels (phi_m elsewhere);
+// per-block max of |phi_solved - phi| and min of the new phi
+__global__ __launch_bounds__(kBlock) void k_cpl_relax(float *__restrict__ phi, const float *__restrict__ solved,
+                                                      const uint32_t *__restrict__ mask, int64_t Ns, double theta,
+                                                      double phi_m, float *__restrict__ part) {
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double d = 0.0, lo = phi_m;
+    if (v < Ns) {
+        const double old = (double)phi[v];
+        const double nw = (mask[v] & kActive) ? (double)solved[v] : phi_m;
+        d = fabs(nw - old);
+        const double upd = old + theta * (nw - old);
+        phi[v] = (float)upd;
+        lo = upd;
+    }
+    d = wave_max(d);
+    for (int o = 32; o > 0; o >>= 1) lo = fmin(lo, __shfl_xor(lo, o));
+    __shared__ double red[2][kBlock / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][wv] = d;
+        red[1][wv] = lo;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = red[0][0], b = red[1][0];
+        for (int w = 1; w < kBlock / 64; ++w) {
+            a = fmax(a, red[0][w]);
+            b = fmin(b, red[1][w]);
+        }
+        part[2 * (int64_t)blockIdx.x] = (float)a;
+        part[2 * (int64_t)blockIdx.x + 1] = (float)b;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cpl_fill(float *__restrict__ a, int64_t n, float val) {
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v < n) a[v] = val;
+}
+
+}  // namespace
+
+struct lbm19_coupled {
+    lbm19_solver *o2 = nullptr, *phi = nullptr;
+    lbm_coupling cp{};
+    double c_in = 1.0;
+    int nx = 0, ny = 0, nz = 0, nx_o = 0, off = 0;
+    int64_t Ns = 0;
+    int nb = 0;
+    std::vector<float> n_site;
+    size_t ws_o2 = 0, ws_phi = 0, off_phi_ws = 0, off_n = 0, off_phi = 0, off_new = 0, off_c = 0, off_src = 0,
+           off_part = 0, need = 0;
+    char *ws = nullptr;
+    hipStream_t st = nullptr;
+    lbm_coupled_info last{};
+    template <class T>
+    T *at(size_t o) const { return reinterpret_cast<T *>(ws + o); }
+    ~lbm19_coupled() {
+        delete o2;
+        delete phi;
+    }
+};
+
+extern "C" {
+
+int lbm19_create(const lbm_grid *g, const uint8_t *phase, const lbm_params *p, lbm19_solver **out) {
+    return create19(g, phase, p, false, out);
 }
 
 int lbm19_get_info(const lbm19_solver *s, lbm_info *info) {
@@ -521,10 +666,11 @@ int lbm19_run_to_steady(lbm19_solver *s, lbm_run_info *info) {
     const int64_t K = std::max<int64_t>(2, p.check_every);
     // Stop when, over windows of K steps, (i) the C field moves by less than
     // tol_change per step relative to max C, (ii) the output (mean interior flux,
-    // or the total sink when reacting) is within tol_flux of its limit, estimated
+    // the total sink when reacting, the membrane current of the potential
+    // problem) is within tol_flux of its limit, estimated
     // from the ratio rho of successive window changes as |d| max(1, rho/(1-rho)),
-    // on two checks in a row, and (iii) the mass balance J_in - J_out - R closes
-    // to tol_balance of J_in.
+    // on two checks in a row, and (iii) the balance J_in - J_out - R (R the net
+    // sink) closes to tol_balance of the largest of the three.
     double q[3] = {0, 0, 0};
     int nq = 0, good = 0, st = LBM_NOT_CONVERGED;
     s->last.checks = 0;
@@ -537,7 +683,7 @@ int lbm19_run_to_steady(lbm19_solver *s, lbm_run_info *info) {
             break;
         }
         ++s->last.checks;
-        const double qk = s->react ? s->last.rate : s->last.j_vol;
+        const double qk = s->react ? s->last.rate : (s->potential ? s->last.j_out : s->last.j_vol);
         q[0] = q[1];
         q[1] = q[2];
         q[2] = qk;
@@ -549,9 +695,8 @@ int lbm19_run_to_steady(lbm19_solver *s, lbm_run_info *info) {
             if (rho < 1.0) est = std::fabs(d1) / std::fabs(qk) * std::max(1.0, rho > 0 ? rho / (1.0 - rho) : 0.0);
         }
         s->last.est_error = est;
-        const double bal = s->last.j_in != 0.0
-                               ? std::fabs(s->last.j_in - s->last.j_out - s->last.rate) / std::fabs(s->last.j_in)
-                               : INFINITY;
+        const double den = std::max({std::fabs(s->last.j_in), std::fabs(s->last.j_out), std::fabs(s->last.rate)});
+        const double bal = den > 0.0 ? std::fabs(s->last.j_in - s->last.j_out - s->last.rate) / den : INFINITY;
         const bool ok = s->last.residual < p.tol_change && est < p.tol_flux && bal < p.tol_balance;
         good = ok ? good + 1 : 0;
         if (good >= 2) {
@@ -603,7 +748,7 @@ int lbm19_concentration(const lbm19_solver *s, float *c_dev) {
     if (!s->ws) return LBM_ERR_UNBOUND;
     const int nb = (int)((s->N + kBlock - 1) / kBlock);
     k_d3q19_conc<<<nb, kBlock, 0, s->st>>>(s->at<float>(s->off_f[s->cur]), s->at<uint32_t>(s->off_mask),
-                                           s->react ? s->at<float>(s->off_kn) : nullptr, c_dev, s->N,
+                                           s->react ? s->at<float>(s->off_kn) : nullptr, s->src, c_dev, s->N,
                                            s->P.nx, s->P.sh0, s->P.slope);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s->st);
@@ -611,5 +756,215 @@ int lbm19_concentration(const lbm19_solver *s, float *c_dev) {
 }
 
 void lbm19_destroy(lbm19_solver *s) { delete s; }
+
+
+int lbm_coupling_default(lbm_coupling *c) {
+    if (!c) return LBM_ERR_INVALID_ARG;
+    std::memset(c, 0, sizeof(*c));
+    c->struct_size = sizeof(lbm_coupling);
+    c->k_ref = 1e-2;
+    c->beta = 21.3;
+    c->gamma = 1e-3;
+    c->phi_m = 0.6;
+    c->phi_ref = 0.6;
+    c->tau_phi = 1.0;
+    c->theta = 0.5;
+    c->tol_phi = 1e-6;
+    c->max_iter = 200;
+    return LBM_OK;
+}
+
+int lbm19_coupled_create(const lbm_grid *g, const uint8_t *phase, const lbm_params *p, const lbm_coupling *cp,
+                         lbm19_coupled **out) {
+    try {
+        if (!g || !phase || !p || !cp || !out) return LBM_ERR_INVALID_ARG;
+        *out = nullptr;
+        if (cp->struct_size != sizeof(lbm_coupling) || !(cp->k_ref > 0.0) || !(cp->beta >= 0.0) ||
+            !(cp->gamma >= 0.0) || !(cp->tau_phi > 0.5) || !(cp->theta > 0.0 && cp->theta <= 1.0) ||
+            !(cp->tol_phi > 0.0) || cp->max_iter < 1 || p->mode != LBM_MODE_REACT || !(p->c_in > 0.0))
+            return LBM_ERR_INVALID_ARG;
+        // the largest site rate, at the membrane potential, must keep k n below 1
+        if (6.0 * cp->k_ref * std::exp(cp->beta * std::max(0.0, cp->phi_m - cp->phi_ref)) >= 1.0)
+            return LBM_ERR_UNSTABLE;
+        auto c = std::make_unique<lbm19_coupled>();
+        c->cp = *cp;
+        c->c_in = p->c_in;
+        lbm_params po = *p;
+        po.k_lat = cp->k_ref;
+        po.catalyst_phases = 1u << LBM_PT;
+        po.reactive_fluids = 1u << LBM_IONOMER;
+        int st = create19(g, phase, &po, false, &c->o2);
+        if (st != LBM_OK) return st;
+        lbm_params pp = *p;
+        pp.mode = LBM_MODE_PROTON;
+        pp.c_in = pp.c_out = cp->phi_m;
+        pp.tau_ref = cp->tau_phi;
+        pp.knudsen = 0;
+        pp.k_lat = 0.0;
+        st = create19(g, phase, &pp, true, &c->phi);
+        if (st != LBM_OK) return st;
+        const cl::Prepared &O = c->o2->P, &F = c->phi->P;
+        c->nx = F.nx;
+        c->ny = F.ny;
+        c->nz = F.nz;
+        c->nx_o = O.nx;
+        c->off = O.nx - F.nx;
+        c->Ns = (int64_t)F.nx * F.ny * F.nz;
+        c->nb = (int)((c->Ns + kBlock - 1) / kBlock);
+        // sites: ionomer with Pt face neighbours, reached by both problems
+        c->n_site.assign(c->Ns, 0.f);
+        for (int64_t r = 0; r < (int64_t)F.ny * F.nz; ++r)
+            for (int x = 0; x < F.nx; ++x) {
+                const int64_t v = r * F.nx + x, vo = r * O.nx + x + c->off;
+                if (F.active[v] && O.active[vo] && O.phase[vo] == LBM_IONOMER && O.n_cat[vo] > 0)
+                    c->n_site[v] = (float)O.n_cat[vo];
+            }
+        lbm19_workspace_bytes(c->o2, &c->ws_o2);
+        lbm19_workspace_bytes(c->phi, &c->ws_phi);
+        size_t o = align256(c->ws_o2);
+        c->off_phi_ws = o;
+        o += align256(c->ws_phi);
+        const size_t s4 = align256(4 * (size_t)c->Ns);
+        c->off_n = o;
+        o += s4;
+        c->off_phi = o;
+        o += s4;
+        c->off_new = o;
+        o += s4;
+        c->off_src = o;
+        o += s4;
+        c->off_c = o;
+        o += align256(4 * (size_t)O.nx * O.ny * O.nz);
+        c->off_part = o;
+        o += align256(8 * (size_t)c->nb);
+        c->need = o;
+        *out = c.release();
+        return LBM_OK;
+    } catch (...) {
+        return LBM_ERR_INVALID_ARG;
+    }
+}
+
+int lbm19_coupled_workspace_bytes(const lbm19_coupled *c, size_t *bytes) {
+    if (!c || !bytes) return LBM_ERR_INVALID_ARG;
+    *bytes = c->need;
+    return LBM_OK;
+}
+
+int lbm19_coupled_bind(lbm19_coupled *c, void *ws, size_t bytes, void *stream) {
+    if (!c || !ws || (reinterpret_cast<uintptr_t>(ws) & 255u) || bytes < c->need) return LBM_ERR_WORKSPACE;
+    c->ws = static_cast<char *>(ws);
+    c->st = static_cast<hipStream_t>(stream);
+    int st = lbm19_bind(c->o2, c->ws, c->ws_o2, stream);
+    if (st == LBM_OK) st = lbm19_bind(c->phi, c->ws + c->off_phi_ws, c->ws_phi, stream);
+    if (st != LBM_OK) {
+        c->ws = nullptr;
+        return st;
+    }
+    c->phi->src = c->at<float>(c->off_src);
+    hipError_t e = hipMemcpyAsync(c->at<float>(c->off_n), c->n_site.data(), 4 * (size_t)c->Ns,
+                                  hipMemcpyHostToDevice, c->st);
+    if (e == hipSuccess) {
+        k_cpl_fill<<<c->nb, kBlock, 0, c->st>>>(c->at<float>(c->off_phi), c->Ns, (float)c->cp.phi_m);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        k_cpl_fill<<<c->nb, kBlock, 0, c->st>>>(c->at<float>(c->off_src), c->Ns, 0.f);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    if (e != hipSuccess) {
+        c->ws = nullptr;
+        return cl::record_error(e, "lbm19_coupled_bind");
+    }
+    // the potential starts from the membrane value everywhere
+    return lbm19_set_initial_concentration(c->phi, c->at<float>(c->off_phi));
+}
+
+int lbm19_coupled_run(lbm19_coupled *c, lbm_coupled_info *info) {
+    if (!c) return LBM_ERR_INVALID_ARG;
+    if (!c->ws) return LBM_ERR_UNBOUND;
+    const lbm_coupling &cp = c->cp;
+    lbm_coupled_info &I = c->last;
+    std::memset(&I, 0, sizeof(I));
+    I.status = LBM_NOT_CONVERGED;
+    std::vector<float> part(2 * (size_t)c->nb);
+    lbm_run_info r{};
+    int inner = LBM_OK;
+    for (int it = 1; it <= cp.max_iter; ++it) {
+        // O2 with the Tafel rate of the current potential
+        k_cpl_rate<<<c->nb, kBlock, 0, c->st>>>(c->o2->at<float>(c->o2->off_kn), c->at<float>(c->off_n),
+                                                c->at<float>(c->off_phi), c->Ns, c->nx, c->nx_o, c->off, cp.k_ref,
+                                                cp.beta, cp.phi_ref);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return cl::record_error(e, "lbm19_coupled_run");
+        int st = lbm19_run_to_steady(c->o2, &r);
+        if (st != LBM_OK) {  // an error, or an inner solve out of steps
+            inner = st;
+            break;
+        }
+        I.o2_steps = r.steps;
+        I.rate = r.rate;
+        st = lbm19_concentration(c->o2, c->at<float>(c->off_c));
+        if (st < 0) return I.status = st;
+        // the potential with the proton source of that O2 field
+        k_cpl_source<<<c->nb, kBlock, 0, c->st>>>(c->at<float>(c->off_src), c->at<float>(c->off_n),
+                                                  c->at<float>(c->off_phi), c->at<float>(c->off_c), c->Ns, c->nx,
+                                                  c->nx_o, c->off, cp.gamma, cp.beta, cp.phi_ref, c->c_in);
+        e = hipGetLastError();
+        if (e != hipSuccess) return cl::record_error(e, "lbm19_coupled_run");
+        st = lbm19_run_to_steady(c->phi, &r);
+        if (st != LBM_OK) {
+            inner = st;
+            break;
+        }
+        I.phi_steps = r.steps;
+        I.proton_in = -r.j_out;
+        I.source = r.rate;
+        st = lbm19_concentration(c->phi, c->at<float>(c->off_new));
+        if (st < 0) return I.status = st;
+        k_cpl_relax<<<c->nb, kBlock, 0, c->st>>>(c->at<float>(c->off_phi), c->at<float>(c->off_new),
+                                                 c->phi->at<uint32_t>(c->phi->off_mask), c->Ns, cp.theta, cp.phi_m,
+                                                 c->at<float>(c->off_part));
+        e = hipGetLastError();
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(part.data(), c->at<float>(c->off_part), 4 * part.size(), hipMemcpyDeviceToHost, c->st);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+        if (e != hipSuccess) return cl::record_error(e, "lbm19_coupled_run");
+        double d = 0.0, lo = cp.phi_m;
+        for (int b = 0; b < c->nb; ++b) {
+            d = std::max(d, (double)part[2 * (size_t)b]);
+            lo = std::min(lo, (double)part[2 * (size_t)b + 1]);
+        }
+        I.iterations = it;
+        I.dphi = d;
+        I.status = LBM_NOT_CONVERGED;
+        I.phi_min = lo;
+        if (d < cp.tol_phi) {
+            I.status = LBM_OK;
+            break;
+        }
+    }
+    if (inner != LBM_OK) I.status = inner < 0 ? inner : LBM_NOT_CONVERGED;
+    if (info) *info = I;
+    return I.status;
+}
+
+int lbm19_coupled_fields(const lbm19_coupled *c, float *c_dev, float *phi_dev) {
+    if (!c) return LBM_ERR_INVALID_ARG;
+    if (!c->ws) return LBM_ERR_UNBOUND;
+    hipError_t e = hipSuccess;
+    if (c_dev) {
+        const int st = lbm19_concentration(c->o2, c_dev);
+        if (st != LBM_OK) return st;
+    }
+    if (phi_dev) {
+        e = hipMemcpyAsync(phi_dev, c->at<float>(c->off_phi), 4 * (size_t)c->Ns, hipMemcpyDeviceToDevice, c->st);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    }
+    return e == hipSuccess ? LBM_OK : cl::record_error(e, "lbm19_coupled_fields");
+}
+
+void lbm19_coupled_destroy(lbm19_coupled *c) { delete c; }
 
 }  // extern "C"

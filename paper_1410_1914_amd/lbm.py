@@ -61,6 +61,21 @@ class lbm_info(ctypes.Structure):
                 ("percolates", c_int32), ("mode", c_int32)]
 
 
+class lbm_coupling(ctypes.Structure):
+    _fields_ = [("struct_size", c_uint32), ("k_ref", c_double), ("beta", c_double), ("gamma", c_double),
+                ("phi_m", c_double), ("phi_ref", c_double), ("tau_phi", c_double), ("theta", c_double),
+                ("tol_phi", c_double), ("max_iter", c_int32)]
+
+
+class lbm_coupled_info(ctypes.Structure):
+    _fields_ = [("iterations", c_int32), ("status", c_int32), ("dphi", c_double), ("phi_min", c_double),
+                ("rate", c_double), ("source", c_double), ("proton_in", c_double),
+                ("o2_steps", c_int64), ("phi_steps", c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class LbmError(RuntimeError):
     def __init__(self, fn, status):
         detail = lbm_last_error() if status == ERR_HIP else ""
@@ -132,6 +147,14 @@ SIGNATURES = {
     "lbm19_get_populations": ([_P, _P], c_int32),
     "lbm19_concentration": ([_P, _P], c_int32),
     "lbm19_destroy": ([_P], None),
+    "lbm_coupling_default": ([ctypes.POINTER(lbm_coupling)], c_int32),
+    "lbm19_coupled_create": ([ctypes.POINTER(lbm_grid), ctypes.POINTER(c_uint8), ctypes.POINTER(lbm_params),
+                              ctypes.POINTER(lbm_coupling), _PP], c_int32),
+    "lbm19_coupled_workspace_bytes": ([_P, ctypes.POINTER(ctypes.c_size_t)], c_int32),
+    "lbm19_coupled_bind": ([_P, _P, ctypes.c_size_t, _P], c_int32),
+    "lbm19_coupled_run": ([_P, ctypes.POINTER(lbm_coupled_info)], c_int32),
+    "lbm19_coupled_fields": ([_P, _P, _P], c_int32),
+    "lbm19_coupled_destroy": ([_P], None),
 }
 
 
@@ -699,6 +722,79 @@ class Solver19:
     def close(self):
         if getattr(self, "h", None):
             load().lbm19_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lbm_coupling_default(**overrides) -> lbm_coupling:
+    c = lbm_coupling()
+    _check("lbm_coupling_default", load().lbm_coupling_default(ctypes.byref(c)))
+    for k, v in overrides.items():
+        if not hasattr(c, k):
+            raise AttributeError(k)
+        setattr(c, k, v)
+    return c
+
+
+class Coupled19:
+    """Oxygen and proton potential coupled through the Tafel rate (Eqs. 15-18b)
+    on D3Q19: two solvers in one torch-owned workspace, iterated on the device."""
+
+    def __init__(self, phase: np.ndarray, params: lbm_params | None = None, coupling: lbm_coupling | None = None,
+                 voxel_m: float = 2e-9, device: str = "cuda", stream=None):
+        import torch
+
+        require_gpu()
+        lib = load()
+        self.params = params if params is not None else lbm_params_default(mode=MODE_REACT)
+        self.coupling = coupling if coupling is not None else lbm_coupling_default()
+        ph = np.ascontiguousarray(phase, dtype=np.uint8)
+        if ph.ndim != 3:
+            raise ValueError("phase map must be (nz, ny, nx)")
+        self.shape = ph.shape
+        nz, ny, nx = ph.shape
+        g = lbm_grid(nx, ny, nz, voxel_m)
+        self.h = ctypes.c_void_p()
+        _check("lbm19_coupled_create", lib.lbm19_coupled_create(
+            ctypes.byref(g), ph.ctypes.data_as(ctypes.POINTER(c_uint8)), ctypes.byref(self.params),
+            ctypes.byref(self.coupling), ctypes.byref(self.h)))
+        n = ctypes.c_size_t()
+        _check("lbm19_coupled_workspace_bytes", lib.lbm19_coupled_workspace_bytes(self.h, ctypes.byref(n)))
+        self.nbytes = n.value
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        self.ws = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
+        self.ws_ptr = (self.ws.data_ptr() + 255) // 256 * 256
+        torch.cuda.synchronize(self.device)
+        with torch.cuda.device(self.device):
+            _check("lbm19_coupled_bind", lib.lbm19_coupled_bind(self.h, self.ws_ptr, self.nbytes,
+                                                                self.stream.cuda_stream))
+
+    def run(self):
+        r = lbm_coupled_info()
+        st = _check("lbm19_coupled_run", load().lbm19_coupled_run(self.h, ctypes.byref(r)))
+        return st, r
+
+    def fields(self):
+        """(C on the O2 grid, reservoir plane included; phi on the structure grid)."""
+        import torch
+
+        nz, ny, nx = self.shape
+        nx_o = nx + (1 if self.params.reservoir_plane else 0)
+        c = torch.empty((nz, ny, nx_o), dtype=torch.float32, device=self.device)
+        phi = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+        torch.cuda.current_stream(self.device).synchronize()
+        _check("lbm19_coupled_fields", load().lbm19_coupled_fields(self.h, c.data_ptr(), phi.data_ptr()))
+        return c, phi
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().lbm19_coupled_destroy(self.h)
         self.h = None
 
     def __del__(self):

@@ -306,3 +306,37 @@ def test_d3q19_entry_points_on_the_host():
     assert L.lbm19_deff(h, ctypes.byref(d)) == lbm.ERR_NO_PERCOLATION and d.value == 0.0
     L.lbm19_destroy(h)
     L.lbm19_destroy(None)
+
+
+def test_coupled_entry_points_on_the_host():
+    """lbm19_coupled_*: defaults, argument checks and the stability bound, with
+    no device call."""
+    import ctypes
+
+    L = lbm.load()
+    c = lbm.lbm_coupling_default()
+    assert (c.k_ref, c.beta, c.gamma, c.phi_m, c.theta, c.max_iter) == (1e-2, 21.3, 1e-3, 0.6, 0.5, 200)
+    ph = sg.pt_cl(4, shape=(6, 8, 12))
+    ph[:, :, -1][ph[:, :, -1] == lbm.PORE] = lbm.IONOMER
+    g = lbm.lbm_grid(12, 8, 6, 2e-9)
+    u8 = ph.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+
+    def create(p, cp):
+        h = ctypes.c_void_p()
+        return L.lbm19_coupled_create(ctypes.byref(g), u8, ctypes.byref(p), ctypes.byref(cp), ctypes.byref(h)), h
+
+    st, h = create(lbm.lbm_params_default(mode=lbm.MODE_REACT), c)
+    assert st == 0
+    n = ctypes.c_size_t()
+    assert L.lbm19_coupled_workspace_bytes(h, ctypes.byref(n)) == 0 and n.value > 2 * 19 * 4 * 12 * 8 * 6
+    assert L.lbm19_coupled_run(h, None) == lbm.ERR_UNBOUND
+    L.lbm19_coupled_destroy(h)
+    for kw in (dict(theta=0.0), dict(theta=1.5), dict(tau_phi=0.5), dict(k_ref=0.0), dict(tol_phi=0.0),
+               dict(max_iter=0), dict(struct_size=8), dict(gamma=-1.0)):
+        assert create(lbm.lbm_params_default(mode=lbm.MODE_REACT), lbm.lbm_coupling_default(**kw))[0] \
+            == lbm.ERR_INVALID_ARG, kw
+    assert create(lbm.lbm_params_default(mode=lbm.MODE_DEFF), c)[0] == lbm.ERR_INVALID_ARG
+    # k n must stay below 1 on a site with six Pt faces at the membrane potential
+    assert create(lbm.lbm_params_default(mode=lbm.MODE_REACT),
+                  lbm.lbm_coupling_default(k_ref=0.1, phi_m=0.7))[0] == lbm.ERR_UNSTABLE
+    L.lbm19_coupled_destroy(None)
