@@ -899,11 +899,11 @@ int lbm19_coupled_run(lbm19_coupled *c, lbm_coupled_info *info) {
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return cl::record_error(e, "lbm19_coupled_run");
         int st = lbm19_run_to_steady(c->o2, &r);
+        I.o2_steps = r.steps;
         if (st != LBM_OK) {  // an error, or an inner solve out of steps
             inner = st;
             break;
         }
-        I.o2_steps = r.steps;
         I.rate = r.rate;
         st = lbm19_concentration(c->o2, c->at<float>(c->off_c));
         if (st < 0) return I.status = st;
@@ -914,11 +914,11 @@ int lbm19_coupled_run(lbm19_coupled *c, lbm_coupled_info *info) {
         e = hipGetLastError();
         if (e != hipSuccess) return cl::record_error(e, "lbm19_coupled_run");
         st = lbm19_run_to_steady(c->phi, &r);
+        I.phi_steps = r.steps;
         if (st != LBM_OK) {
             inner = st;
             break;
         }
-        I.phi_steps = r.steps;
         I.proton_in = -r.j_out;
         I.source = r.rate;
         st = lbm19_concentration(c->phi, c->at<float>(c->off_new));
