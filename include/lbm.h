@@ -407,7 +407,8 @@ void lbm19_destroy(lbm19_solver *s);
  *   mismatch, k_ref <= 0, beta < 0, gamma < 0, tau_phi <= 1/2, theta outside
  *   (0, 1], tol_phi <= 0, max_iter < 1, a mode other than LBM_MODE_REACT or
  *   c_in <= 0; LBM_ERR_UNSTABLE when 6 k_ref exp(beta max(0, phi_m - phi_ref))
- *   >= 1; otherwise the errors of lbm19_create.
+ *   >= 1; LBM_ERR_NO_PERCOLATION when no reaction site is reached by both
+ *   problems; otherwise the errors of lbm19_create.
  * lbm19_coupled_workspace_bytes / lbm19_coupled_bind: as lbm19_*; the workspace
  *   holds both solvers and five FP32 fields of the structure grid.
  * lbm19_coupled_run: the iteration above; *info (may be NULL) receives the

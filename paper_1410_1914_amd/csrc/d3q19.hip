@@ -819,6 +819,9 @@ int lbm19_coupled_create(const lbm_grid *g, const uint8_t *phase, const lbm_para
                 if (F.active[v] && O.active[vo] && O.phase[vo] == LBM_IONOMER && O.n_cat[vo] > 0)
                     c->n_site[v] = (float)O.n_cat[vo];
             }
+        // no site reached by both oxygen and protons: nothing to couple
+        if (std::none_of(c->n_site.begin(), c->n_site.end(), [](float n) { return n > 0.f; }))
+            return LBM_ERR_NO_PERCOLATION;
         lbm19_workspace_bytes(c->o2, &c->ws_o2);
         lbm19_workspace_bytes(c->phi, &c->ws_phi);
         size_t o = align256(c->ws_o2);

@@ -339,4 +339,9 @@ def test_coupled_entry_points_on_the_host():
     # k n must stay below 1 on a site with six Pt faces at the membrane potential
     assert create(lbm.lbm_params_default(mode=lbm.MODE_REACT),
                   lbm.lbm_coupling_default(k_ref=0.1, phi_m=0.7))[0] == lbm.ERR_UNSTABLE
+    # no ionomer at the membrane face: no site is reached by the potential
+    dry = ph.copy()
+    dry[:, :, -1][dry[:, :, -1] == lbm.IONOMER] = lbm.PORE
+    u8 = dry.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    assert create(lbm.lbm_params_default(mode=lbm.MODE_REACT), c)[0] == lbm.ERR_NO_PERCOLATION
     L.lbm19_coupled_destroy(None)
