@@ -123,3 +123,88 @@ def test_stronger_proton_resistance_lowers_the_rate():
     ph = _structure(4)
     rates = [CO.solve(ph, L.Params(), CO.Coupling(gamma=g)).rate for g in (0.0, 2e-3, 2e-2)]
     assert rates[0] > rates[1] > rates[2] > 0
+
+
+def _lap(act, rate, face_in, face_out, c_in, c_out):
+    """A u = b for the D3Q19 link Laplacian at tau = 1 on the simulated voxels:
+    sum a_i (u_n - u) + sum 2 a_i (C_b - u) over open face links = rate u."""
+    import scipy.sparse as sp
+
+    nz, ny, nx = act.shape
+    idx = -np.ones(act.shape, np.int64)
+    idx[act] = np.arange(act.sum())
+    n = int(act.sum())
+    rows, cols, vals = [], [], []
+    b = np.zeros(n)
+    links = [c for c in itertools.product((-1, 0, 1), repeat=3) if 0 < sum(map(abs, c)) <= 2]
+    for z, y, x in zip(*np.nonzero(act)):
+        i = idx[z, y, x]
+        diag = rate[z, y, x]
+        for cx, cy, cz in links:
+            a = 1 / 18 if abs(cx) + abs(cy) + abs(cz) == 1 else 1 / 36
+            tx, ty, tz = x + cx, (y + cy) % ny, (z + cz) % nz
+            if tx < 0 or tx >= nx:
+                if act[tz, ty, x] and (face_in if tx < 0 else face_out):
+                    diag += 2 * a
+                    b[i] += 2 * a * (c_in if tx < 0 else c_out)
+            elif act[tz, ty, tx]:
+                diag += a
+                rows.append(i)
+                cols.append(idx[tz, ty, tx])
+                vals.append(-a)
+        rows.append(i)
+        cols.append(i)
+        vals.append(diag)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(n, n)), b
+
+
+def test_coupled_fixed_point_at_tau_one_equals_a_direct_nonlinear_solve():
+    """With every tau = 1, the coupled fixed point solves, independently of the
+    LBM and of the Picard iteration: u = (1 - k n) C obeys the link Laplacian with
+    rate k n / (1 - k n) (k from phi), and w = phi - q obeys it with phi_m on the
+    membrane face and source q(C, phi).  Solved here as one nonlinear system by a
+    library root finder."""
+    from scipy.optimize import root
+
+    ph = _structure(4)
+    params = L.Params(d_ionomer_rel=1.0)          # every diffusivity equal: tau = 1
+    cp = CO.Coupling(gamma=2e-2)
+    r = CO.solve(ph, params, cp)
+    po, pp = CO.o2_problem(ph, params, cp), CO.phi_problem(ph, cp)
+    assert np.allclose(po.tau[po.active], 1.0) and np.allclose(pp.tau[pp.active], 1.0)
+    off = po.nx - pp.nx
+    n = CO.sites(po, pp)
+    n_o = np.zeros(po.active.shape)
+    n_o[:, :, off:] = n
+    ao, ap = po.active, pp.active
+    zero_o, zero_p = np.zeros(ao.shape), np.zeros(ap.shape)
+    A_phi, b_phi = _lap(ap, zero_p, False, True, 0.0, cp.phi_m)
+    no, npp = int(ao.sum()), int(ap.sum())
+
+    def unpack(xv):
+        C = np.zeros(ao.shape)
+        C[ao] = xv[:no]
+        phi = np.full(ap.shape, cp.phi_m)
+        phi[ap] = xv[no:]
+        return C, phi
+
+    def residual(xv):
+        C, phi = unpack(xv)
+        e = np.ones(ao.shape)
+        e[:, :, off:] = np.exp(cp.beta * (phi - cp.phi_ref))
+        kn = cp.k_ref * n_o * e
+        A_o, b_o = _lap(ao, kn / (1 - kn), True, False, params.c_in, 0.0)
+        u = ((1 - kn) * C)[ao]
+        q = cp.gamma * n * (C[:, :, off:] / params.c_in) * np.exp(cp.beta * (phi - cp.phi_ref))
+        w = (phi - q)[ap]
+        return np.concatenate([A_o @ u - b_o, A_phi @ w - b_phi + q[ap]])
+
+    # the Picard fixed point satisfies the independent equations ...
+    assert np.abs(residual(np.concatenate([r.C[ao], r.phi[ap]]))).max() < 1e-10
+    # ... and a library root finder from a generic start lands on it
+    x0 = np.concatenate([np.ones(no), np.full(npp, cp.phi_m)])
+    sol = root(residual, x0, method="hybr", tol=1e-14)
+    assert np.abs(residual(sol.x)).max() < 1e-11
+    C, phi = unpack(sol.x)
+    assert np.abs(phi - r.phi).max() < 1e-9
+    assert np.abs(np.where(ao, C, 0) - np.where(ao, r.C, 0)).max() < 1e-9
