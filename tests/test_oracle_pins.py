@@ -352,3 +352,142 @@ def test_step_is_linear_in_boundary_data():
     b = O.solve(ph, _params(knudsen=True, c_in=2.0, c_out=0.0))
     assert b.deff == pytest.approx(a.deff, rel=1e-12)
     assert np.allclose(b.f, 2 * a.f, atol=1e-13)
+
+
+# ------------------------------------------------------------------ per-voxel Knudsen mapping
+
+def _slit_and_line(nx=16, ny=8, nz=6):
+    """Carbon with two straight pore channels along x, neither touching the other:
+    a slit one voxel thick in y spanning every z (y = 1), and a 1 x 1 line
+    (y = 4, z = 2).  Every diagonal run with a y or z step leaves a channel after
+    one voxel, so the pore size is uniform along each channel, x faces included."""
+    ph = np.full((nz, ny, nx), O.CARBON, np.uint8)
+    ph[:, 1, :] = O.PORE
+    ph[2, 4, :] = O.PORE
+    return ph
+
+
+def _hand_dp(nx, ny, nz):
+    """Section 2.1.3 by hand, in voxel edges: the mean over the 13 directions of the
+    pore run through a voxel times |d|.
+    Slit (thickness 1 in y, all of z): x -> nx, y -> 1, z -> nz (one period),
+    (1,+-1,0) -> 1 x sqrt2, (1,0,+-1) -> nx x sqrt2 (z wraps, x stops at the faces),
+    (0,1,+-1) -> 1 x sqrt2, the four body diagonals -> 1 x sqrt3.
+    Line (1 x 1): x -> nx, every other direction -> one voxel."""
+    r2, r3 = math.sqrt(2.0), math.sqrt(3.0)
+    slit = (nx + 1 + nz + r2 * (1 + 1 + nx + nx + 1 + 1) + 4 * r3) / 13.0
+    line = (nx + 1 + 1 + 6 * r2 + 4 * r3) / 13.0
+    return slit, line
+
+
+@pytest.mark.parametrize("voxel_m", [2e-9, 1e-9])
+def test_knudsen_mapping_of_straight_channels(voxel_m):
+    """Knudsen diffusivity per voxel, end to end: d_p by hand (Section 2.1.3), D_Kn of
+    d_p * voxel edge (Eq. 8, T = 353 K, M = 0.032), Bosanquet with D_b (Eqs. 7, 9),
+    tau from D / D_ref with D_ref the larger channel's D (Eq. 24), and the exact
+    steady state of straight channels: D_eff/D0 = sum over channels of (area / A) D/D_b
+    (anti-bounce-back faces make the linear profile exact at any tau)."""
+    nx, ny, nz = 16, 8, 6
+    ph = _slit_and_line(nx, ny, nz)
+    T = 353.0
+    prob = O.prepare(ph, _params(knudsen=True, voxel_m=voxel_m, T_K=T))
+    dp_slit, dp_line = _hand_dp(nx, ny, nz)
+    assert np.allclose(prob.d_p[:, 1, :], dp_slit, rtol=0, atol=1e-12)
+    assert np.allclose(prob.d_p[2, 4, :], dp_line, rtol=0, atol=1e-12)
+    # Eqs. 7-9 written out: D_b, D_Kn = (d / 3) sqrt(8 R T / (pi M)), 1/D = 1/D_b + 1/D_Kn
+    D_b = 0.22e-4 * (T / 293.2) ** 1.5
+    vbar = math.sqrt(8 * 8.314 * T / (math.pi * 0.032))
+    D = [1.0 / (1.0 / D_b + 3.0 / (d * voxel_m * vbar)) for d in (dp_slit, dp_line)]
+    assert D[0] > D[1]
+    assert np.allclose(prob.D[:, 1, :], D[0], rtol=1e-13)
+    assert np.allclose(prob.D[2, 4, :], D[1], rtol=1e-13)
+    # tau_ref = 1 goes to the largest diffusivity (the slit); the line scales with it
+    assert np.allclose(prob.tau[:, 1, :], 1.0, rtol=0, atol=1e-14)
+    assert np.allclose(prob.tau[2, 4, :], 0.5 + 0.5 * D[1] / D[0], rtol=0, atol=1e-14)
+    s = O.solve_fixed_point(prob)
+    want = (nz * D[0] + 1 * D[1]) / (ny * nz) / D_b
+    assert s.deff == pytest.approx(want, rel=1e-11)
+    # Knudsen matters here: without it the same structure gives the open-area fraction
+    s0 = O.solve(ph, _params(knudsen=False))
+    assert s0.deff == pytest.approx((nz + 1) / (ny * nz), rel=1e-11)
+    assert want < 0.5 * s0.deff
+
+
+# ------------------------------------------------------------------ catalyst face neighbours
+
+def test_catalyst_neighbour_count_hand_built():
+    """n(x) of Eq. 18a: catalyst face neighbours, periodic in y and z, nothing
+    beyond the x faces.  Counted by hand on a built map."""
+    nz, ny, nx = 4, 5, 6
+    ph = np.zeros((nz, ny, nx), np.uint8)
+    # corner voxel (z, y, x) = (0, 0, 0): Pt at x + 1 (counts), across the y wrap
+    # (y = 4) and across the z wrap (z = 3) (both count), and at x = 5 of its own
+    # row (does not count: x is not periodic)
+    ph[0, 0, 1] = O.PT
+    ph[0, 4, 0] = O.PT
+    ph[3, 0, 0] = O.PT
+    ph[0, 0, 5] = O.PT
+    # voxel (2, 2, 3): catalyst on all six faces, carbon on three of them
+    for dz, dy, dx, phase in ((1, 0, 0, O.PT), (-1, 0, 0, O.CARBON), (0, 1, 0, O.PT), (0, -1, 0, O.CARBON),
+                              (0, 0, 1, O.PT), (0, 0, -1, O.CARBON)):
+        ph[2 + dz, 2 + dy, 3 + dx] = phase
+    # voxel (1, 3, 5) on the outlet face: Pt at x = 0 of its row must not count,
+    # Pt at x = 4 counts
+    ph[1, 3, 0] = O.PT
+    ph[1, 3, 4] = O.PT
+    pt_only = O.catalyst_neighbours(ph, 1 << O.PT)
+    pt_carbon = O.catalyst_neighbours(ph, (1 << O.PT) | (1 << O.CARBON))
+    assert pt_only[0, 0, 0] == 3
+    assert pt_only[2, 2, 3] == 3 and pt_carbon[2, 2, 3] == 6
+    assert pt_only[1, 3, 5] == 1
+    # the row-end Pt at x = 5 of row (0, 0) sees the voxel at x = 4 only
+    assert pt_only[0, 0, 4] == 1
+    # brute force over every voxel: count the six face neighbours one by one
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                n = 0
+                for dz, dy, dx in ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)):
+                    xx = x + dx
+                    if xx < 0 or xx >= nx:
+                        continue
+                    n += ph[(z + dz) % nz, (y + dy) % ny, xx] == O.PT
+                assert pt_only[z, y, x] == n, (z, y, x)
+    # the sink of the reactive problem is k n on reactive fluid voxels only
+    prob = O.prepare(ph, _params(mode=O.MODE_REACT, k_lat=0.01, reservoir_plane=False))
+    assert prob.kn[0, 0, 0] == pytest.approx(0.03, rel=1e-15)
+    assert prob.kn[0, 0, 1] == 0.0  # a Pt voxel does not react itself
+
+
+@pytest.mark.parametrize("N,k", [(24, 0.004)])
+def test_reactive_channel_cosh_along_z_neighbours(N, k):
+    """The cosh channel with its catalyst neighbours across the z wrap instead of y:
+    a pore row at z = 0 of a (2, 1, N) map whose other plane is Pt has n = 2 (z = 1
+    and, through the wrap, z = -1), and ny = 1 makes its y neighbours itself."""
+    ph = np.full((2, 1, N), O.PT, np.uint8)
+    ph[0, 0, :] = O.PORE
+    prob = O.prepare(ph, _params(mode=O.MODE_REACT, k_lat=k, reservoir_plane=False))
+    assert (prob.n_cat[0, 0] == 2).all()
+    s = O.solve_fixed_point(prob)
+    C = O.concentration(prob, s.f)[0, 0]
+    kappa = 2 * k / (1 - 2 * k)
+    th = math.acosh(1 + kappa / (2 * 0.125))
+    A = 2.0 / (math.cosh(th * (N + 0.5)) + math.cosh(th * (N - 0.5)))
+    u = A * np.cosh(th * (N - 0.5 - np.arange(N)))
+    assert np.allclose(C * (1 - 2 * k), u, rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("mode,k", [(O.MODE_DEFF, 0.0), (O.MODE_REACT, 1e-2)])
+def test_preconditioned_gmres_route_agrees_with_sparse_lu(mode, k):
+    """The Krylov route used for the stored fixed points of large catalyst layers
+    (GMRES with an incomplete-LU preconditioner, certified by one plain step) gives
+    the sparse direct solve's answer on a four-phase Knudsen layer."""
+    ph = sg.pt_cl(8, shape=(8, 10, 20))
+    prob = O.prepare(ph, _params(mode=mode, knudsen=True, voxel_m=2e-9, k_lat=k))
+    a = O.solve_fixed_point(prob, "direct")
+    b = O.solve_fixed_point(prob, "gmres")
+    assert np.abs(b.f - a.f).max() < 1e-12
+    if mode == O.MODE_DEFF:
+        assert b.deff == pytest.approx(a.deff, rel=1e-11)
+    else:
+        assert b.rate == pytest.approx(a.rate, rel=1e-11)
