@@ -84,12 +84,18 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(info, knudsen: bool, n_listed: int) -> float:
-    """Bytes one stream-collide launch must move: 7 FP32 reads + 7 FP32 writes per
-    fluid voxel (+4 for its FP32 1/tau with Knudsen), and per listed 64-voxel
-    segment its 120-byte record and 4-byte list entry."""
-    per_fluid = 56.0 + (4.0 if knudsen else 0.0)
-    return info.n_active * per_fluid + n_listed * 124.0
+def algorithmic_bytes(info, knudsen: bool) -> float:
+    """Bytes one stream-collide launch must move per the method's data: 7 FP32
+    reads + 7 FP32 writes per fluid voxel (56 B), plus its metadata: 1 B of flags
+    and, with Knudsen diffusivity, its FP32 1/tau (61 B per fluid update)."""
+    return info.n_active * (56.0 + 1.0 + (4.0 if knudsen else 0.0))
+
+
+def metadata_bytes(n_listed: int) -> float:
+    """Bytes of the layout's own bookkeeping per launch, reported apart from the
+    algorithmic bytes: per listed 64-voxel segment its 120-byte record and 4-byte
+    list entry."""
+    return n_listed * 124.0
 
 
 def listed_segments(active):
@@ -160,7 +166,8 @@ def headline(args, lbm, structgen):
     mlups = updates / wall / 1e6
     per_launch_s = kms / 1e3 / steps_timed * spl
     # one launch, of either form, must read and write the lattice once
-    alg = algorithmic_bytes(info, knudsen=True, n_listed=listed_segments(s.host_fields()[0]))
+    alg = algorithmic_bytes(info, knudsen=True)
+    meta = metadata_bytes(listed_segments(s.host_fields()[0]))
     achieved = alg / per_launch_s / 1e9
     log(f"[bench] {steps_timed} LBM steps in {wall:.3f}s: {mlups:.0f} MLUPS; kernel mean {per_launch_s*1e6:.1f} us "
         f"per launch ({spl} step(s)), {achieved:.0f} GB/s algorithmic")
@@ -177,7 +184,10 @@ def headline(args, lbm, structgen):
             "tiling": {"segs_per_wave": tiling[0], "waves_per_block": tiling[1], "xcd_remap": tiling[2],
                        "two_step_rows": temporal[0] if spl == 2 else 0,
                        "two_step_planes": temporal[1] if spl == 2 else 0},
-            "alg_bytes_per_launch": int(alg), "mean_launch_us": round(per_launch_s * 1e6, 2),
+            "alg_bytes_per_launch": int(alg), "alg_bytes_per_update": 61,
+            "metadata_bytes_per_launch": int(meta),
+            "traffic_bytes_per_launch": (int(tb) if tb else None),
+            "mean_launch_us": round(per_launch_s * 1e6, 2),
             "kernel_source_sha": sha}
     res = {"mlups": mlups, "ms_per_step": 1e3 * wall / args.steps, "roofline": roof, "workload": workload,
            "other_form": other,
@@ -453,7 +463,7 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": round(head["ms_per_step"], 3),
         "higher_is_better": True,
-        "scaling": "weak",
+        "scaling": "none",
         "vs_baseline": None,
         "dtype": "f64",
         "storage_dtype": "f32",

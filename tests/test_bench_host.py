@@ -29,8 +29,10 @@ def test_listed_segments_brute_force():
 def test_algorithmic_bytes():
     # 7 FP32 reads + 7 FP32 writes per fluid update, +4 B of 1/tau with Knudsen,
     # and 120 B record + 4 B list entry per visited segment
-    assert bench.algorithmic_bytes(_Info(256), knudsen=False, n_listed=4) == 256 * 56 + 4 * 124
-    assert bench.algorithmic_bytes(_Info(256), knudsen=True, n_listed=4) == 256 * 60 + 4 * 124
+    # 56 B of populations + 1 B of flags per fluid update, + 4 B of 1/tau with Knudsen
+    assert bench.algorithmic_bytes(_Info(256), knudsen=False) == 256 * 57
+    assert bench.algorithmic_bytes(_Info(256), knudsen=True) == 256 * 61
+    assert bench.metadata_bytes(4) == 4 * 124
 
 
 def test_traffic_lookup_requires_matching_kernel_source():
