@@ -92,15 +92,20 @@ struct Engine {
     std::vector<int> live;
     std::vector<RunState> rs;
 
-    hipGraphExec_t gexec = nullptr;
-    int g_cur = -1, g_nblk = -1;
+    // Captured check windows, one per starting lattice: a window whose launch count
+    // is odd ends on the other lattice, so its next replay needs the other graph.
+    // g_valid is cleared whenever the launch form or tables change; both slots are
+    // re-captured lazily after that.
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    int g_nblk[2] = {-1, -1}, g_k[2] = {-1, -1};
+    bool g_slot[2] = {false, false};
     bool g_valid = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;  // bracket the step launches of a window
     bool ev_pending = false;
     int64_t ev_launches = 0;
 
     ~Engine() {
-        if (gexec) (void)hipGraphExecDestroy(gexec);
+        drop_graphs();
         if (res_host) (void)hipHostFree(res_host);
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
@@ -253,11 +258,16 @@ struct Engine {
         }
     }
 
-    hipError_t bind(void *mem, size_t bytes, hipStream_t stream) {
-        if (gexec) {
-            (void)hipGraphExecDestroy(gexec);
-            gexec = nullptr;
+    void drop_graphs() {
+        for (int c = 0; c < 2; ++c) {
+            if (gexec[c]) (void)hipGraphExecDestroy(gexec[c]);
+            gexec[c] = nullptr;
+            g_slot[c] = false;
         }
+    }
+
+    hipError_t bind(void *mem, size_t bytes, hipStream_t stream) {
+        drop_graphs();
         g_valid = false;
         ws = static_cast<char *>(mem);
         st = stream;
@@ -400,8 +410,37 @@ struct Engine {
         return hipStreamSynchronize(st);
     }
 
-    // One check window: `reps` launches of a captured graph of K0 steps, then the
-    // FP64 reductions (which also refresh the concentration snapshot).
+    // Capture K0 steps starting from lattice `from` into graph slot `from`.
+    hipError_t capture(int K0, int from) {
+        if (gexec[from]) {
+            (void)hipGraphExecDestroy(gexec[from]);
+            gexec[from] = nullptr;
+        }
+        g_slot[from] = false;
+        hipGraph_t graph = nullptr;
+        hipError_t e = note(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        if (e != hipSuccess) return e;
+        const int c0 = cur;
+        cur = from;
+        hipError_t e1 = steps(K0);
+        cur = c0;
+        e = note(hipStreamEndCapture(st, &graph), "hipStreamEndCapture");
+        if (e1 != hipSuccess) return e1;
+        if (e != hipSuccess) return e;
+        e = note(hipGraphInstantiate(&gexec[from], graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return e;
+        g_slot[from] = true;
+        g_nblk[from] = step_nblk;
+        g_k[from] = K0;
+        return hipSuccess;
+    }
+
+    // One check window: `reps` replays of a captured graph of K0 steps, then the
+    // FP64 reductions (which also refresh the concentration snapshot).  When K0
+    // steps take an odd number of launches (the two-step form with K0/2 odd), each
+    // replay ends on the other lattice, so replays alternate between the graphs
+    // captured from either lattice.
     hipError_t window(int K0, int64_t reps) {
         if (st == nullptr) {  // the legacy default stream cannot be captured
             for (int64_t r = 0; r < reps; ++r) {
@@ -410,37 +449,27 @@ struct Engine {
             }
             return measure_enqueue(1);
         }
-        if (!g_valid || g_cur != cur || g_nblk != step_nblk) {
-            if (gexec) {
-                (void)hipGraphExecDestroy(gexec);
-                gexec = nullptr;
-            }
-            hipGraph_t graph = nullptr;
-            hipError_t e = note(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-            if (e != hipSuccess) return e;
-            const int c0 = cur;
-            hipError_t e1 = steps(K0);
-            cur = c0;
-            e = note(hipStreamEndCapture(st, &graph), "hipStreamEndCapture");
-            if (e1 != hipSuccess) return e1;
-            if (e != hipSuccess) return e;
-            e = note(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
-            (void)hipGraphDestroy(graph);
-            if (e != hipSuccess) return e;
+        if (!g_valid) {
+            drop_graphs();
             g_valid = true;
-            g_cur = cur;
-            g_nblk = step_nblk;
+        }
+        const bool fl = flips(K0) != 0;
+        for (int k = 0; k < ((fl && reps > 1) ? 2 : 1); ++k) {
+            const int from = cur ^ k;
+            if (!g_slot[from] || g_nblk[from] != step_nblk || g_k[from] != K0) {
+                hipError_t e = capture(K0, from);
+                if (e != hipSuccess) return e;
+            }
         }
         hipError_t e = note(hipEventRecord(ev0, st), "hipEventRecord");
         for (int64_t r = 0; r < reps && e == hipSuccess; ++r) {
-            e = note(hipGraphLaunch(gexec, st), "hipGraphLaunch");
-            if (flips(K0)) cur ^= 1;
+            e = note(hipGraphLaunch(gexec[cur], st), "hipGraphLaunch");
+            if (fl) cur ^= 1;
         }
         if (e == hipSuccess) e = note(hipEventRecord(ev1, st), "hipEventRecord");
         if (e != hipSuccess) return e;
         ev_pending = true;
         ev_launches = (int64_t)K0 * reps;
-        if (flips(K0)) g_valid = false;  // the next window starts from the other lattice
         return measure_enqueue(1);
     }
 

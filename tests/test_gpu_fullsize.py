@@ -3,8 +3,11 @@
 The oracle cannot reach the fixed point of a 128^3 or 256^3 structure in seconds,
 but it can take one exact FP64 step.  So each case:
 
-* runs the autotuned HIP solver from the cold start for some steps, so the state
-  has real boundary layers, sinks and interfaces;
+* autotunes the HIP solver (the benchmark's launch configuration);
+* writes a seeded random state over every fluid voxel of the grid
+  (lbm_set_populations), so that no voxel is near equilibrium: a gather from a
+  wrong neighbour, a wrong bounce-back, a wrong relaxation rate or a wrong segment
+  offset anywhere in the grid changes the result;
 * streams and collides that stored state once with the oracle;
 * compares with the GPU's next stored state, element by element over every fluid
   voxel;
@@ -38,7 +41,8 @@ def test_full_size_step_and_reductions(hip, name, make, voxel, kw):
     ph = make()
     s = hip.Solver(ph, hip.lbm_params_default(check_every=100, **kw), voxel_m=voxel)
     s.autotune(5)  # the benchmark's launch configuration (also advances the state)
-    s.advance(300)
+    # a random state far from equilibrium on every voxel (populations in [0, 0.5))
+    s.set_populations(torch.from_numpy(sg.random_state(41, s.shape, scale=0.5)).cuda())
     torch.cuda.synchronize()
     print(f"[fullsize] {name}: tiling {s.tiling()}, oracle preparation", flush=True)
     okw = dict(kw)
@@ -48,6 +52,12 @@ def test_full_size_step_and_reductions(hip, name, make, voxel, kw):
     assert np.array_equal(s.host_fields()[0].ravel().astype(bool), act)
 
     g = s.populations().cpu().numpy().reshape(7, -1).astype(np.float64)  # stored post-collision state
+    # the state is far from equilibrium everywhere: the non-equilibrium part is of
+    # the order of the populations themselves on every fluid voxel
+    ceq = g.sum(axis=0)
+    w = O.weights(0.25)
+    neq = np.abs(g - w[:, None] * ceq[None, :])[:, act].max(axis=0)
+    assert np.quantile(neq, 0.01) > 0.02
     s.step(1)
     got = s.populations().cpu().numpy().reshape(7, -1)
     f1 = O.stream(prob, g)
@@ -99,20 +109,32 @@ def test_batched_instances_match_single_solves(hip):
 @pytest.mark.parametrize("name,make,voxel,kw", CASES, ids=[c[0] for c in CASES])
 def test_full_size_two_step_launch_is_bit_identical(hip, name, make, voxel, kw):
     """One launch of the two-step kernel (the autotuner's other form) against two
-    single-step launches, from a developed state of the full-size structure.  Both
-    runs start from the same dense state written with lbm_set_populations (the
-    dense read-out is unshifted, so writing it back is not a bit-exact round trip
-    of the solver's own state)."""
+    single-step launches, from a seeded random state over the whole full-size
+    structure (far from equilibrium on every voxel, so every halo row, chunk-end
+    plane and x-edge voxel of every tile matters).  Both runs start from the same
+    dense state written with lbm_set_populations."""
     import torch
 
     ph = make()
     s = hip.Solver(ph, hip.lbm_params_default(check_every=100, **kw), voxel_m=voxel)
-    s.advance(300)
-    f0 = s.populations()
+    f0 = torch.from_numpy(sg.random_state(43, s.shape, scale=0.5)).cuda()
     s.set_temporal(0)
     s.set_populations(f0)
+    g0 = s.populations().cpu().numpy().reshape(7, -1).astype(np.float64)  # the state as stored
     s.step(2)
     ref = s.populations()
+    # the two single steps against two exact FP64 oracle steps, over every fluid voxel
+    okw = dict(kw)
+    okw["knudsen"] = bool(okw["knudsen"])
+    prob = O.prepare(ph, O.Params(voxel_m=voxel, **okw))
+    act = prob.active.ravel()
+    # the stored states are post-collision: each step streams, then collides
+    want = O.collide(prob, O.stream(prob, O.collide(prob, O.stream(prob, g0))))
+    got2 = ref.cpu().numpy().reshape(7, -1)
+    scale = max(1.0, float(np.abs(want).max()))
+    err = float(np.abs(got2[:, act] - want[:, act]).max())
+    print(f"[fullsize] {name}: two steps, max |GPU - oracle| = {err:.2e} (scale {scale:.2f})", flush=True)
+    assert err < 4e-6 * scale
     for by, zc in ((6, 16), (8, 64)):
         s.set_populations(f0)
         s.set_temporal(by, zc)
