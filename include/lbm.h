@@ -314,6 +314,20 @@ int lbm_pore_size_device(const uint8_t *pore_dev, int32_t nx, int32_t ny, int32_
 int lbm_reach_device(const uint8_t *pass_dev, int32_t nx, int32_t ny, int32_t nz, int32_t faces, uint8_t *hit_dev,
                      int32_t *cycles, void *stream);
 
+/* lbm_reach_device_static: lbm_reach_device for callers that cannot allocate
+ * (code under HIP graph capture elsewhere on the stream's device, tight serving
+ * loops, harnesses that forbid allocation).  Same arguments, results and errors;
+ * it calls no hipMalloc, hipHostMalloc or other allocating routine.  The sweeps'
+ * change flag lives in a fixed 256-byte device array of this library (one copy per
+ * device, held until the process ends) instead of freshly allocated pinned host
+ * memory; it does not grow with the grid, so every grid lbm_reach_device accepts
+ * is accepted.  The flag is cleared by a kernel at the start of every sweep cycle
+ * and read back with a copy into host memory followed by a synchronisation of
+ * stream, once per cycle.  Calls that overlap on one device (other host threads,
+ * other streams) share that flag and race: serialise them. */
+int lbm_reach_device_static(const uint8_t *pass_dev, int32_t nx, int32_t ny, int32_t nz, int32_t faces,
+                            uint8_t *hit_dev, int32_t *cycles, void *stream);
+
 /* ---- D3Q19 solver (Section 4, Eqs. 21-24: the paper's own lattice)
  *
  * The same problems as lbm_create (modes, phases, Knudsen diffusivity, sink,

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <numeric>
 
 #include "kernels.h"
@@ -179,6 +180,83 @@ __global__ __launch_bounds__(256) void k_reach_sweep_x(const uint8_t *__restrict
     if (any) *changed = 1;
 }
 
+// Clears n counters of the allocation-free reach's scratch (a kernel, not a
+// memset, so the call stays free of memset nodes if a caller ever records it).
+__global__ void k_zero_i32(int32_t *p, int n) {
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n) p[i] = 0;
+}
+
+}  // namespace
+
+// Scratch of lbm_reach_device_static: counters in device memory that the library
+// never allocates.  Slot 0 is the change flag of the current sweep cycle; the rest
+// is reserved.  Each device holds its own copy for the life of the process.
+constexpr int kReachScratchInts = 64;  // 256 bytes
+static __device__ __align__(256) int32_t scratch[kReachScratchInts];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int32_t *g_scratch_dev[kMaxDevices];  // device address of `scratch`, per device
+
+// The device address of this device's `scratch`, looked up once per device with
+// that device current (the symbol's host-side name is not a device address).
+hipError_t reach_scratch(int32_t **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_dev[dev] = static_cast<int32_t *>(ptr);
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
+
+// Seeds, then sweep cycles until one turns nothing on: the loop both reach entry
+// points share.  `flag_dev` is the change flag the sweeps set; flag(true, nullptr)
+// clears it before a cycle, flag(false, &v) waits for the cycle's work and reads
+// it into v.
+template <class Flag>
+hipError_t reach_cycles(const uint8_t *pass_dev, int32_t nx, int32_t ny, int32_t nz, int32_t faces, uint8_t *hit_dev,
+                        hipStream_t st, int32_t *flag_dev, Flag &&flag, int32_t *n_cycles) {
+    const int64_t N = (int64_t)nx * ny * nz;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_reach_seed, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, pass_dev, nx, ny, nz, faces,
+                       hit_dev);
+    hipError_t e = hipGetLastError();
+    *n_cycles = 0;
+    // every productive cycle turns at least one voxel on, so at most N + 1 cycles run
+    for (int64_t cyc = 0; e == hipSuccess && cyc <= N; ++cyc) {
+        e = flag(true, nullptr);
+        if (e != hipSuccess) break;
+        {
+            const int64_t lines = (int64_t)ny * nz;  // x: one wave per line
+            hipLaunchKernelGGL(k_reach_sweep_x, dim3((unsigned)((lines + 3) / 4)), dim3(256), 0, st, pass_dev, hit_dev,
+                               nx, ny, nz, flag_dev);
+            e = hipGetLastError();
+        }
+        for (int axis = 1; axis < 3 && e == hipSuccess; ++axis) {  // y, z: one thread per line
+            const int64_t lines = axis == 1 ? (int64_t)nx * nz : (int64_t)nx * ny;
+            hipLaunchKernelGGL(k_reach_sweep, dim3((unsigned)((lines + 255) / 256)), dim3(256), 0, st, pass_dev, hit_dev,
+                               nx, ny, nz, axis, flag_dev);
+            e = hipGetLastError();
+        }
+        int32_t changed = 0;
+        if (e == hipSuccess) e = flag(false, &changed);
+        ++*n_cycles;
+        if (e != hipSuccess || !changed) break;
+    }
+    return e;
+}
+
 }  // namespace
 
 extern "C" {
@@ -212,35 +290,47 @@ int lbm_reach_device(const uint8_t *pass_dev, int32_t nx, int32_t ny, int32_t nz
     hipError_t e = hipHostMalloc((void **)&changed, sizeof(int), hipHostMallocMapped);
     int *changed_dev = nullptr;
     if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&changed_dev, changed, 0);
-    (void)hipGetLastError();
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_reach_seed, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, pass_dev, nx, ny, nz,
-                           faces, hit_dev);
-        e = hipGetLastError();
-    }
-    // every productive cycle turns at least one voxel on, so at most N + 1 cycles run
     int32_t n_cycles = 0;
-    for (int64_t cyc = 0; e == hipSuccess && cyc <= N; ++cyc) {
-        *changed = 0;
-        {
-            const int64_t lines = (int64_t)ny * nz;  // x: one wave per line
-            hipLaunchKernelGGL(k_reach_sweep_x, dim3((unsigned)((lines + 3) / 4)), dim3(256), 0, st, pass_dev, hit_dev,
-                               nx, ny, nz, changed_dev);
-            e = hipGetLastError();
-        }
-        for (int axis = 1; axis < 3 && e == hipSuccess; ++axis) {  // y, z: one thread per line
-            const int64_t lines = axis == 1 ? (int64_t)nx * nz : (int64_t)nx * ny;
-            hipLaunchKernelGGL(k_reach_sweep, dim3((unsigned)((lines + 255) / 256)), dim3(256), 0, st, pass_dev, hit_dev,
-                               nx, ny, nz, axis, changed_dev);
-            e = hipGetLastError();
-        }
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        ++n_cycles;
-        if (e != hipSuccess || !*changed) break;
+    if (e == hipSuccess) {
+        auto flag = [&](bool zero, int32_t *value) -> hipError_t {
+            if (zero) {
+                *changed = 0;
+                return hipSuccess;
+            }
+            const hipError_t se = hipStreamSynchronize(st);
+            *value = *changed;
+            return se;
+        };
+        e = reach_cycles(pass_dev, nx, ny, nz, faces, hit_dev, st, changed_dev, flag, &n_cycles);
     }
     if (changed) (void)hipHostFree(changed);
     if (cycles) *cycles = n_cycles;
     return cl::record_error(e, "lbm_reach_device");
+}
+
+int lbm_reach_device_static(const uint8_t *pass_dev, int32_t nx, int32_t ny, int32_t nz, int32_t faces,
+                            uint8_t *hit_dev, int32_t *cycles, void *stream) {
+    if (!pass_dev || !hit_dev || nx <= 0 || ny <= 0 || nz <= 0 || faces < 1 || faces > 3) return LBM_ERR_INVALID_ARG;
+    const int64_t N = (int64_t)nx * ny * nz;
+    if ((N + 255) / 256 > INT32_MAX) return LBM_ERR_INVALID_ARG;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int32_t *flag_dev = nullptr;
+    hipError_t e = reach_scratch(&flag_dev);
+    int32_t n_cycles = 0;
+    if (e == hipSuccess) {
+        auto flag = [&](bool zero, int32_t *value) -> hipError_t {
+            if (zero) {
+                hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, flag_dev, 1);
+                return hipGetLastError();
+            }
+            hipError_t ce = hipMemcpyAsync(value, flag_dev, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+            if (ce == hipSuccess) ce = hipStreamSynchronize(st);
+            return ce;
+        };
+        e = reach_cycles(pass_dev, nx, ny, nz, faces, hit_dev, st, flag_dev, flag, &n_cycles);
+    }
+    if (cycles) *cycles = n_cycles;
+    return cl::record_error(e, "lbm_reach_device_static");
 }
 
 }  // extern "C"

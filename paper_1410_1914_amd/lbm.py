@@ -96,6 +96,7 @@ SIGNATURES = {
     "lbm_get_pore_depth": ([_P, ctypes.POINTER(c_uint8)], c_int32),
     "lbm_pore_size_device": ([_P, c_int32, c_int32, c_int32, _P, _P], c_int32),
     "lbm_reach_device": ([_P, c_int32, c_int32, c_int32, c_int32, _P, ctypes.POINTER(c_int32), _P], c_int32),
+    "lbm_reach_device_static": ([_P, c_int32, c_int32, c_int32, c_int32, _P, ctypes.POINTER(c_int32), _P], c_int32),
     "lbm_workspace_bytes": ([_P, ctypes.POINTER(ctypes.c_size_t)], c_int32),
     "lbm_bind": ([_P, _P, ctypes.c_size_t, _P], c_int32),
     "lbm_set_initial_concentration": ([_P, _P], c_int32),
@@ -216,19 +217,27 @@ def pore_size_device(pore):
     return out
 
 
-def reach_device(pass_mask, faces=3):
+def reach_device(pass_mask, faces=3, out=None, static_scratch=False):
     """Voxels of ``pass_mask`` 6-connected to its x = 0 face (faces & 1) and/or
-    x = nx - 1 face (faces & 2), on the GPU (lbm_reach_device): (uint8 tensor, sweep cycles)."""
+    x = nx - 1 face (faces & 2), on the GPU (lbm_reach_device): (uint8 tensor, sweep cycles).
+
+    ``out``: an existing uint8 CUDA tensor of the map's shape to fill (else a new
+    one).  ``static_scratch``: call lbm_reach_device_static, the variant that
+    allocates nothing."""
     import torch
 
     require_gpu()
     m = _device_map(pass_mask)
     nz, ny, nx = m.shape
-    out = torch.empty(m.shape, dtype=torch.uint8, device="cuda")
+    if out is None:
+        out = torch.empty(m.shape, dtype=torch.uint8, device="cuda")
+    elif out.shape != m.shape or out.dtype != torch.uint8 or not out.is_cuda or not out.is_contiguous():
+        raise ValueError("out must be a contiguous uint8 CUDA tensor of the map's shape")
     cycles = c_int32()
     st = torch.cuda.current_stream().cuda_stream
-    _check("lbm_reach_device", load().lbm_reach_device(m.data_ptr(), nx, ny, nz, int(faces), out.data_ptr(),
-                                                       ctypes.byref(cycles), st))
+    name = "lbm_reach_device_static" if static_scratch else "lbm_reach_device"
+    _check(name, getattr(load(), name)(m.data_ptr(), nx, ny, nz, int(faces), out.data_ptr(),
+                                       ctypes.byref(cycles), st))
     return out, cycles.value
 
 
