@@ -103,7 +103,8 @@ int unet_zero(void *dst, int64_t bytes, void *stream);
  * voxels), rest 0.  omega is 1/tau as stored by lbm_get_host_fields (uploaded to the
  * device).  When weight is not NULL it receives the training weight of each voxel:
  * min(weight_cap, (D_ref / D)^weight_power) on active voxels, 0 elsewhere (slowly
- * relaxing, low-diffusivity voxels weigh more; weight_cap >= 1, 0 <= weight_power <= 4). */
+ * relaxing, low-diffusivity voxels weigh more; weight_cap >= 1, 0 <= weight_power <= 4).
+ * n_cat may be NULL (c2 = 0: the effective-property problems have no sink). */
 int unet_features(const uint8_t *active, const uint8_t *n_cat, const float *omega, float tau_ref,
                   uint16_t *feat, float *weight, float weight_power, float weight_cap, int32_t nz, int32_t ny,
                   int32_t nx, void *stream);
@@ -133,6 +134,92 @@ int unet_start_field(const float *y, const uint8_t *depth, int32_t depth_max, fl
  * on long ones.  c_in != c_out, cmax > 0. */
 int unet_corrector_map(const float *src, float *dst, int64_t nvox, int32_t nx, float c_in, float c_out,
                        int32_t inverse, float cmax, void *stream);
+
+/* ---- The network as one object
+ *
+ * The fixed architecture above (four levels of 16, 32, 64 and 128 channels, two
+ * 3x3x3 convolutions with ReLU per level, 2x2x2 average pooling, nearest 2x
+ * upsampling with skip concatenation, 1x1x1 FP32 head; 16 input channels from
+ * unet_features) on one grid nz x ny x nx (each a multiple of 8).
+ *
+ * Parameters are one flat FP32 array of unet_param_count() values: tensor t
+ * (0..13 the convolutions in forward order e1a e1b e2a e2b e3a e3b b4a b4b d3a d3b
+ * d2a d2b d1a d1b, 14 the head) has its weights at w_offset (w_count values:
+ * [cout][unet_kpad(cin)] as in unet_conv3d_fwd, or the head's 16 channel weights)
+ * and its bias at b_offset (cout values; the head has one).  Entries between
+ * tensors are padding (zero).
+ *
+ * unet_create: a handle for the grid; train != 0 adds the gradient buffers and the
+ *   Adam moments.  -1 for sizes that are not positive multiples of 8 or above 2^31
+ *   voxels.  No device call.
+ * unet_workspace_bytes / unet_bind: the caller-owned device workspace (>= the
+ *   size, 256-byte aligned; parameters, their BF16 copies, activations, and when
+ *   training their gradients and the moments) and the HIP stream every call
+ *   enqueues on.  bind zeroes the workspace and forgets the parameters.
+ * unet_set_params: copies params_dev (device, unet_param_count() FP32 values) in
+ *   and makes the BF16 copies; the Adam moments and step count stay (bind zeroes
+ *   them).
+ * unet_get_params: copies the FP32 parameters and/or (training) the gradients of
+ *   the last unet_backward out to device arrays of the same layout (either may be
+ *   NULL, not both).
+ * unet_forward: out_dev[v] (FP32, nz ny nx values; NULL: the internal output buffer)
+ *   = network(feat_dev) + base_dev[v] (base_dev may be NULL).  feat_dev: BF16
+ *   [v][16] as from unet_features (NULL: the internal feature buffer that
+ *   unet_features_buffer exposes).
+ * unet_backward: after unet_forward on a training handle, the gradients of the
+ *   parameters for the output gradient dout_dev (FP32 per voxel), overwriting the
+ *   previous ones.
+ * unet_adam_step: one Adam step (bias-corrected, step count kept by the handle)
+ *   of every parameter with the gradients of the last backward.
+ * unet_train_step: forward, the weighted masked MSE of unet_mse against
+ *   target_dev (mask_dev != 0 voxels, count of them, weight_dev may be NULL),
+ *   backward and an Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with rate lr;
+ *   loss_dev (may be NULL) receives the loss before the step.
+ * unet_predict: the solver's start field c_dev (FP32, nz ny nx) for a structure
+ *   given by the solver's dense device fields (active, n_cat (may be NULL), omega
+ *   = 1/tau, as lbm_get_host_fields gives them) and tau_ref: features, forward,
+ *   then the inverse of the training target per *tgt:
+ *     UNET_TARGET_LOG: min(cmax, max(0, exp(y) - eps)), and 0 (the cold start)
+ *       where depth (device, may be NULL) exceeds depth_max;
+ *     UNET_TARGET_CORRECTOR: min(cmax, max(0, lin(x) + y (c_in - c_out) / nx))
+ *       with lin the linear profile between the Dirichlet faces (Eq. 19);
+ *     UNET_TARGET_PLAIN: y itself.
+ * unet_features_buffer: device addresses of the handle's feature (BF16 [v][16])
+ *   and output (FP32 [v]) buffers.
+ * Every call returns 0, -1 for invalid arguments (NULL handle, unbound handle,
+ * parameters not set, backward without a training forward before it), -6 when a
+ * launch or copy failed.  One handle per thread. */
+typedef struct unet_net unet_net;
+
+enum { UNET_TARGET_LOG = 0, UNET_TARGET_CORRECTOR = 1, UNET_TARGET_PLAIN = 2 };
+
+typedef struct {
+    uint32_t struct_size;   /* = sizeof(unet_target)                               */
+    int32_t kind;           /* UNET_TARGET_*                                       */
+    float eps;              /* LOG: the offset of ln(C + eps)                      */
+    float cmax;             /* upper clip of the start field                       */
+    float c_in, c_out;      /* CORRECTOR: Dirichlet values at x = 0 and x = L      */
+    const uint8_t *depth;   /* LOG: pore-depth map (lbm_get_pore_depth), or NULL   */
+    int32_t depth_max;      /* LOG: keep the prediction up to this depth           */
+} unet_target;
+
+int64_t unet_param_count(void);
+int unet_param_tensor(int32_t tensor, int32_t *cin, int32_t *cout, int64_t *w_offset, int64_t *w_count,
+                      int64_t *b_offset);
+int unet_create(int32_t nz, int32_t ny, int32_t nx, int32_t train, unet_net **out);
+int unet_workspace_bytes(const unet_net *n, size_t *bytes);
+int unet_bind(unet_net *n, void *workspace_dev, size_t bytes, void *stream);
+int unet_set_params(unet_net *n, const float *params_dev);
+int unet_get_params(const unet_net *n, float *params_dev, float *grads_dev);
+int unet_forward(unet_net *n, const uint16_t *feat_dev, const float *base_dev, float *out_dev);
+int unet_backward(unet_net *n, const uint16_t *feat_dev, const float *dout_dev);
+int unet_adam_step(unet_net *n, float lr, float beta1, float beta2, float eps);
+int unet_train_step(unet_net *n, const uint16_t *feat_dev, const float *target_dev, const uint8_t *mask_dev,
+                    const float *weight_dev, int64_t count, float lr, float *loss_dev);
+int unet_predict(unet_net *n, const uint8_t *active_dev, const uint8_t *n_cat_dev, const float *omega_dev,
+                 float tau_ref, const unet_target *tgt, float *c_dev);
+int unet_features_buffer(const unet_net *n, uint16_t **feat_dev, float **out_dev);
+void unet_destroy(unet_net *n);
 
 /* Lane-layout self check of the MFMA builtin: a = A (16x32, row major FP32),
  * b = B (32x16); writes D = A B through the kernels' fragment mapping into d

@@ -18,7 +18,7 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
 
 LIBS = {
     "_liblbm.so": ["prep.cpp", "kernels.hip", "engine.hip", "charz.hip", "d3q19.hip"],
-    "_libunet.so": ["unet_kernels.hip"],
+    "_libunet.so": ["unet_kernels.hip", "unet_net.hip"],
 }
 
 

@@ -400,7 +400,7 @@ __global__ void k_features(const uint8_t *active, const uint8_t *ncat, const flo
         const float tau = 1.f / omega[v];
         const float drel = fmaxf((tau - 0.5f) / (tau_ref - 0.5f), 1e-9f);
         f[1] = log10f(drel) / 3.f;
-        f[2] = (float)ncat[v] / 6.f;
+        f[2] = ncat ? (float)ncat[v] / 6.f : 0.f;
         w = fminf(weight_cap, powf(1.f / drel, weight_power));
     }
     uint16_t *o = feat + v * 16;
@@ -623,7 +623,7 @@ int unet_zero(void *dst, int64_t bytes, void *stream) {
 int unet_features(const uint8_t *active, const uint8_t *n_cat, const float *omega, float tau_ref, uint16_t *feat,
                   float *weight, float weight_power, float weight_cap, int32_t nz, int32_t ny, int32_t nx,
                   void *stream) {
-    if (!active || !n_cat || !omega || !feat || nz <= 0 || ny <= 0 || nx <= 0 || !(tau_ref > 0.5f)) return -1;
+    if (!active || !omega || !feat || nz <= 0 || ny <= 0 || nx <= 0 || !(tau_ref > 0.5f)) return -1;
     if (weight && !(weight_cap >= 1.f && weight_power >= 0.f && weight_power <= 4.f)) return -1;
     (void)hipGetLastError();
     hipLaunchKernelGGL(k_features, grid1((int64_t)nz * ny * nx), dim3(256), 0, static_cast<hipStream_t>(stream),

@@ -1,12 +1,14 @@
-"""Binding of include/unet.h and the warm-start network built from those kernels.
+"""Binding of include/unet.h and the warm-start network.
 
-``UNet`` is a 3-D U-Net with four levels of 16, 32, 64 and 128 channels: two
-3x3x3 convolutions with ReLU per level, 2x2x2 average pooling on the way down,
-nearest-neighbour upsampling and channel concatenation with the skip tensor on the
-way up, and a 1x1x1 output head.  Every forward and backward operation is a
-kernel of ``_libunet.so`` (BF16 MFMA convolutions with FP32 accumulation, FP32
-weight gradients, Adam on FP32 master weights); this module only allocates the
-buffers (torch tensors on the GPU) and calls the kernels in order.
+The network is the library's ``unet_net`` object: a 3-D U-Net with four levels of
+16, 32, 64 and 128 channels (two 3x3x3 convolutions with ReLU per level, 2x2x2
+average pooling on the way down, nearest-neighbour upsampling and channel
+concatenation with the skip tensor on the way up, a 1x1x1 output head) whose
+forward pass, backward pass, Adam step and prediction are single C calls running
+the kernels of ``_libunet.so`` (BF16 MFMA convolutions with FP32 accumulation,
+FP32 weight gradients, Adam on FP32 master weights).  ``UNet`` holds the flat
+parameter array and the torch-owned workspaces of its handles; the layer wrappers
+below expose the individual kernels with the same names as the C calls.
 """
 from __future__ import annotations
 
@@ -42,7 +44,29 @@ SIGNATURES = {
     "unet_corrector_map": ([_P, _P, _i64, _i32, _f32, _f32, _i32, _f32, _P], _i32),
     "unet_features": ([_P, _P, _P, _f32, _P, _P, _f32, _f32, _i32, _i32, _i32, _P], _i32),
     "unet_mfma_selftest": ([_P, _P, _P, _P], _i32),
+    "unet_param_count": ([], _i64),
+    "unet_param_tensor": ([_i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i64),
+                           ctypes.POINTER(_i64), ctypes.POINTER(_i64)], _i32),
+    "unet_create": ([_i32, _i32, _i32, _i32, ctypes.POINTER(_P)], _i32),
+    "unet_workspace_bytes": ([_P, ctypes.POINTER(ctypes.c_size_t)], _i32),
+    "unet_bind": ([_P, _P, ctypes.c_size_t, _P], _i32),
+    "unet_set_params": ([_P, _P], _i32),
+    "unet_get_params": ([_P, _P, _P], _i32),
+    "unet_forward": ([_P, _P, _P, _P], _i32),
+    "unet_backward": ([_P, _P, _P], _i32),
+    "unet_adam_step": ([_P, _f32, _f32, _f32, _f32], _i32),
+    "unet_train_step": ([_P, _P, _P, _P, _P, _i64, _f32, _P], _i32),
+    "unet_predict": ([_P, _P, _P, _P, _f32, ctypes.c_void_p, _P], _i32),
+    "unet_features_buffer": ([_P, ctypes.POINTER(_P), ctypes.POINTER(_P)], _i32),
+    "unet_destroy": ([_P], None),
 }
+
+UNET_TARGET_LOG, UNET_TARGET_CORRECTOR, UNET_TARGET_PLAIN = 0, 1, 2
+
+
+class unet_target(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("kind", _i32), ("eps", _f32), ("cmax", _f32),
+                ("c_in", _f32), ("c_out", _f32), ("depth", _P), ("depth_max", _i32)]
 
 _lib = None
 
@@ -191,8 +215,55 @@ def conv_flops(shape):
     return sum(2 * 27 * cin * cout * vox[level[name[:2]]] for name, cin, cout in layer_specs())
 
 
+def param_count():
+    return int(load().unet_param_count())
+
+
+def param_tensor(t):
+    """(cin, cout, w_offset, w_count, b_offset) of parameter tensor t of the flat array
+    (0..13 the convolutions in forward order, 14 the head)."""
+    cin, cout = _i32(), _i32()
+    wo, wc, bo = _i64(), _i64(), _i64()
+    _call("unet_param_tensor", t, ctypes.byref(cin), ctypes.byref(cout), ctypes.byref(wo), ctypes.byref(wc),
+          ctypes.byref(bo))
+    return cin.value, cout.value, wo.value, wc.value, bo.value
+
+
+class _Handle:
+    """One unet_net handle bound to a torch-owned workspace (a grid and a mode)."""
+
+    def __init__(self, shape, train, device):
+        import torch
+
+        h = _P()
+        _call("unet_create", int(shape[0]), int(shape[1]), int(shape[2]), 1 if train else 0, ctypes.byref(h))
+        self.h = h
+        nb = ctypes.c_size_t()
+        _call("unet_workspace_bytes", self.h, ctypes.byref(nb))
+        self.ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=device)
+        ptr = (self.ws.data_ptr() + 255) // 256 * 256
+        _call("unet_bind", self.h, ptr, nb.value, _stream())
+        self.version = -1
+        self.shape, self.train = tuple(shape), train
+
+    def close(self):
+        if self.h:
+            load().unet_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class UNet:
-    """Parameters (FP32 masters + BF16 copies, Adam moments) and forward/backward."""
+    """The warm-start network of include/unet.h (unet_net): parameters in one flat
+    FP32 device array (``params``; ``W`` and ``B`` are views of it per tensor), and
+    one library handle per grid and mode, created on first use.  Forward, backward,
+    the Adam step and prediction are single ABI calls; this class only allocates
+    the workspaces and keeps the handles' parameters current."""
 
     def __init__(self, device="cuda", seed=0):
         import torch
@@ -200,34 +271,36 @@ class UNet:
         load()
         self.device = torch.device(device)
         self.specs = layer_specs()
+        self.params = torch.zeros(param_count(), dtype=torch.float32, device=self.device)
+        self.W, self.B = {}, {}
+        self._layout = {}
+        for t, (name, cin, cout) in enumerate(self.specs + [("head", LEVELS[0], 1)]):
+            ci, co, wo, wc, bo = param_tensor(t)
+            assert (ci, co) == (cin, cout), (name, ci, co)
+            self._layout[name] = (wo, wc, bo, co)
+            self.W[name] = self.params[wo:wo + wc].view(cout, -1) if name != "head" else self.params[wo:wo + wc]
+            self.B[name] = self.params[bo:bo + co]
         rng = np.random.default_rng(seed)
-        self.W, self.B, self.Wb = {}, {}, {}
+        host = np.zeros(self.params.numel(), np.float32)
         for name, cin, cout in self.specs:
-            kp = unet_kpad(cin)
+            wo, wc, bo, _ = self._layout[name]
+            kp = wc // cout
             w = np.zeros((cout, kp), np.float32)
             w[:, :27 * cin] = rng.normal(0.0, np.sqrt(2.0 / (27 * cin)), (cout, 27 * cin))
-            self.W[name] = torch.from_numpy(w).to(self.device)
-            self.B[name] = torch.zeros(cout, dtype=torch.float32, device=self.device)
+            host[wo:wo + wc] = w.ravel()
         c1 = LEVELS[0]
-        self.W["head"] = torch.from_numpy(rng.normal(0.0, 0.1 / np.sqrt(c1), c1).astype(np.float32)).to(self.device)
-        self.B["head"] = torch.zeros(1, dtype=torch.float32, device=self.device)
-        self._sync_bf16()
-        self.m = {k: torch.zeros_like(v) for k, v in self.W.items()}
-        self.v = {k: torch.zeros_like(v) for k, v in self.W.items()}
-        self.mb = {k: torch.zeros_like(v) for k, v in self.B.items()}
-        self.vb = {k: torch.zeros_like(v) for k, v in self.B.items()}
+        wo, wc, _, _ = self._layout["head"]
+        host[wo:wo + wc] = rng.normal(0.0, 0.1 / np.sqrt(c1), c1).astype(np.float32)
+        self.params.copy_(torch.from_numpy(host))
+        self.version = 0  # bumped whenever the parameters change
         self.t = 0
         self.target_eps = 0.0  # > 0: the network predicts ln(C + target_eps) instead of C
-        self._bufs = None
+        self._handles = {}
 
     # parameters -------------------------------------------------------------
-    def _sync_bf16(self):
-        import torch
-
-        for name, _, _ in self.specs:
-            wb = torch.empty(self.W[name].shape, dtype=torch.bfloat16, device=self.device)
-            unet_to_bf16(self.W[name], wb, wb.numel())
-            self.Wb[name] = wb
+    def touch(self):
+        """Call after changing ``params`` (or a W / B view) in place."""
+        self.version += 1
 
     def state_dict(self):
         d = {f"W_{k}": v.cpu().numpy() for k, v in self.W.items()}
@@ -239,10 +312,10 @@ class UNet:
         import torch
 
         for k in self.W:
-            self.W[k] = torch.from_numpy(np.asarray(d[f"W_{k}"], np.float32)).to(self.device)
-            self.B[k] = torch.from_numpy(np.asarray(d[f"B_{k}"], np.float32)).to(self.device)
+            self.W[k].copy_(torch.from_numpy(np.asarray(d[f"W_{k}"], np.float32).reshape(self.W[k].shape)))
+            self.B[k].copy_(torch.from_numpy(np.asarray(d[f"B_{k}"], np.float32).reshape(self.B[k].shape)))
         self.target_eps = float(d["target_eps"]) if "target_eps" in d else 0.0
-        self._sync_bf16()
+        self.touch()
 
     def save(self, path):
         np.savez(path, **self.state_dict())
@@ -257,130 +330,88 @@ class UNet:
     def n_params(self):
         return sum(int(27 * cin * cout + cout) for _, cin, cout in self.specs) + LEVELS[0] + 1
 
-    # buffers ----------------------------------------------------------------
-    def _alloc(self, shape, train):
+    # handles ----------------------------------------------------------------
+    def handle(self, shape, train=False):
+        """The bound handle for a grid (created on first use) with current parameters."""
         import torch
 
-        key = (tuple(shape), train)
-        if self._bufs is not None and self._bufs["key"] == key:
-            return self._bufs
-        for s in shape:
+        key = (tuple(int(s) for s in shape), bool(train))
+        for s in key[0]:
             if s % 8:
                 raise ValueError("grid sizes must be multiples of 8 (three 2x poolings)")
-        c1, c2, c3, c4 = LEVELS
-        dims = [tuple(shape), tuple(s // 2 for s in shape), tuple(s // 4 for s in shape), tuple(s // 8 for s in shape)]
-        V = [int(np.prod(d)) for d in dims]
-        bf = lambda v, c: torch.zeros((v, c), dtype=torch.bfloat16, device=self.device)  # noqa: E731
-        b = {"key": key, "dims": dims, "V": V,
-             "a1": bf(V[0], c1), "cat1": bf(V[0], c1 + c2), "d1a": bf(V[0], c1), "d1b": bf(V[0], c1),
-             "p2": bf(V[1], c1), "a2": bf(V[1], c2), "cat2": bf(V[1], c2 + c3), "d2a": bf(V[1], c2), "d2b": bf(V[1], c2),
-             "p3": bf(V[2], c2), "a3": bf(V[2], c3), "cat3": bf(V[2], c3 + c4), "d3a": bf(V[2], c3), "d3b": bf(V[2], c3),
-             "p4": bf(V[3], c3), "b4a": bf(V[3], c4), "b4b": bf(V[3], c4),
-             "out": torch.zeros(V[0], dtype=torch.float32, device=self.device)}
-        if train:
-            for k in list(b):
-                if isinstance(b[k], torch.Tensor) and b[k].dtype == torch.bfloat16:
-                    b["g_" + k] = torch.zeros_like(b[k])
-            b["g_out"] = torch.zeros(V[0], dtype=torch.float32, device=self.device)
-            b["wt"] = torch.zeros(max(cin * unet_kpad(cout) for _, cin, cout in self.specs), dtype=torch.bfloat16,
-                                  device=self.device)
-            self.gW = {k: torch.zeros_like(v) for k, v in self.W.items()}
-            self.gB = {k: torch.zeros_like(v) for k, v in self.B.items()}
-            b["loss"] = torch.zeros(1, dtype=torch.float32, device=self.device)
-        self._bufs = b
-        return b
+        h = self._handles.get(key)
+        if h is None:
+            h = _Handle(key[0], key[1], self.device)
+            self._handles[key] = h
+        if h.version != self.version:
+            torch.cuda.current_stream(self.device).synchronize()
+            _call("unet_set_params", h.h, self.params.data_ptr())
+            h.version = self.version
+        return h
 
-    # forward ----------------------------------------------------------------
-    def _conv(self, name, x, ldx, offx, y, ldy, offy, dims, cin, cout, relu=True):
-        unet_conv3d_fwd(x, ldx, offx, self.Wb[name], self.B[name], y, ldy, offy, None, dims, cin, cout, relu)
+    def release(self, shape=None):
+        """Free the handles (of one grid, or all)."""
+        for key in [k for k in self._handles if shape is None or k[0] == tuple(shape)]:
+            self._handles.pop(key).close()
 
-    def forward(self, feat, shape, train=False, base=None):
+    def _pull(self, h):
+        """After an optimiser step on handle h: its parameters are the current ones."""
+        _call("unet_get_params", h.h, self.params.data_ptr(), None)
+        self.version += 1
+        h.version = self.version
+
+    # network ----------------------------------------------------------------
+    def forward(self, feat, shape, train=False, base=None, out=None):
         """feat: (V, 16) BF16 features on `shape`; returns the FP32 prediction (V,)."""
-        b = self._alloc(shape, train)
-        c1, c2, c3, c4 = LEVELS
-        d0, d1, d2, d3 = b["dims"]
-        self._conv("e1a", feat, IN_CH, 0, b["a1"], c1, 0, d0, IN_CH, c1)
-        self._conv("e1b", b["a1"], c1, 0, b["cat1"], c1 + c2, 0, d0, c1, c1)
-        unet_pool_fwd(b["cat1"], c1 + c2, 0, b["p2"], c1, 0, d0, c1)
-        self._conv("e2a", b["p2"], c1, 0, b["a2"], c2, 0, d1, c1, c2)
-        self._conv("e2b", b["a2"], c2, 0, b["cat2"], c2 + c3, 0, d1, c2, c2)
-        unet_pool_fwd(b["cat2"], c2 + c3, 0, b["p3"], c2, 0, d1, c2)
-        self._conv("e3a", b["p3"], c2, 0, b["a3"], c3, 0, d2, c2, c3)
-        self._conv("e3b", b["a3"], c3, 0, b["cat3"], c3 + c4, 0, d2, c3, c3)
-        unet_pool_fwd(b["cat3"], c3 + c4, 0, b["p4"], c3, 0, d2, c3)
-        self._conv("b4a", b["p4"], c3, 0, b["b4a"], c4, 0, d3, c3, c4)
-        self._conv("b4b", b["b4a"], c4, 0, b["b4b"], c4, 0, d3, c4, c4)
-        unet_up_fwd(b["b4b"], c4, 0, b["cat3"], c3 + c4, c3, d2, c4)
-        self._conv("d3a", b["cat3"], c3 + c4, 0, b["d3a"], c3, 0, d2, c3 + c4, c3)
-        self._conv("d3b", b["d3a"], c3, 0, b["d3b"], c3, 0, d2, c3, c3)
-        unet_up_fwd(b["d3b"], c3, 0, b["cat2"], c2 + c3, c2, d1, c3)
-        self._conv("d2a", b["cat2"], c2 + c3, 0, b["d2a"], c2, 0, d1, c2 + c3, c2)
-        self._conv("d2b", b["d2a"], c2, 0, b["d2b"], c2, 0, d1, c2, c2)
-        unet_up_fwd(b["d2b"], c2, 0, b["cat1"], c1 + c2, c1, d0, c2)
-        self._conv("d1a", b["cat1"], c1 + c2, 0, b["d1a"], c1, 0, d0, c1 + c2, c1)
-        self._conv("d1b", b["d1a"], c1, 0, b["d1b"], c1, 0, d0, c1, c1)
-        unet_head_fwd(b["d1b"], c1, self.W["head"], self.B["head"], base, b["out"], b["V"][0], c1)
-        return b["out"]
+        import torch
 
-    # backward ---------------------------------------------------------------
-    def _conv_bwd(self, name, x, ldx, offx, y, ldy, offy, gy, ldg, offg, gx, ldgx, offgx, dims, cin, cout):
-        """gy holds dL/dy (post-ReLU) at [offg, offg+cout); overwritten with dL/dpre.
-        Accumulates weight and bias gradients; writes dL/dx into gx when given."""
-        b = self._bufs
-        nv = int(np.prod(dims))
-        unet_relu_bwd(y, ldy, offy, gy, ldg, offg, nv, cout)
-        unet_conv3d_wgrad(x, ldx, offx, gy, ldg, offg, dims, cin, cout, self.gW[name], self.gB[name])
-        if gx is not None:
-            unet_conv3d_wtrans(self.Wb[name], b["wt"], cin, cout)
-            unet_conv3d_fwd(gy, ldg, offg, b["wt"], None, gx, ldgx, offgx, None, dims, cout, cin, False)
+        h = self.handle(shape, train)
+        if out is None:
+            out = torch.empty(int(np.prod(shape)), dtype=torch.float32, device=self.device)
+        _call("unet_forward", h.h, _ptr(feat), _ptr(base), out.data_ptr())
+        return out
 
-    def backward(self, feat, dout):
-        b = self._bufs
-        c1, c2, c3, c4 = LEVELS
-        d0, d1, d2, d3 = b["dims"]
-        for k in self.gW:
-            unet_zero(self.gW[k])
-            unet_zero(self.gB[k])
-        for k in ("g_cat1", "g_cat2", "g_cat3"):
-            unet_zero(b[k])
-        unet_head_bwd(b["d1b"], c1, self.W["head"], dout, b["g_d1b"], self.gW["head"], self.gB["head"], b["V"][0], c1)
-        self._conv_bwd("d1b", b["d1a"], c1, 0, b["d1b"], c1, 0, b["g_d1b"], c1, 0, b["g_d1a"], c1, 0, d0, c1, c1)
-        self._conv_bwd("d1a", b["cat1"], c1 + c2, 0, b["d1a"], c1, 0, b["g_d1a"], c1, 0, b["g_cat1"], c1 + c2, 0, d0,
-                       c1 + c2, c1)
-        unet_up_bwd(b["g_cat1"], c1 + c2, c1, b["g_d2b"], c2, 0, d0, c2)
-        self._conv_bwd("d2b", b["d2a"], c2, 0, b["d2b"], c2, 0, b["g_d2b"], c2, 0, b["g_d2a"], c2, 0, d1, c2, c2)
-        self._conv_bwd("d2a", b["cat2"], c2 + c3, 0, b["d2a"], c2, 0, b["g_d2a"], c2, 0, b["g_cat2"], c2 + c3, 0, d1,
-                       c2 + c3, c2)
-        unet_up_bwd(b["g_cat2"], c2 + c3, c2, b["g_d3b"], c3, 0, d1, c3)
-        self._conv_bwd("d3b", b["d3a"], c3, 0, b["d3b"], c3, 0, b["g_d3b"], c3, 0, b["g_d3a"], c3, 0, d2, c3, c3)
-        self._conv_bwd("d3a", b["cat3"], c3 + c4, 0, b["d3a"], c3, 0, b["g_d3a"], c3, 0, b["g_cat3"], c3 + c4, 0, d2,
-                       c3 + c4, c3)
-        unet_up_bwd(b["g_cat3"], c3 + c4, c3, b["g_b4b"], c4, 0, d2, c4)
-        self._conv_bwd("b4b", b["b4a"], c4, 0, b["b4b"], c4, 0, b["g_b4b"], c4, 0, b["g_b4a"], c4, 0, d3, c4, c4)
-        self._conv_bwd("b4a", b["p4"], c3, 0, b["b4a"], c4, 0, b["g_b4a"], c4, 0, b["g_p4"], c3, 0, d3, c3, c4)
-        unet_pool_bwd(b["g_p4"], c3, 0, b["g_cat3"], c3 + c4, 0, d2, c3)
-        self._conv_bwd("e3b", b["a3"], c3, 0, b["cat3"], c3 + c4, 0, b["g_cat3"], c3 + c4, 0, b["g_a3"], c3, 0, d2, c3, c3)
-        self._conv_bwd("e3a", b["p3"], c2, 0, b["a3"], c3, 0, b["g_a3"], c3, 0, b["g_p3"], c2, 0, d2, c2, c3)
-        unet_pool_bwd(b["g_p3"], c2, 0, b["g_cat2"], c2 + c3, 0, d1, c2)
-        self._conv_bwd("e2b", b["a2"], c2, 0, b["cat2"], c2 + c3, 0, b["g_cat2"], c2 + c3, 0, b["g_a2"], c2, 0, d1, c2, c2)
-        self._conv_bwd("e2a", b["p2"], c1, 0, b["a2"], c2, 0, b["g_a2"], c2, 0, b["g_p2"], c1, 0, d1, c1, c2)
-        unet_pool_bwd(b["g_p2"], c1, 0, b["g_cat1"], c1 + c2, 0, d0, c1)
-        self._conv_bwd("e1b", b["a1"], c1, 0, b["cat1"], c1 + c2, 0, b["g_cat1"], c1 + c2, 0, b["g_a1"], c1, 0, d0, c1, c1)
-        self._conv_bwd("e1a", feat, IN_CH, 0, b["a1"], c1, 0, b["g_a1"], c1, 0, None, 0, 0, d0, IN_CH, c1)
+    def backward(self, feat, dout, shape):
+        """Parameter gradients for dout (FP32 per voxel) after forward(train=True)."""
+        h = self.handle(shape, True)
+        _call("unet_backward", h.h, _ptr(feat), dout.data_ptr())
 
-    def adam_step(self, lr, b1=0.9, b2=0.999, eps=1e-8):
+    def grads(self, shape):
+        """The flat FP32 parameter gradients of the last backward (a new tensor)."""
+        import torch
+
+        g = torch.empty_like(self.params)
+        _call("unet_get_params", self.handle(shape, True).h, None, g.data_ptr())
+        return g
+
+    def adam_step(self, shape, lr, b1=0.9, b2=0.999, eps=1e-8):
+        h = self.handle(shape, True)
+        _call("unet_adam_step", h.h, lr, b1, b2, eps)
         self.t += 1
-        for k in self.W:
-            wb = self.Wb.get(k)
-            unet_adam(self.W[k], self.m[k], self.v[k], self.gW[k], wb, self.W[k].numel(), lr, b1, b2, eps, self.t)
-            unet_adam(self.B[k], self.mb[k], self.vb[k], self.gB[k], None, self.B[k].numel(), lr, b1, b2, eps, self.t)
+        self._pull(h)
 
     def train_step(self, feat, shape, target, mask, count, lr, weight=None):
-        """One Adam step on the (weighted) masked MSE between the prediction and target."""
-        b = self._alloc(shape, True)
-        pred = self.forward(feat, shape, train=True)
-        unet_zero(b["loss"])
-        unet_mse(pred, target, mask, b["g_out"], b["loss"], b["V"][0], count, weight)
-        self.backward(feat, b["g_out"])
-        self.adam_step(lr)
-        return b["loss"]
+        """One Adam step on the (weighted) masked MSE between the prediction and target;
+        returns the loss (a one-element device tensor, before the step)."""
+        import torch
+
+        h = self.handle(shape, True)
+        loss = torch.zeros(1, dtype=torch.float32, device=self.device)
+        _call("unet_train_step", h.h, _ptr(feat), target.data_ptr(), mask.data_ptr(), _ptr(weight), int(count), lr,
+              loss.data_ptr())
+        self.t += 1
+        self._pull(h)
+        return loss
+
+    def predict(self, active, n_cat, omega, tau_ref, target):
+        """Start field (FP32 dense tensor on the grid of ``active``) from the solver's
+        dense device fields; ``target`` is a unet_target."""
+        import torch
+
+        shape = tuple(active.shape)
+        h = self.handle(shape, False)
+        c = torch.empty(shape, dtype=torch.float32, device=self.device)
+        target.struct_size = ctypes.sizeof(unet_target)
+        _call("unet_predict", h.h, active.data_ptr(), _ptr(n_cat), omega.data_ptr(), tau_ref,
+              ctypes.addressof(target), c.data_ptr())
+        return c

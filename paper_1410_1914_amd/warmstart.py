@@ -123,26 +123,26 @@ def features(w: Workload, active, ncat, omega, tau_ref=1.0):
 
 
 def predict(net, w: Workload, active, ncat, omega, depth=None, depth_max=None):
-    """Start field for the solver (FP32, dense simulated grid, on the GPU).
+    """Start field for the solver (FP32, dense simulated grid, on the GPU), by one
+    unet_predict call on the solver's dense fields.
 
     ``react``: the predicted steady concentration; when the pore-depth map is given,
     the cold value 0 in voxels deeper than depth_max. ``deff``: the linear profile
     plus the predicted corrector."""
     import torch
 
-    feat, _ = features(w, active, ncat, omega)
-    out = net.forward(feat, active.shape)
-    c = torch.empty(out.numel(), dtype=torch.float32, device=out.device)
+    a = torch.from_numpy(np.ascontiguousarray(active)).cuda()
+    o = torch.from_numpy(np.ascontiguousarray(omega)).cuda()
+    n = torch.from_numpy(np.ascontiguousarray(ncat)).cuda() if w.mode == lbm.MODE_REACT else None
+    d = torch.from_numpy(np.ascontiguousarray(depth)).cuda() if depth is not None else None
     if w.target == "corrector":
         p = params(w)
-        unet.unet_corrector_map(out, c, out.numel(), active.shape[2], p.c_in, p.c_out, True, C_MAX)
-    elif depth is not None:
-        d = torch.from_numpy(np.ascontiguousarray(depth)).to(out.device)
-        dm = w.depth_max if depth_max is None else depth_max
-        unet.unet_start_field(out, d, dm, w.target_eps, C_MAX, c, out.numel())
+        tgt = unet.unet_target(kind=unet.UNET_TARGET_CORRECTOR, eps=1.0, cmax=C_MAX, c_in=p.c_in, c_out=p.c_out)
     else:
-        unet.unet_log_map(out, c, out.numel(), w.target_eps, True, C_MAX)
-    return c.view(active.shape)
+        tgt = unet.unet_target(kind=unet.UNET_TARGET_LOG, eps=w.target_eps, cmax=C_MAX,
+                               depth=d.data_ptr() if d is not None else None,
+                               depth_max=w.depth_max if depth_max is None else depth_max)
+    return net.predict(a, n, o, 1.0, tgt)
 
 
 # ------------------------------------------------------------------ solves
@@ -164,6 +164,7 @@ def solve(solver, w: Workload, c0=None, fallback=True, chunk=0, log=None):
     solver.set_initial_concentration(c0)
     K = solver.params.check_every
     used_fallback = False
+    spent = 0  # steps taken from a rejected start (they count against it)
     if c0 is not None and fallback and not bool(torch.isfinite(c0).all()):
         used_fallback = True
         solver.set_initial_concentration(None)
@@ -172,6 +173,7 @@ def solve(solver, w: Workload, c0=None, fallback=True, chunk=0, log=None):
         st, i2 = solver.advance(K)
         if st != lbm.OK and i2.residual > i1.residual:
             used_fallback = True
+            spent = int(i2.steps)
             solver.set_initial_concentration(None)
     if chunk > 0:
         while True:
@@ -184,8 +186,8 @@ def solve(solver, w: Workload, c0=None, fallback=True, chunk=0, log=None):
     else:
         st, info = solver.run_to_steady()
     torch.cuda.synchronize()
-    return {"status": st, "steps": int(info.steps), "wall_s": time.perf_counter() - t0, "out": _output(solver, w),
-            "fallback": used_fallback}
+    return {"status": st, "steps": int(info.steps) + spent, "wall_s": time.perf_counter() - t0,
+            "out": _output(solver, w), "fallback": used_fallback, "steps_before_fallback": spent}
 
 
 # ------------------------------------------------------------------ training data
@@ -258,6 +260,7 @@ def train(net, w: Workload, data, epochs=4, lr=1e-3, log=print, seed=0, weight_p
     if net.t == 0:  # start the output bias at the mean target
         m = float(np.mean([float(d["y"][d["active"].view(-1) > 0].mean()) for d in data[:32]]))
         net.B["head"].fill_(m)
+        net.touch()
     net.target_eps = w.target_eps
     step = 0
     for ep in range(epochs):

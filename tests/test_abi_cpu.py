@@ -345,3 +345,50 @@ def test_coupled_entry_points_on_the_host():
     u8 = dry.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
     assert create(lbm.lbm_params_default(mode=lbm.MODE_REACT), c)[0] == lbm.ERR_NO_PERCOLATION
     L.lbm19_coupled_destroy(None)
+
+
+def test_unet_library_exports_every_declared_symbol():
+    from paper_1410_1914_amd import unet
+
+    lib = unet.load()
+    names = _declared("unet.h")
+    assert len(names) >= 30
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(unet.SIGNATURES)
+
+
+def test_unet_handle_layout_on_the_host():
+    """unet_create and the parameter layout need no device: sizes that are not
+    multiples of 8 are refused, the flat parameter array holds every tensor in
+    forward order without overlap, and a training handle needs more workspace."""
+    import ctypes
+
+    from paper_1410_1914_amd import unet
+
+    lib = unet.load()
+    h = ctypes.c_void_p()
+    for bad in ((12, 16, 16), (0, 8, 8), (8, 8, -8)):
+        assert lib.unet_create(*bad, 0, ctypes.byref(h)) == -1
+    assert lib.unet_create(8, 8, 8, 0, None) == -1
+    total = unet.param_count()
+    end = 0
+    for t, (name, cin, cout) in enumerate(unet.layer_specs() + [("head", unet.LEVELS[0], 1)]):
+        ci, co, wo, wc, bo = unet.param_tensor(t)
+        assert (ci, co) == (cin, cout), name
+        assert wo >= end and bo >= wo + wc and wo % 64 == 0
+        assert wc == (co * unet.unet_kpad(ci) if name != "head" else unet.LEVELS[0])
+        end = bo + co
+    assert end <= total
+    assert lib.unet_param_tensor(15, None, None, None, None, None) == -1
+    sizes = []
+    for train in (0, 1):
+        assert lib.unet_create(16, 16, 24, train, ctypes.byref(h)) == 0
+        nb = ctypes.c_size_t()
+        assert lib.unet_workspace_bytes(h, ctypes.byref(nb)) == 0
+        sizes.append(nb.value)
+        # an unbound handle refuses work
+        assert lib.unet_forward(h, None, None, None) == -1
+        lib.unet_destroy(h)
+    assert sizes[1] > sizes[0] > 16 * 16 * 24 * 16 * 2
+    lib.unet_destroy(None)

@@ -241,9 +241,23 @@ def test_features(U):
     assert np.allclose(_host(wt), np.where(act, np.minimum(3.0, 1 / drel), 0), rtol=1e-5)
 
 
+def _oracle_params(net):
+    """The network's parameters as the FP64 oracle network takes them (convolution
+    weights rounded to BF16, as the kernels read them)."""
+    import torch
+
+    P = {}
+    for name, cin, cout in net.specs:
+        wb = net.W[name].to(torch.bfloat16).to(torch.float64).cpu().numpy()[:, :27 * cin].reshape(cout, 27, cin)
+        P[name] = (wb, net.B[name].cpu().numpy().astype(np.float64))
+    P["head"] = (net.W["head"].cpu().numpy().astype(np.float64), float(net.B["head"].cpu().numpy()[0]))
+    return P
+
+
 def test_network_gradient_matches_finite_differences(U):
-    """The whole backward pass of the BF16 network against FP64 finite differences
-    of the oracle network along two directions per layer checked."""
+    """The whole backward pass of the BF16 network (unet_forward, unet_backward of
+    one library handle) against FP64 finite differences of the oracle network along
+    two directions per layer checked."""
     import torch
 
     rng = np.random.default_rng(1)
@@ -255,22 +269,15 @@ def test_network_gradient_matches_finite_differences(U):
     mask = (rng.random(shape) < 0.7).astype(np.uint8)
     count = int(mask.sum())
     fd_t = _dev_bf16(feat.reshape(-1, 16))
-    b = net._alloc(shape, True)
     pred = net.forward(fd_t, shape, train=True)
     loss = torch.zeros(1, dtype=torch.float32, device="cuda")
-    U.unet_mse(pred, _dev_f32(target.ravel()), torch.tensor(mask.ravel()).cuda(), b["g_out"], loss, pred.numel(), count)
-    net.backward(fd_t, b["g_out"])
+    g_out = torch.zeros(pred.numel(), dtype=torch.float32, device="cuda")
+    U.unet_mse(pred, _dev_f32(target.ravel()), torch.tensor(mask.ravel()).cuda(), g_out, loss, pred.numel(), count)
+    net.backward(fd_t, g_out, shape)
+    grads = net.grads(shape)
     torch.cuda.synchronize()
 
-    def params():
-        P = {}
-        for name, cin, cout in net.specs:
-            wb = net.Wb[name].to(torch.float64).cpu().numpy()[:, :27 * cin].reshape(cout, 27, cin)
-            P[name] = (wb, net.B[name].cpu().numpy().astype(np.float64))
-        P["head"] = (net.W["head"].cpu().numpy().astype(np.float64), float(net.B["head"].cpu().numpy()[0]))
-        return P
-
-    P = params()
+    P = _oracle_params(net)
     ref_pred = C.unet_forward(P, feat)
     assert np.allclose(_host(pred).reshape(shape), ref_pred, rtol=5e-2, atol=5e-2 * np.abs(ref_pred).max())
 
@@ -279,7 +286,9 @@ def test_network_gradient_matches_finite_differences(U):
 
     for name in ("e1a", "e2b", "b4b", "d3a", "d1b"):
         cin = dict((n, c) for n, c, _ in net.specs)[name]
-        g = net.gW[name].cpu().numpy().astype(np.float64)[:, :27 * cin].reshape(P[name][0].shape)
+        wo, wc, bo, cout = net._layout[name]
+        g = grads[wo:wo + wc].view(cout, -1).cpu().numpy().astype(np.float64)[:, :27 * cin]
+        g = g.reshape(P[name][0].shape)
         for d in (g / np.linalg.norm(g), rng.standard_normal(g.shape)):
             d = d / np.linalg.norm(d)
             eps = 1e-3
@@ -290,6 +299,88 @@ def test_network_gradient_matches_finite_differences(U):
             fd = (L(Pp) - L(Pm)) / (2 * eps)
             an = float(np.sum(g * d))
             assert an == pytest.approx(fd, rel=0.15, abs=0.05 * np.linalg.norm(g)), (name, an, fd)
+
+
+def test_network_forward_matches_the_oracle_network(U):
+    """unet_forward of a 16 x 24 x 32 handle (three poolings, every level ragged in
+    channels and sizes) against the FP64 oracle network on the same BF16 inputs and
+    weights; the handle's own buffers (unet_features_buffer) give the same result."""
+    import torch
+
+    rng = np.random.default_rng(21)
+    shape = (16, 24, 32)
+    net = U.UNet(seed=5)
+    net.B["e2a"].copy_(torch.linspace(-0.1, 0.1, 32))  # nonzero biases reach the output
+    net.B["head"].fill_(0.25)
+    net.touch()
+    feat = _bf(rng, *shape, 16)
+    base = rng.standard_normal(shape).astype(np.float32)
+    out = net.forward(_dev_bf16(feat.reshape(-1, 16)), shape, base=_dev_f32(base.ravel()))
+    ref = C.unet_forward(_oracle_params(net), feat) + base
+    err = np.abs(_host(out).reshape(shape) - ref).max()
+    assert err < 2e-2 * np.abs(ref).max(), err
+
+
+def test_predict_is_features_forward_and_inverse_target(U):
+    """unet_predict on device solver fields equals unet_features + unet_forward +
+    the inverse target map called one by one, for the log target with and without
+    a depth mask and for the corrector target."""
+    import torch
+
+    rng = np.random.default_rng(22)
+    shape = (8, 16, 24)
+    act = (rng.random(shape) < 0.6).astype(np.uint8)
+    ncat = np.where(act, rng.integers(0, 4, shape), 0).astype(np.uint8)
+    tau = np.where(act, 0.5 + 0.5 * 10 ** rng.uniform(-3, 0, shape), 1.0)
+    om = np.where(act, 1.0 / tau, 0.0).astype(np.float32)
+    depth = rng.integers(0, 8, shape).astype(np.uint8)
+    a, n, o, d = (torch.tensor(v).cuda() for v in (act, ncat, om, depth))
+    net = U.UNet(seed=6)
+    feat = torch.empty((int(np.prod(shape)), 16), dtype=torch.bfloat16, device="cuda")
+    U.unet_features(a, n, o, 1.0, feat, shape)
+    y = net.forward(feat, shape)
+    V = y.numel()
+    for kind, dep in ((U.UNET_TARGET_LOG, None), (U.UNET_TARGET_LOG, d), (U.UNET_TARGET_CORRECTOR, None)):
+        tgt = U.unet_target(kind=kind, eps=1e-3, cmax=1.5, c_in=1.0, c_out=0.0,
+                            depth=dep.data_ptr() if dep is not None else None, depth_max=3)
+        got = net.predict(a, n, o, 1.0, tgt)
+        want = torch.empty(V, dtype=torch.float32, device="cuda")
+        if kind == U.UNET_TARGET_CORRECTOR:
+            U.unet_corrector_map(y, want, V, shape[2], 1.0, 0.0, True, 1.5)
+        elif dep is not None:
+            U.unet_start_field(y, dep, 3, 1e-3, 1.5, want, V)
+        else:
+            U.unet_log_map(y, want, V, 1e-3, True, 1.5)
+        torch.cuda.synchronize()
+        assert torch.equal(got.view(-1), want), kind
+
+
+def test_train_step_is_forward_backward_adam(U):
+    """unet_train_step equals unet_forward, unet_mse, unet_backward and
+    unet_adam_step called one by one (two networks from the same parameters)."""
+    import torch
+
+    rng = np.random.default_rng(23)
+    shape = (8, 8, 16)
+    feat = _dev_bf16(_bf(rng, *shape, 16).reshape(-1, 16))
+    target = _dev_f32(rng.standard_normal(int(np.prod(shape))) * 0.1)
+    mask = torch.tensor((rng.random(int(np.prod(shape))) < 0.8).astype(np.uint8)).cuda()
+    count = int(mask.sum())
+    a, b = U.UNet(seed=7), U.UNet(seed=7)
+    for step in range(2):
+        la = a.train_step(feat, shape, target, mask, count, 1e-3)
+        pred = b.forward(feat, shape, train=True)
+        lb = torch.zeros(1, dtype=torch.float32, device="cuda")
+        g = torch.zeros_like(pred)
+        U.unet_mse(pred, target, mask, g, lb, pred.numel(), count)
+        b.backward(feat, g, shape)
+        b.adam_step(shape, 1e-3)
+        torch.cuda.synchronize()
+        assert torch.equal(la, lb), step
+        assert torch.equal(a.params, b.params), step
+    assert a.t == b.t == 2
+    # a step moved the parameters
+    assert not torch.equal(a.params, U.UNet(seed=7).params)
 
 
 def test_log_map_round_trip(U):
