@@ -22,11 +22,13 @@ Also reported on the same JSON line:
     sequential single solves vs one batched solve, with the error against the
     stored oracle values;
   * warm_start: learned start vs cold start (C = 0) and vs a linear-profile start
-    on fresh Pt catalyst layers, when the trained networks exist: the reactive
-    problem at 192^3 and the effective-diffusivity problem at 96^3 (at 192^3, whose
-    cold solve alone takes ~2.5 M steps, with ``--warm-deff``);
-  * batch64 (``--batch64``): 64 uneven reactive structures, one batched solve vs
-    64 sequential single solves.
+    on a fresh 192^3 Pt catalyst layer (seed 20000), when the trained networks
+    exist: the effective-diffusivity problem (cold solve ~2.5 M steps) and the
+    reactive problem;
+  * batch64: 64 uneven reactive structures (edges 48..160), one batched solve vs
+    64 sequential single solves;
+  * skipped: optional legs left out because their estimated time did not fit in
+    the wall-clock budget (--budget, default 540 s).
 """
 from __future__ import annotations
 
@@ -57,15 +59,15 @@ def parse():
     ap.add_argument("--no-charz", action="store_true", help="skip the device structure-characterisation leg")
     ap.add_argument("--no-d3q19", action="store_true", help="skip the D3Q19 (paper's lattice) leg")
     ap.add_argument("--coupled", action="store_true", help="add the coupled O2 / proton-potential leg")
-    ap.add_argument("--warm-deff", action="store_true",
-                    help="run the effective-diffusivity warm-start comparison at 192^3 instead of 96^3 (several minutes)")
+    ap.add_argument("--no-batch64", action="store_true", help="skip the 64-structure batch leg")
+    ap.add_argument("--budget", type=float, default=540.0,
+                    help="wall-clock seconds for the whole run: an optional leg whose estimated time would not fit "
+                         "in what is left is skipped and listed under 'skipped'")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU time budget of the oracle sample")
     ap.add_argument("--no-tune", action="store_true", help="keep the default tiling (no autotuning)")
     ap.add_argument("--tiling", default=None,
                     help="segments/wave,waves/workgroup,xcd: use this one-step launch instead of autotuning "
                          "(profiles pin the form the autotuner keeps at 256^3: 1,1,1)")
-    ap.add_argument("--batch64", action="store_true",
-                    help="also time the uneven 64-structure reactive batch: batched vs sequential solves")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--batch-max-edge", type=int, default=None)
     ap.add_argument("--copy-probe", action="store_true",
@@ -421,17 +423,24 @@ def batch64_leg(lbm, insts):
             "fluid_updates_single": int(updates), "fluid_updates_batched": int(b_updates)}
 
 
-def warm_leg(args):
-    """Learned start vs cold start (and vs a linear-profile start): the reactive
-    workload at 192^3, and the effective-diffusivity workload at 96^3, or at 192^3
-    (cold solve alone ~2.5 M steps, minutes) with --warm-deff."""
+def warm_leg(name, seeds=(20000,)):
+    """Learned start vs cold start (C = 0) and vs a linear-profile start on fresh
+    192^3 Pt catalyst layers: ``deff`` the effective-diffusivity problem (cold solve
+    ~2.5 M steps), ``react`` the reactive one."""
     from paper_1410_1914_amd import warmstart
 
-    shapes = {} if args.warm_deff else {"deff": (96, 96, 96)}
-    return warmstart.bench_warm_vs_cold(("react", "deff"), shapes)
+    w = warmstart.bench_warm_vs_cold((name,), None, {name: tuple(seeds)})
+    return w[name] if w else None
+
+
+# Estimated wall time of the optional legs (seconds) at the reference stream-collide
+# rate of 126 us per 256^3 step, scaled by the rate measured in the run.
+LEG_SECONDS = {"cpu_baseline": 5.0, "characterise": 8.0, "d3q19": 8.0, "solves": 6.0, "warm_deff": 335.0,
+               "batch64": 215.0, "warm_react": 40.0}
 
 
 def main():
+    t_start = time.perf_counter()
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver has no multi-GPU path.",
@@ -451,7 +460,8 @@ def main():
     import structgen
     from paper_1410_1914_amd import lbm
 
-    insts = batch64_structures(args) if args.batch64 else None  # host work before the GPU is touched
+    # host work before the GPU is touched
+    insts = batch64_structures(args) if not args.no_batch64 else None
     lbm.require_gpu()
     head, ph = headline(args, lbm, structgen)
     out = {
@@ -475,26 +485,50 @@ def main():
         "other_form": head["other_form"],
         "prep_s": head["prep_s"],
     }
-    if not args.no_cpu:
+    # optional legs, in order, each only when its estimated time fits in the budget
+    speed = head["roofline"]["mean_launch_us"] / 126.0 if args.n == 256 else 1.0
+    skipped = []
+
+    def fits(leg, extra=0.0):
+        est = LEG_SECONDS[leg] * (speed if leg.startswith(("warm", "batch")) else 1.0) + extra
+        left = args.budget - (time.perf_counter() - t_start)
+        if est <= left:
+            return True
+        skipped.append({"leg": leg, "estimated_s": round(est), "left_s": round(left)})
+        log(f"[bench] skipping {leg}: estimated {est:.0f}s, {left:.0f}s of the budget left")
+        return False
+
+    if not args.no_cpu and fits("cpu_baseline", args.cpu_seconds):
         log("[bench] CPU oracle baseline ...")
         out["cpu_baseline"] = cpu_baseline(args, ph, structgen)
-    if not args.no_charz:
+    if not args.no_charz and fits("characterise"):
         out["characterise"] = charz_leg(lbm, ph)
-    if not args.no_d3q19:
+    if not args.no_d3q19 and fits("d3q19"):
         out["d3q19"] = d3q19_leg(lbm, ph, args)
     if args.coupled:
         out["coupled"] = coupled_leg(lbm, structgen)
     del ph
-    if not args.no_solves:
+    if not args.no_solves and fits("solves"):
         log("[bench] 32^3 solves/s legs ...")
         out["solves"] = solves_leg(lbm, structgen)
-    if insts is not None:
+    warm = {}
+    if not args.no_warm and fits("warm_deff"):
+        log("[bench] warm start, effective diffusivity at 192^3 ...")
+        r = warm_leg("deff")
+        if r is not None:
+            warm["deff"] = r
+    if insts is not None and fits("batch64"):
         log("[bench] 64-structure batch leg ...")
         out["batch64"] = batch64_leg(lbm, insts)
-    if not args.no_warm:
-        w = warm_leg(args)
-        if w is not None:
-            out["warm_start"] = w
+    if not args.no_warm and fits("warm_react"):
+        log("[bench] warm start, reactive at 192^3 ...")
+        r = warm_leg("react")
+        if r is not None:
+            warm["react"] = r
+    if warm:
+        out["warm_start"] = warm
+    out["skipped"] = skipped
+    out["wall_s"] = round(time.perf_counter() - t_start, 1)
     print(json.dumps(out), flush=True)
 
 

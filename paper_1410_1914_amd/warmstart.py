@@ -350,19 +350,19 @@ def compare(net, w: Workload, seeds, shape=None, log=print, unmasked=True):
     return summ
 
 
-def bench_warm_vs_cold(names=("react", "deff"), shapes=None):
-    """Leg of bench.py: every named workload whose trained weights are present (two
-    test structures for the reactive one, one for the slow effective-diffusivity one),
-    on its test grid unless ``shapes`` names another for it."""
-    seeds = {"react": (20000, 20001), "deff": (20000,)}
+def bench_warm_vs_cold(names=("react", "deff"), shapes=None, seeds=None):
+    """Leg of bench.py: every named workload whose trained weights are present, on
+    its test grid (192^3) unless ``shapes`` names another for it, on the test
+    structures ``seeds`` names for it (default: seed 20000)."""
     out = {}
     for name in names:
         w = WORKLOADS[name]
         if not os.path.exists(w.weights):
             continue
         net = unet.UNet.from_file(w.weights)
-        out[name] = compare(net, w, seeds[name], shape=(shapes or {}).get(name),
+        out[name] = compare(net, w, (seeds or {}).get(name, (20000,)), shape=(shapes or {}).get(name),
                             log=lambda *a: print(*a, file=sys.stderr, flush=True), unmasked=False)
+        net.release()
     return out or None
 
 
