@@ -135,6 +135,24 @@ int lbm_params_default(lbm_params *p);
  * success *out receives a new handle.  Errors: INVALID_ARG, BAD_PHASE, UNSTABLE. */
 int lbm_create(const lbm_grid *g, const uint8_t *phase_host, const lbm_params *p, lbm_solver **out);
 
+/* lbm_create with the device's share of the preprocessing: the two steps whose
+ * cost grows with the voxel count, the 13-direction pore size (Section 2.1.3) and
+ * the reach of the transport phases from the Dirichlet faces, run on the current
+ * device (as lbm_pore_size_device and lbm_reach_device) instead of the host.  Every
+ * other step, and every result (the handle's host fields included), is that of
+ * lbm_create, bit for bit.  scratch_dev: caller-owned device memory of at least
+ * lbm_prep_scratch_bytes bytes, 256-byte aligned, free for other use again when
+ * the call returns; stream: a hipStream_t (NULL: the null stream), synchronised
+ * before the call returns.  Errors: those of lbm_create, LBM_ERR_WORKSPACE for a
+ * missing, small or misaligned scratch, LBM_ERR_HIP for a failed device call.
+ * lbm_batch_create_device is the same for lbm_batch_create: instances are
+ * prepared on parallel host threads that take turns on the device.
+ * lbm_prep_scratch_bytes: the scratch these calls need for n structures (the
+ * largest instance's: about 10 bytes per voxel). */
+int lbm_prep_scratch_bytes(int32_t n, const lbm_grid *grids, const lbm_params *params, size_t *bytes);
+int lbm_create_device(const lbm_grid *g, const uint8_t *phase_host, const lbm_params *p, void *scratch_dev,
+                      size_t scratch_bytes, void *stream, lbm_solver **out);
+
 /* Sizes and reference values of a created solver. */
 int lbm_get_info(const lbm_solver *s, lbm_info *info);
 
@@ -252,6 +270,10 @@ const char *lbm_last_error(void);
 /* n >= 1 structures; grids[i], phases_host[i] (nz*ny*nx bytes), params[i]. */
 int lbm_batch_create(int32_t n, const lbm_grid *grids, const uint8_t *const *phases_host,
                      const lbm_params *params, lbm_batch **out);
+/* lbm_batch_create with the device's share of the preprocessing (see lbm_create_device). */
+int lbm_batch_create_device(int32_t n, const lbm_grid *grids, const uint8_t *const *phases_host,
+                            const lbm_params *params, void *scratch_dev, size_t scratch_bytes, void *stream,
+                            lbm_batch **out);
 int lbm_batch_workspace_bytes(const lbm_batch *b, size_t *bytes);
 int lbm_batch_bind(lbm_batch *b, void *workspace_dev, size_t bytes, void *hip_stream);
 /* Tiling chosen by lbm_batch_autotune (or set explicitly): segments per wave
@@ -416,7 +438,16 @@ void lbm19_destroy(lbm19_solver *s);
  *
  * lbm_coupling_default: k_ref 1e-2, beta 21.3 1/V (alpha F / R T at alpha 0.61,
  *   333 K), gamma 1e-3 V, phi_m = phi_ref = 0.6 V, tau_phi 1, theta 0.5,
- *   tol_phi 1e-6 V, max_iter 200.
+ *   tol_phi 1e-6 V, max_iter 200, potential_solver 0.
+ * Potential solves: at tau_phi = 1 every post-collision population of the
+ *   potential lattice is a_i u with u = phi + S, so its steady state is the
+ *   solution of sum_links a_i (u(x) - u(x - c_i)) + sum_open 2 a_i (u(x) - phi_m)
+ *   = S(x) (links to simulated voxels; open links at the membrane face).  With
+ *   potential_solver 0 that symmetric positive definite system is solved on the
+ *   device by Jacobi-preconditioned conjugate gradients in FP64 to a residual of
+ *   1e-12 of the right-hand side, starting from the previous iterate, and the
+ *   lattice is set to the equilibrium a_i u, followed by one measured step; with
+ *   1 (or tau_phi != 1) the lattice steps to its own stop rule.
  * lbm19_coupled_create: LBM_ERR_INVALID_ARG for NULL pointers, a struct_size
  *   mismatch, k_ref <= 0, beta < 0, gamma < 0, tau_phi <= 1/2, theta outside
  *   (0, 1], tol_phi <= 0, max_iter < 1, a mode other than LBM_MODE_REACT or
@@ -443,6 +474,10 @@ typedef struct {
     double theta;         /* Picard under-relaxation, (0, 1]                     */
     double tol_phi;       /* stop when phi changes by less than this, V          */
     int32_t max_iter;
+    int32_t potential_solver; /* 0: at tau_phi = 1 the potential's steady state by
+                                 conjugate gradients on its exact equivalent (the
+                                 D3Q19 link Laplacian), else by stepping; 1: always
+                                 by stepping the potential lattice                */
 } lbm_coupling;
 
 typedef struct {
@@ -453,6 +488,7 @@ typedef struct {
     double source;        /* proton source per unit area (sum q / A)             */
     double proton_in;     /* current in through the membrane face, per area      */
     int64_t o2_steps, phi_steps;
+    int64_t phi_cg_iterations; /* conjugate-gradient iterations of all potential solves */
 } lbm_coupled_info;
 
 typedef struct lbm19_coupled lbm19_coupled;

@@ -725,7 +725,7 @@ int hip_status_at(hipError_t e, const char *where) {
 #define hip_status(e) hip_status_at((e), __func__)
 
 int make_engine(int n, const lbm_grid *grids, const uint8_t *const *phases, const lbm_params *params,
-                std::unique_ptr<Engine> &out) {
+                std::unique_ptr<Engine> &out, const DeviceAssist *dev = nullptr) {
     if (n <= 0 || n > 65535 || !grids || !phases || !params) return LBM_ERR_INVALID_ARG;
     auto E = std::make_unique<Engine>();
     E->ninst = n;
@@ -737,7 +737,7 @@ int make_engine(int n, const lbm_grid *grids, const uint8_t *const *phases, cons
     const int nth = std::max(1, std::min<int>(n, (int)std::thread::hardware_concurrency()));
     std::atomic<int> next{0};
     auto work = [&]() {
-        for (int i = next++; i < n; i = next++) st[i] = prepare(grids[i], phases[i], params[i], E->P[i]);
+        for (int i = next++; i < n; i = next++) st[i] = prepare(grids[i], phases[i], params[i], E->P[i], dev);
     };
     std::vector<std::thread> pool;
     for (int t = 1; t < nth; ++t) pool.emplace_back(work);
@@ -822,6 +822,61 @@ int lbm_create(const lbm_grid *g, const uint8_t *phase, const lbm_params *p, lbm
     auto *s = new lbm_solver;
     s->E = std::move(E);
     *out = s;
+    return LBM_OK;
+    LBM_GUARD_END
+}
+
+int lbm_prep_scratch_bytes(int32_t n, const lbm_grid *grids, const lbm_params *params, size_t *bytes) {
+    if (n <= 0 || !grids || !params || !bytes) return LBM_ERR_INVALID_ARG;
+    size_t b = 0;
+    for (int i = 0; i < n; ++i) {
+        if (grids[i].nx <= 0 || grids[i].ny <= 0 || grids[i].nz <= 0) return LBM_ERR_INVALID_ARG;
+        b = std::max(b, cl::prep_scratch_bytes(grids[i], params[i]));
+    }
+    *bytes = b;
+    return LBM_OK;
+}
+
+// lbm_create / lbm_batch_create with the device share of the preprocessing.
+static int create_device(int32_t n, const lbm_grid *grids, const uint8_t *const *phases, const lbm_params *params,
+                         void *scratch, size_t bytes, void *stream, std::unique_ptr<cl::Engine> &E) {
+    if (!scratch || (reinterpret_cast<uintptr_t>(scratch) & 255)) return LBM_ERR_WORKSPACE;
+    std::mutex mu;
+    cl::DeviceAssist d;
+    d.scratch = scratch;
+    d.bytes = bytes;
+    d.stream = stream;
+    d.mu = &mu;
+    cl::g_last_error[0] = 0;
+    return cl::make_engine(n, grids, phases, params, E, &d);
+}
+
+int lbm_create_device(const lbm_grid *g, const uint8_t *phase, const lbm_params *p, void *scratch_dev,
+                      size_t scratch_bytes, void *stream, lbm_solver **out) {
+    LBM_GUARD_BEGIN
+    if (!g || !phase || !p || !out) return LBM_ERR_INVALID_ARG;
+    *out = nullptr;
+    std::unique_ptr<cl::Engine> E;
+    const int st = create_device(1, g, &phase, p, scratch_dev, scratch_bytes, stream, E);
+    if (st != LBM_OK) return st;
+    auto *s = new lbm_solver;
+    s->E = std::move(E);
+    *out = s;
+    return LBM_OK;
+    LBM_GUARD_END
+}
+
+int lbm_batch_create_device(int32_t n, const lbm_grid *grids, const uint8_t *const *phases, const lbm_params *params,
+                            void *scratch_dev, size_t scratch_bytes, void *stream, lbm_batch **out) {
+    LBM_GUARD_BEGIN
+    if (!out) return LBM_ERR_INVALID_ARG;
+    *out = nullptr;
+    std::unique_ptr<cl::Engine> E;
+    const int st = create_device(n, grids, phases, params, scratch_dev, scratch_bytes, stream, E);
+    if (st != LBM_OK) return st;
+    auto *b = new lbm_batch;
+    b->E = std::move(E);
+    *out = b;
     return LBM_OK;
     LBM_GUARD_END
 }

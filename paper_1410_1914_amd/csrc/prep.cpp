@@ -8,6 +8,8 @@
 // problems, reservoir plane) and Section 4 Eq. (24) (tau from D).
 #include "prep.h"
 
+#include <hip/hip_runtime.h>
+
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -57,7 +59,67 @@ void flood(int nx, int ny, int nz, const std::vector<uint8_t> &pass, const std::
     }
 }
 
+// The device's share of prepare(): scratch layout (each part 256-byte aligned) and
+// the two calls.  Every status is an LBM_* code.
+size_t align256(size_t n) { return (n + 255) / 256 * 256; }
+
+struct ScratchParts {
+    size_t dp, pore, pass, hit, total;
+};
+
+ScratchParts scratch_parts(int64_t Ns, int64_t N) {
+    ScratchParts s{};
+    s.dp = 0;
+    s.pore = align256(sizeof(double) * (size_t)Ns);
+    s.pass = s.pore + align256((size_t)Ns);
+    s.hit = s.pass + align256((size_t)N);
+    s.total = s.hit + align256((size_t)N);
+    return s;
+}
+
+int dev_status(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_ERR_HIP; }
+
+int device_pore_size(const DeviceAssist &d, int nx, int ny, int nz, const std::vector<uint8_t> &pore,
+                     std::vector<double> &dp, const ScratchParts &sp) {
+    const int64_t N = (int64_t)nx * ny * nz;
+    hipStream_t st = static_cast<hipStream_t>(d.stream);
+    char *base = static_cast<char *>(d.scratch);
+    hipError_t e = hipMemcpyAsync(base + sp.pore, pore.data(), (size_t)N, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return LBM_ERR_HIP;
+    const int s = lbm_pore_size_device(reinterpret_cast<const uint8_t *>(base + sp.pore), nx, ny, nz,
+                                       reinterpret_cast<double *>(base + sp.dp), d.stream);
+    if (s != LBM_OK) return s;
+    dp.resize((size_t)N);
+    e = hipMemcpyAsync(dp.data(), base + sp.dp, sizeof(double) * (size_t)N, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    return dev_status(e);
+}
+
+// hit = pass voxels connected to the x = 0 face (faces & 1) and/or x = nx - 1 (faces & 2)
+int device_reach(const DeviceAssist &d, int nx, int ny, int nz, const std::vector<uint8_t> &pass, int faces,
+                 std::vector<uint8_t> &hit, const ScratchParts &sp, bool upload) {
+    const int64_t N = (int64_t)nx * ny * nz;
+    hipStream_t st = static_cast<hipStream_t>(d.stream);
+    char *base = static_cast<char *>(d.scratch);
+    hipError_t e = hipSuccess;
+    if (upload) e = hipMemcpyAsync(base + sp.pass, pass.data(), (size_t)N, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return LBM_ERR_HIP;
+    const int s = lbm_reach_device(reinterpret_cast<const uint8_t *>(base + sp.pass), nx, ny, nz, faces,
+                                   reinterpret_cast<uint8_t *>(base + sp.hit), nullptr, d.stream);
+    if (s != LBM_OK) return s;
+    hit.resize((size_t)N);
+    e = hipMemcpyAsync(hit.data(), base + sp.hit, (size_t)N, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    return dev_status(e);
+}
+
 }  // namespace
+
+size_t prep_scratch_bytes(const lbm_grid &g, const lbm_params &p) {
+    const int res = (p.mode == LBM_MODE_REACT && p.reservoir_plane) ? 1 : 0;
+    const int64_t Ns = (int64_t)g.nx * g.ny * g.nz, N = (int64_t)(g.nx + res) * g.ny * g.nz;
+    return scratch_parts(Ns, N).total;
+}
 
 // Pore size by 13-direction averaging (Section 2.1.3).  For each direction the
 // lines are scanned once: every maximal run of pore voxels is measured from its
@@ -111,7 +173,7 @@ void pore_size_13(int nx, int ny, int nz, const uint8_t *pore, std::vector<doubl
     for (int64_t v = 0; v < N; ++v) dp[v] /= 13.0;
 }
 
-int prepare(const lbm_grid &g, const uint8_t *phase, const lbm_params &p, Prepared &o) {
+int prepare(const lbm_grid &g, const uint8_t *phase, const lbm_params &p, Prepared &o, const DeviceAssist *dev) {
     if (g.nx <= 0 || g.ny <= 0 || g.nz <= 0 || !phase) return LBM_ERR_INVALID_ARG;
     if (p.struct_size != sizeof(lbm_params)) return LBM_ERR_INVALID_ARG;
     if (p.mode < LBM_MODE_DEFF || p.mode > LBM_MODE_PROTON) return LBM_ERR_INVALID_ARG;
@@ -140,6 +202,13 @@ int prepare(const lbm_grid &g, const uint8_t *phase, const lbm_params &p, Prepar
     o.nz = g.nz;
     const int nx = o.nx, ny = o.ny, nz = o.nz;
     const int64_t N = (int64_t)nx * ny * nz;
+    const ScratchParts sp = scratch_parts(Ns, N);
+    if (dev && (!dev->scratch || dev->bytes < sp.total || (reinterpret_cast<uintptr_t>(dev->scratch) & 255)))
+        return LBM_ERR_WORKSPACE;
+    std::unique_lock<std::mutex> dev_lock;  // held while this call uses the shared scratch
+    auto lock_device = [&]() {
+        if (dev && dev->mu && !dev_lock.owns_lock()) dev_lock = std::unique_lock<std::mutex>(*dev->mu);
+    };
 
     // phase of the simulated grid (the reservoir plane is pore)
     std::vector<uint8_t> ph(N);
@@ -171,7 +240,13 @@ int prepare(const lbm_grid &g, const uint8_t *phase, const lbm_params &p, Prepar
         if (o.knudsen) {
             std::vector<uint8_t> pore(Ns);
             for (int64_t v = 0; v < Ns; ++v) pore[v] = phase[v] == LBM_PORE;
-            pore_size_13(g.nx, g.ny, g.nz, pore.data(), dp);
+            if (dev) {
+                lock_device();
+                const int ds = device_pore_size(*dev, g.nx, g.ny, g.nz, pore, dp, sp);
+                if (ds != LBM_OK) return ds;
+            } else {
+                pore_size_13(g.nx, g.ny, g.nz, pore.data(), dp);
+            }
         }
         const double kn_coef = std::sqrt(8.0 * kR * p.T_K / (kPi * p.M_kg_mol)) / 3.0;  // Eq. (8)
         for (int z = 0; z < nz; ++z)
@@ -200,16 +275,29 @@ int prepare(const lbm_grid &g, const uint8_t *phase, const lbm_params &p, Prepar
             seed[r] = left[r] = 1;
             if (!react) seed[r + nx - 1] = 1;
         }
-    flood(nx, ny, nz, transport, seed, o.active);
+    if (dev) {
+        lock_device();
+        const int ds = device_reach(*dev, nx, ny, nz, transport, react ? 1 : 3, o.active, sp, true);
+        if (ds != LBM_OK) return ds;
+    } else {
+        flood(nx, ny, nz, transport, seed, o.active);
+    }
     if (react) {
         o.percolates = std::any_of(o.active.begin(), o.active.end(), [](uint8_t a) { return a != 0; });
     } else {
         std::vector<uint8_t> fromleft;
-        flood(nx, ny, nz, transport, left, fromleft);
+        if (dev) {
+            const int ds = device_reach(*dev, nx, ny, nz, transport, 1, fromleft, sp, false);
+            if (ds != LBM_OK) return ds;
+        } else {
+            flood(nx, ny, nz, transport, left, fromleft);
+        }
         o.percolates = false;
         for (int64_t r = 0; r < (int64_t)ny * nz && !o.percolates; ++r)
             if (fromleft[r * nx + nx - 1]) o.percolates = true;
     }
+
+    if (dev_lock.owns_lock()) dev_lock.unlock();
 
     // D_ref and tau (Eq. 24 with tau_ref at D_ref)
     double dmax = 0.0;

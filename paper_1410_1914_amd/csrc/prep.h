@@ -3,6 +3,7 @@
 #pragma once
 
 #include <cstdint>
+#include <mutex>
 #include <vector>
 
 #include "../../include/lbm.h"
@@ -36,8 +37,24 @@ struct Prepared {
     std::vector<float> omega_c;
 };
 
-// Returns an LBM_* status.
-int prepare(const lbm_grid &g, const uint8_t *phase, const lbm_params &p, Prepared &out);
+// Device assistance for prepare(): the 13-direction pore size and the reach from
+// the Dirichlet faces run on the device (lbm_pore_size_device, lbm_reach_device)
+// in a caller-owned scratch buffer, on `stream`.  The results are identical to the
+// host computation.  `mu` serialises the device sections of concurrent calls that
+// share the scratch.
+struct DeviceAssist {
+    void *scratch = nullptr;
+    size_t bytes = 0;
+    void *stream = nullptr;
+    std::mutex *mu = nullptr;
+};
+
+// Scratch bytes prepare() needs with device assistance for a structure of g.
+size_t prep_scratch_bytes(const lbm_grid &g, const lbm_params &p);
+
+// Returns an LBM_* status.  dev: optional device assistance (may be null).
+int prepare(const lbm_grid &g, const uint8_t *phase, const lbm_params &p, Prepared &out,
+            const DeviceAssist *dev = nullptr);
 
 // Distance (6-neighbour steps through active voxels, periodic in y and z) of every
 // simulated voxel from the pore voxels joined to a Dirichlet face through pore

@@ -64,13 +64,13 @@ class lbm_info(ctypes.Structure):
 class lbm_coupling(ctypes.Structure):
     _fields_ = [("struct_size", c_uint32), ("k_ref", c_double), ("beta", c_double), ("gamma", c_double),
                 ("phi_m", c_double), ("phi_ref", c_double), ("tau_phi", c_double), ("theta", c_double),
-                ("tol_phi", c_double), ("max_iter", c_int32)]
+                ("tol_phi", c_double), ("max_iter", c_int32), ("potential_solver", c_int32)]
 
 
 class lbm_coupled_info(ctypes.Structure):
     _fields_ = [("iterations", c_int32), ("status", c_int32), ("dphi", c_double), ("phi_min", c_double),
                 ("rate", c_double), ("source", c_double), ("proton_in", c_double),
-                ("o2_steps", c_int64), ("phi_steps", c_int64)]
+                ("o2_steps", c_int64), ("phi_steps", c_int64), ("phi_cg_iterations", c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -92,6 +92,12 @@ SIGNATURES = {
     "lbm_params_default": ([ctypes.POINTER(lbm_params)], c_int32),
     "lbm_create": ([ctypes.POINTER(lbm_grid), ctypes.POINTER(c_uint8), ctypes.POINTER(lbm_params), _PP], c_int32),
     "lbm_get_info": ([_P, ctypes.POINTER(lbm_info)], c_int32),
+    "lbm_prep_scratch_bytes": ([c_int32, ctypes.POINTER(lbm_grid), ctypes.POINTER(lbm_params),
+                                ctypes.POINTER(ctypes.c_size_t)], c_int32),
+    "lbm_create_device": ([ctypes.POINTER(lbm_grid), ctypes.POINTER(c_uint8), ctypes.POINTER(lbm_params), _P,
+                           ctypes.c_size_t, _P, _PP], c_int32),
+    "lbm_batch_create_device": ([c_int32, ctypes.POINTER(lbm_grid), ctypes.POINTER(ctypes.POINTER(c_uint8)),
+                                 ctypes.POINTER(lbm_params), _P, ctypes.c_size_t, _P, _PP], c_int32),
     "lbm_get_host_fields": ([_P, ctypes.POINTER(c_uint8), ctypes.POINTER(c_uint8), ctypes.POINTER(c_float)], c_int32),
     "lbm_get_pore_depth": ([_P, ctypes.POINTER(c_uint8)], c_int32),
     "lbm_pore_size_device": ([_P, c_int32, c_int32, c_int32, _P, _P], c_int32),
@@ -259,13 +265,37 @@ def lbm_params_default(**overrides) -> lbm_params:
     return p
 
 
-def lbm_create(phase: np.ndarray, params: lbm_params, voxel_m: float = 2e-9):
+def _device_scratch(grids, pars, n):
+    """A torch-owned device scratch for the device share of the preprocessing:
+    (tensor, aligned address, bytes)."""
+    import torch
+
+    nb = ctypes.c_size_t()
+    _check("lbm_prep_scratch_bytes", load().lbm_prep_scratch_bytes(n, grids, pars, ctypes.byref(nb)))
+    t = torch.empty(nb.value + 256, dtype=torch.uint8, device="cuda")
+    return t, (t.data_ptr() + 255) // 256 * 256, nb.value
+
+
+def lbm_create(phase: np.ndarray, params: lbm_params, voxel_m: float = 2e-9, device_prep: bool = False):
+    """lbm_create, or lbm_create_device (pore size and reach on the GPU) when
+    device_prep is set."""
     ph = np.ascontiguousarray(phase, dtype=np.uint8)
     if ph.ndim != 3:
         raise ValueError("phase map must be (nz, ny, nx)")
     nz, ny, nx = ph.shape
     g = lbm_grid(nx, ny, nz, voxel_m)
     h = ctypes.c_void_p()
+    if device_prep:
+        import torch
+
+        require_gpu()
+        scratch, ptr, nb = _device_scratch(ctypes.byref(g), ctypes.byref(params), 1)
+        st = torch.cuda.current_stream().cuda_stream
+        torch.cuda.current_stream().synchronize()
+        _check("lbm_create_device", load().lbm_create_device(ctypes.byref(g), ph.ctypes.data_as(ctypes.POINTER(c_uint8)),
+                                                             ctypes.byref(params), ptr, nb, st, ctypes.byref(h)))
+        del scratch
+        return h
     _check("lbm_create", load().lbm_create(ctypes.byref(g), ph.ctypes.data_as(ctypes.POINTER(c_uint8)),
                                            ctypes.byref(params), ctypes.byref(h)))
     return h
@@ -393,7 +423,7 @@ def lbm_destroy(h):
         load().lbm_destroy(h)
 
 
-def lbm_batch_create(phases, params_list, voxel_m: float = 2e-9):
+def lbm_batch_create(phases, params_list, voxel_m: float = 2e-9, device_prep: bool = False):
     n = len(phases)
     grids = (lbm_grid * n)()
     arrs = [np.ascontiguousarray(p, dtype=np.uint8) for p in phases]
@@ -404,6 +434,17 @@ def lbm_batch_create(phases, params_list, voxel_m: float = 2e-9):
         ptrs[i] = a.ctypes.data_as(ctypes.POINTER(c_uint8))
     pars = (lbm_params * n)(*params_list)
     h = ctypes.c_void_p()
+    if device_prep:
+        import torch
+
+        require_gpu()
+        scratch, ptr, nb = _device_scratch(grids, pars, n)
+        st = torch.cuda.current_stream().cuda_stream
+        torch.cuda.current_stream().synchronize()
+        _check("lbm_batch_create_device", load().lbm_batch_create_device(n, grids, ptrs, pars, ptr, nb, st,
+                                                                         ctypes.byref(h)))
+        del scratch
+        return h
     _check("lbm_batch_create", load().lbm_batch_create(n, grids, ptrs, pars, ctypes.byref(h)))
     return h
 
@@ -505,14 +546,14 @@ class Solver:
     """One structure: a workspace tensor and a stream from torch, the rest in HIP."""
 
     def __init__(self, phase: np.ndarray, params: lbm_params | None = None, voxel_m: float = 2e-9,
-                 device: str = "cuda", stream=None, **overrides):
+                 device: str = "cuda", stream=None, device_prep: bool = False, **overrides):
         import torch
 
         require_gpu()
         self.params = params if params is not None else lbm_params_default()
         for k, v in overrides.items():
             setattr(self.params, k, v)
-        self.h = lbm_create(phase, self.params, voxel_m)
+        self.h = lbm_create(phase, self.params, voxel_m, device_prep=device_prep)
         self.info = lbm_get_info(self.h)
         self.nbytes = lbm_workspace_bytes(self.h)
         self.device = torch.device(device)
@@ -816,12 +857,13 @@ class Coupled19:
 class Batch:
     """Many structures solved together (one launch per step over all live instances)."""
 
-    def __init__(self, phases, params_list, voxel_m: float = 2e-9, device: str = "cuda", stream=None):
+    def __init__(self, phases, params_list, voxel_m: float = 2e-9, device: str = "cuda", stream=None,
+                 device_prep: bool = False):
         import torch
 
         require_gpu()
         self.n = len(phases)
-        self.h = lbm_batch_create(phases, params_list, voxel_m)
+        self.h = lbm_batch_create(phases, params_list, voxel_m, device_prep=device_prep)
         self.nbytes = lbm_batch_workspace_bytes(self.h)
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)

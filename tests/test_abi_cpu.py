@@ -392,3 +392,24 @@ def test_unet_handle_layout_on_the_host():
         lib.unet_destroy(h)
     assert sizes[1] > sizes[0] > 16 * 16 * 24 * 16 * 2
     lib.unet_destroy(None)
+
+
+def test_device_preparation_refuses_a_bad_scratch_without_touching_the_device():
+    """lbm_create_device checks the caller's scratch before any device call: a
+    misaligned or too small scratch is LBM_ERR_WORKSPACE."""
+    import ctypes
+
+    lib = lbm.load()
+    ph = np.ascontiguousarray(sg.pt_cl(1, shape=(6, 6, 20)))
+    g = lbm.lbm_grid(20, 6, 6, 2e-9)
+    p = lbm.lbm_params_default(knudsen=1)
+    nb = ctypes.c_size_t()
+    assert lib.lbm_prep_scratch_bytes(1, ctypes.byref(g), ctypes.byref(p), ctypes.byref(nb)) == lbm.OK
+    assert nb.value >= 10 * 6 * 6 * 20
+    h = ctypes.c_void_p()
+    u8 = ph.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    assert lib.lbm_create_device(ctypes.byref(g), u8, ctypes.byref(p), 256 + 8, nb.value, None,
+                                 ctypes.byref(h)) == lbm.ERR_WORKSPACE
+    assert lib.lbm_create_device(ctypes.byref(g), u8, ctypes.byref(p), 256, 16, None,
+                                 ctypes.byref(h)) == lbm.ERR_WORKSPACE
+    assert not h.value

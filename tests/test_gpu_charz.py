@@ -99,3 +99,79 @@ def test_full_size_npmc_256(hip):
     got, cycles = hip.reach_device(transport, 3)
     print(f"[charz] 256^3 reach: {cycles} sweep cycles", flush=True)
     assert np.array_equal(got.cpu().numpy().astype(bool), O.flood(transport, _faces_seed(ph.shape, 3)))
+
+
+PREP_CASES = [
+    ("pt", 1, (9, 10, 70), dict(mode=0, knudsen=1)),
+    ("pt", 4, (8, 7, 130), dict(mode=1, knudsen=1, k_lat=0.02)),
+    ("pt", 6, (6, 5, 64), dict(mode=2)),
+    ("npmc", 2, (12, 12, 65), dict(mode=1, knudsen=1, k_lat=0.01, catalyst_phases=(1 << 1) | (1 << 2))),
+    ("two", 3, (16, 16, 32), dict(mode=0, knudsen=0, tau_ref=0.8)),
+    ("pt", 9, (1, 1, 150), dict(mode=0, knudsen=1)),
+]
+
+
+def _host_state(hip, h):
+    info = hip.lbm_get_info(h)
+    act, ncat, om = hip.lbm_get_host_fields(h)
+    return info, act, ncat, om
+
+
+@pytest.mark.parametrize("kind,seed,shape,kw", PREP_CASES)
+def test_create_with_device_preparation_is_bit_identical(hip, kind, seed, shape, kw):
+    """lbm_create_device (pore size and reach on the GPU) gives the handle
+    lbm_create gives: the same sizes and reference values, bit-identical host
+    fields, and bit-identical steps from the cold start."""
+    import torch
+
+    ph = _phase(kind, seed, shape)
+    p = hip.lbm_params_default(**kw)
+    a = hip.lbm_create(ph, p, 2e-9)
+    b = hip.lbm_create(ph, p, 2e-9, device_prep=True)
+    ia, *fa = _host_state(hip, a)
+    ib, *fb = _host_state(hip, b)
+    hip.lbm_destroy(a)
+    hip.lbm_destroy(b)
+    for f in ("nx", "ny", "nz", "n_active", "n_segments", "percolates", "d0", "d_ref", "d0_lat"):
+        assert getattr(ia, f) == getattr(ib, f), f
+    for x, y in zip(fa, fb):
+        assert np.array_equal(x, y)
+    s1, s2 = hip.Solver(ph, p), hip.Solver(ph, p, device_prep=True)
+    s1.step(7)
+    s2.step(7)
+    assert torch.equal(s1.populations(), s2.populations())
+
+
+def test_batch_create_with_device_preparation_is_bit_identical(hip):
+    phases = [sg.pt_cl(2024000 + i, shape=(e, e, e)) for i, e in enumerate((24, 40, 16, 32))]
+    params = [hip.lbm_params_default(mode=1, knudsen=1, k_lat=10 ** -(i + 1)) for i in range(4)]
+    a = hip.Batch(phases, params)
+    b = hip.Batch(phases, params, device_prep=True)
+    for i in range(4):
+        for x, y in zip(a.host_fields(i), b.host_fields(i)):
+            assert np.array_equal(x, y), i
+
+
+def test_device_preparation_of_the_256_cube():
+    """The benchmark structure: identical fields, and the time of both routes."""
+    import time
+
+    from paper_1410_1914_amd import lbm as hip
+
+    hip.require_gpu()
+    ph = sg.npmc_cl(1, n=256)
+    p = hip.lbm_params_default(mode=1, knudsen=1, k_lat=1e-4, catalyst_phases=(1 << O.CARBON) | (1 << O.PT))
+    hip.lbm_destroy(hip.lbm_create(ph[:8], p, 1e-9, device_prep=True))  # first device use
+    t0 = time.perf_counter()
+    a = hip.lbm_create(ph, p, 1e-9)
+    t1 = time.perf_counter()
+    b = hip.lbm_create(ph, p, 1e-9, device_prep=True)
+    t2 = time.perf_counter()
+    print(f"[prep] 256^3 NPMC: host lbm_create {t1 - t0:.2f}s, lbm_create_device {t2 - t1:.2f}s", flush=True)
+    ia, *fa = _host_state(hip, a)
+    ib, *fb = _host_state(hip, b)
+    hip.lbm_destroy(a)
+    hip.lbm_destroy(b)
+    assert ia.n_active == ib.n_active
+    for x, y in zip(fa, fb):
+        assert np.array_equal(x, y)
