@@ -272,7 +272,7 @@ __global__ __launch_bounds__(kBlock) void k_d3q19_conc(const float *__restrict__
 
 size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
-int wrapi(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+__host__ __device__ inline int wrapi(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
 }  // namespace
 
@@ -544,6 +544,205 @@ __global__ __launch_bounds__(kBlock) void k_cpl_fill(float *__restrict__ a, int6
     if (v < n) a[v] = val;
 }
 
+// ---- the potential's steady state at tau_phi = 1 by preconditioned conjugate gradients
+//
+// With tau = 1 every post-collision population of the potential lattice is a_i u,
+// u = phi + S (S the source the collision adds), so its steady state is the
+// solution of the link Laplacian of the D3Q19 links (Eqs. 21-24 at tau = 1):
+//   sum over links to simulated voxels  a_i (u(x) - u(x - c_i))
+// + sum over open membrane-face links 2 a_i (u(x) - phi_m)            = S(x),
+// symmetric positive definite on the voxels the membrane face reaches.  The
+// conjugate-gradient iteration with the inverse diagonal as preconditioner solves
+// it in FP64; the lattice then takes the equilibrium state a_i u, which the
+// stepping would have reached.  Vectors are dense over the structure grid (zero
+// off the potential's voxels); per-block partial sums, then one-block finishing
+// kernels that keep the iteration's scalars on the device.
+struct Pcg {
+    const uint32_t *mask;
+    double *u, *r, *p, *ap, *dinv, *part, *scal;  // scal: rz, alpha, beta, rmax, bmax, pap
+    int64_t N;
+    int nx, ny, nz, nblk;
+    double phi_m;
+};
+enum { P_RZ = 0, P_ALPHA, P_BETA, P_RMAX, P_BMAX, P_PAP };
+
+// per block: the sum of a, the maxima of m1 and m2 (three partial slots)
+__device__ __forceinline__ void block_sums(double a, double m1, double m2, double *part) {
+    __shared__ double red[3][kBlock / 64];
+    a = wave_sum(a);
+    m1 = wave_max(m1);
+    m2 = wave_max(m2);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][wv] = a;
+        red[1][wv] = m1;
+        red[2][wv] = m2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s0 = 0.0, x1 = 0.0, x2 = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            s0 += red[0][w];
+            x1 = fmax(x1, red[1][w]);
+            x2 = fmax(x2, red[2][w]);
+        }
+        part[3 * (int64_t)blockIdx.x] = s0;
+        part[3 * (int64_t)blockIdx.x + 1] = x1;
+        part[3 * (int64_t)blockIdx.x + 2] = x2;
+    }
+}
+
+// (A q)(v) on the potential's voxels, the diagonal and the open-link sum
+__device__ __forceinline__ double pcg_apply(const Pcg &g, int64_t v, const double *__restrict__ q, double &diag,
+                                            double &open) {
+    const uint32_t m = g.mask[v];
+    const uint32_t vv = (uint32_t)v, nx = (uint32_t)g.nx, ny = (uint32_t)g.ny, r = vv / nx;
+    const int x = (int)(vv - r * nx), z = (int)(r / ny), y = (int)(r - (uint32_t)z * ny);
+    double off = 0.0;
+    diag = 0.0;
+    open = 0.0;
+#pragma unroll
+    for (int i = 1; i < kQ; ++i) {
+        const double w = weight(i);
+        if (!((m >> i) & 1u)) {
+            const int sy = wrapi(y - CY[i], g.ny), sz = wrapi(z - CZ[i], g.nz);
+            off += w * q[((int64_t)sz * g.ny + sy) * g.nx + (x - CX[i])];
+            diag += w;
+        } else if (CX[i] == -1 && x == g.nx - 1 && ((m >> (24 + FACE_SLOT[i])) & 1u)) {
+            open += 2.0 * w;
+        }
+    }
+    diag += open;
+    return diag * q[v] - off;
+}
+
+// u = phi + S (the previous potential as the first guess), the inverse diagonal
+__global__ __launch_bounds__(kBlock) void k_pcg_start(Pcg g, const float *__restrict__ phi,
+                                                      const float *__restrict__ src) {
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v >= g.N) return;
+    const bool act = (g.mask[v] & kActive) != 0;
+    g.u[v] = act ? (double)phi[v] + (double)src[v] : 0.0;
+    g.p[v] = 0.0;
+    double d = 0.0;
+    if (act) {
+        const uint32_t m = g.mask[v];
+        const int x = (int)(v % g.nx);
+        for (int i = 1; i < kQ; ++i) {
+            if (!((m >> i) & 1u)) d += weight(i);
+            else if (CX[i] == -1 && x == g.nx - 1 && ((m >> (24 + FACE_SLOT[i])) & 1u)) d += 2.0 * weight(i);
+        }
+    }
+    g.dinv[v] = d > 0.0 ? 1.0 / d : 0.0;
+}
+
+// r = b - A u, p = M^-1 r; partials of r.M^-1 r, max|r| and max|b|
+__global__ __launch_bounds__(kBlock) void k_pcg_residual(Pcg g, const float *__restrict__ src) {
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double rz = 0.0, rm = 0.0, bm = 0.0;
+    if (v < g.N) {
+        double rv = 0.0;
+        if (g.mask[v] & kActive) {
+            double diag, open;
+            const double au = pcg_apply(g, v, g.u, diag, open);
+            const double b = (double)src[v] + open * g.phi_m;
+            rv = b - au;
+            bm = fabs(b);
+        }
+        g.r[v] = rv;
+        const double z = g.dinv[v] * rv;
+        g.p[v] = z;
+        rz = rv * z;
+        rm = fabs(rv);
+    }
+    block_sums(rz, rm, bm, g.part);
+}
+
+// ap = A p; partials of p.ap
+__global__ __launch_bounds__(kBlock) void k_pcg_ap(Pcg g) {
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double pap = 0.0;
+    if (v < g.N) {
+        double a = 0.0;
+        if (g.mask[v] & kActive) {
+            double diag, open;
+            a = pcg_apply(g, v, g.p, diag, open);
+        }
+        g.ap[v] = a;
+        pap = g.p[v] * a;
+    }
+    block_sums(pap, 0.0, 0.0, g.part);
+}
+
+// one block: sums of the partials; stage 0 after the residual (rz, bmax, rmax),
+// 1 after A p (alpha = rz / pap), 2 after the update (beta = rz_new / rz, rz, rmax)
+__global__ __launch_bounds__(kBlock) void k_pcg_finish(Pcg g, int stage) {
+    double a = 0.0, m1 = 0.0, m2 = 0.0;
+    for (int k = threadIdx.x; k < g.nblk; k += kBlock) {
+        a += g.part[3 * (int64_t)k];
+        m1 = fmax(m1, g.part[3 * (int64_t)k + 1]);
+        m2 = fmax(m2, g.part[3 * (int64_t)k + 2]);
+    }
+    __shared__ double red[3][kBlock / 64];
+    a = wave_sum(a);
+    m1 = wave_max(m1);
+    m2 = wave_max(m2);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][wv] = a;
+        red[1][wv] = m1;
+        red[2][wv] = m2;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double s0 = 0.0, x1 = 0.0, x2 = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) {  // fixed order: the scalars are deterministic
+        s0 += red[0][w];
+        x1 = fmax(x1, red[1][w]);
+        x2 = fmax(x2, red[2][w]);
+    }
+    if (stage == 0) {
+        g.scal[P_RZ] = s0;
+        g.scal[P_RMAX] = x1;
+        g.scal[P_BMAX] = x2;
+    } else if (stage == 1) {
+        g.scal[P_PAP] = s0;
+        g.scal[P_ALPHA] = s0 > 0.0 ? g.scal[P_RZ] / s0 : 0.0;
+    } else {
+        g.scal[P_BETA] = g.scal[P_RZ] > 0.0 ? s0 / g.scal[P_RZ] : 0.0;
+        g.scal[P_RZ] = s0;
+        g.scal[P_RMAX] = x1;
+    }
+}
+
+// u += alpha p, r -= alpha ap; partials of r.M^-1 r and max|r|
+__global__ __launch_bounds__(kBlock) void k_pcg_update(Pcg g) {
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double rz = 0.0, rm = 0.0;
+    if (v < g.N) {
+        const double al = g.scal[P_ALPHA];
+        g.u[v] += al * g.p[v];
+        const double rv = g.r[v] - al * g.ap[v];
+        g.r[v] = rv;
+        rz = rv * g.dinv[v] * rv;
+        rm = fabs(rv);
+    }
+    block_sums(rz, rm, 0.0, g.part);
+}
+
+// p = M^-1 r + beta p
+__global__ __launch_bounds__(kBlock) void k_pcg_direction(Pcg g) {
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v >= g.N) return;
+    g.p[v] = g.dinv[v] * g.r[v] + g.scal[P_BETA] * g.p[v];
+}
+
+// FP32 copy of u for the lattice's equilibrium state
+__global__ __launch_bounds__(kBlock) void k_pcg_out(Pcg g, float *__restrict__ out) {
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v < g.N) out[v] = (float)g.u[v];
+}
+
 }  // namespace
 
 struct lbm19_coupled {
@@ -555,7 +754,8 @@ struct lbm19_coupled {
     int nb = 0;
     std::vector<float> n_site;
     size_t ws_o2 = 0, ws_phi = 0, off_phi_ws = 0, off_n = 0, off_phi = 0, off_new = 0, off_c = 0, off_src = 0,
-           off_part = 0, need = 0;
+           off_part = 0, off_pcg = 0, need = 0;
+    bool use_cg = false;  // the potential by conjugate gradients (tau_phi = 1)
     char *ws = nullptr;
     hipStream_t st = nullptr;
     lbm_coupled_info last{};
@@ -781,7 +981,8 @@ int lbm19_coupled_create(const lbm_grid *g, const uint8_t *phase, const lbm_para
         *out = nullptr;
         if (cp->struct_size != sizeof(lbm_coupling) || !(cp->k_ref > 0.0) || !(cp->beta >= 0.0) ||
             !(cp->gamma >= 0.0) || !(cp->tau_phi > 0.5) || !(cp->theta > 0.0 && cp->theta <= 1.0) ||
-            !(cp->tol_phi > 0.0) || cp->max_iter < 1 || p->mode != LBM_MODE_REACT || !(p->c_in > 0.0))
+            !(cp->tol_phi > 0.0) || cp->max_iter < 1 || p->mode != LBM_MODE_REACT || !(p->c_in > 0.0) ||
+            cp->potential_solver < 0 || cp->potential_solver > 1)
             return LBM_ERR_INVALID_ARG;
         // the largest site rate, at the membrane potential, must keep k n below 1
         if (6.0 * cp->k_ref * std::exp(cp->beta * std::max(0.0, cp->phi_m - cp->phi_ref)) >= 1.0)
@@ -840,6 +1041,9 @@ int lbm19_coupled_create(const lbm_grid *g, const uint8_t *phase, const lbm_para
         o += align256(4 * (size_t)O.nx * O.ny * O.nz);
         c->off_part = o;
         o += align256(8 * (size_t)c->nb);
+        c->use_cg = cp->tau_phi == 1.0 && cp->potential_solver == 0;
+        c->off_pcg = o;
+        if (c->use_cg) o += 5 * align256(8 * (size_t)c->Ns) + align256(8 * 3 * (size_t)c->nb) + 256;
         c->need = o;
         *out = c.release();
         return LBM_OK;
@@ -884,6 +1088,66 @@ int lbm19_coupled_bind(lbm19_coupled *c, void *ws, size_t bytes, void *stream) {
     return lbm19_set_initial_concentration(c->phi, c->at<float>(c->off_phi));
 }
 
+// The potential's steady state for the current source by preconditioned conjugate
+// gradients (tau_phi = 1, see Pcg), then the lattice set to its equilibrium state
+// and one measured step (fluxes and source as the stepping solver reports them).
+static int potential_cg(lbm19_coupled *c, lbm_run_info *r, int64_t *iters) {
+    const int64_t Ns = c->Ns;
+    const size_t v8 = align256(8 * (size_t)Ns);
+    Pcg g{};
+    g.mask = c->phi->at<uint32_t>(c->phi->off_mask);
+    g.u = c->at<double>(c->off_pcg);
+    g.r = c->at<double>(c->off_pcg + v8);
+    g.p = c->at<double>(c->off_pcg + 2 * v8);
+    g.ap = c->at<double>(c->off_pcg + 3 * v8);
+    g.dinv = c->at<double>(c->off_pcg + 4 * v8);
+    g.part = c->at<double>(c->off_pcg + 5 * v8);
+    g.scal = c->at<double>(c->off_pcg + 5 * v8 + align256(8 * 3 * (size_t)c->nb));
+    g.N = Ns;
+    g.nx = c->nx;
+    g.ny = c->ny;
+    g.nz = c->nz;
+    g.nblk = c->nb;
+    g.phi_m = c->cp.phi_m;
+    const float *src = c->at<float>(c->off_src);
+    hipStream_t st = c->st;
+    k_pcg_start<<<c->nb, kBlock, 0, st>>>(g, c->at<float>(c->off_phi), src);
+    k_pcg_residual<<<c->nb, kBlock, 0, st>>>(g, src);
+    k_pcg_finish<<<1, kBlock, 0, st>>>(g, 0);
+    hipError_t e = hipGetLastError();
+    double sc[8] = {};
+    constexpr double kTol = 1e-12;         // max|r| <= kTol max|b|
+    const int64_t max_it = 200000;
+    int64_t it = 0;
+    bool done = false;
+    while (e == hipSuccess && !done) {
+        e = hipMemcpyAsync(sc, g.scal, sizeof(sc), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) break;
+        if (!(sc[P_RMAX] > kTol * sc[P_BMAX]) || it >= max_it) {
+            done = true;
+            break;
+        }
+        for (int k = 0; k < 32 && e == hipSuccess; ++k, ++it) {
+            k_pcg_ap<<<c->nb, kBlock, 0, st>>>(g);
+            k_pcg_finish<<<1, kBlock, 0, st>>>(g, 1);
+            k_pcg_update<<<c->nb, kBlock, 0, st>>>(g);
+            k_pcg_finish<<<1, kBlock, 0, st>>>(g, 2);
+            k_pcg_direction<<<c->nb, kBlock, 0, st>>>(g);
+            e = hipGetLastError();
+        }
+    }
+    *iters = it;
+    if (e != hipSuccess) return cl::record_error(e, "lbm19_coupled_run (potential)");
+    if (!(sc[P_RMAX] <= kTol * sc[P_BMAX])) return std::isfinite(sc[P_RMAX]) ? LBM_NOT_CONVERGED : LBM_ERR_DIVERGED;
+    k_pcg_out<<<c->nb, kBlock, 0, st>>>(g, c->at<float>(c->off_new));
+    e = hipGetLastError();
+    if (e != hipSuccess) return cl::record_error(e, "lbm19_coupled_run (potential)");
+    int s = lbm19_set_initial_concentration(c->phi, c->at<float>(c->off_new));
+    if (s == LBM_OK) s = lbm19_measure(c->phi, r);
+    return s;
+}
+
 int lbm19_coupled_run(lbm19_coupled *c, lbm_coupled_info *info) {
     if (!c) return LBM_ERR_INVALID_ARG;
     if (!c->ws) return LBM_ERR_UNBOUND;
@@ -916,8 +1180,14 @@ int lbm19_coupled_run(lbm19_coupled *c, lbm_coupled_info *info) {
                                                   c->nx_o, c->off, cp.gamma, cp.beta, cp.phi_ref, c->c_in);
         e = hipGetLastError();
         if (e != hipSuccess) return cl::record_error(e, "lbm19_coupled_run");
-        st = lbm19_run_to_steady(c->phi, &r);
-        I.phi_steps = r.steps;
+        if (c->use_cg) {
+            int64_t iters = 0;
+            st = potential_cg(c, &r, &iters);
+            I.phi_cg_iterations += iters;
+        } else {
+            st = lbm19_run_to_steady(c->phi, &r);
+            I.phi_steps = r.steps;
+        }
         if (st != LBM_OK) {
             inner = st;
             break;
