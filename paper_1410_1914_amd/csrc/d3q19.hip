@@ -1,17 +1,18 @@
 // D3Q19 variant of the solver: the lattice the paper itself uses (Chen et al.,
 // arXiv 1410.1914, Section 4, Eqs. 21-24), beside the D3Q7 production path.
 //
-// Storage is dense over the simulated grid in blocks of 64 voxels (one wave):
-// f[(v >> 6) * 19 * 64 + i * 64 + (v & 63)] with v = (z * ny + y) * nx + x, so a
-// wave's nineteen populations are one contiguous 4864-byte block, FP32, holding the post-collision value shifted by
-// a_i * c_sh(x) (c_sh = sh0 - slope * x, the empty-box profile between Dirichlet
-// faces, or half the inlet value when reacting), two lattices A/B.  Per voxel a
-// 32-bit word says which pull sources are missing (bits 0-18), which face links
-// are open at x = 0 (bits 19-23, the five directions with c_x = +1) and at
-// x = nx - 1 (bits 24-28, the five with c_x = -1), and whether the voxel is
-// simulated (bit 31).  One thread per voxel, 256 per block, blocks dealt to the
-// XCDs in contiguous eighths of the grid so that neighbouring planes share an L2.
-// The collision is evaluated in FP64 and rounded once to FP32.
+// Storage holds the simulated (fluid) voxels only, in x-fastest order: compact
+// index j, populations in blocks of 64 compact voxels,
+// f[(j >> 6) * 19 * 64 + i * 64 + (j & 63)], FP32, holding the post-collision
+// value shifted by a_i * c_sh(x) (c_sh = sh0 - slope * x, the empty-box profile
+// between Dirichlet faces, or half the inlet value when reacting), two lattices
+// A/B.  A wave updates one 64-voxel row segment; its record (D19Rec) holds the
+// fluid masks and compact prefixes of the nine rows it pulls from, (y + ry,
+// z + rz) for ry, rz in {-1, 0, 1}, so the compact index of any pull source is a
+// prefix plus a count of mask bits, and no per-voxel neighbour table exists.
+// Relaxation rates, sink coefficients and the concentration snapshot are compact
+// too; a dense map from voxel to compact index serves the conversions.  The
+// collision is evaluated in FP64 and rounded once to FP32.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -42,37 +43,55 @@ constexpr uint32_t kActive = 1u << 31;
 
 __host__ __device__ constexpr double weight(int i) { return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
 
+// Segment record of the compact layout: the nine rows a wave pulls from, row k
+// being (y + ry, z + rz) with k = (ry + 1) * 3 + (rz + 1) (k = 4 is the
+// segment's own row).
+struct alignas(16) D19Rec {
+    uint64_t m[9];       // simulated voxels of row k over the segment's x range
+    uint32_t pre[9];     // compact index of the first simulated voxel of that range
+    uint32_t edges;      // bit 2k: the voxel before row k's range is simulated; bit 2k + 1: the one after
+    uint16_t s, y, z, pad;  // x0 = 64 s, row y, plane z
+    uint32_t pad2[2];
+};
+static_assert(sizeof(D19Rec) == 128, "D19Rec layout");
+
+// row of the pull source x - c_i
+constexpr int ROW[kQ] = {4, 4, 4, 1, 7, 3, 5, 1, 7, 1, 7, 3, 5, 3, 5, 0, 2, 6, 8};
+
 struct D19Args {
     const float *__restrict__ fin;
     float *__restrict__ fout;
-    const uint32_t *__restrict__ mask;
-    const float *__restrict__ omega;
-    const float *__restrict__ kn;  // k n per voxel (reactive problem only)
-    const float *__restrict__ src; // a given source per voxel, or null
-    float *__restrict__ csnap;     // C at the previous measured step
-    double *__restrict__ part;     // per-block partial sums (measured steps)
-    int64_t N;
+    const D19Rec *__restrict__ rec;
+    const uint32_t *__restrict__ list;  // segments holding simulated voxels
+    const float *__restrict__ omega;    // compact
+    const float *__restrict__ kn;       // k n, compact (reactive problem only)
+    const float *__restrict__ src;      // a given source per voxel (dense), or null
+    float *__restrict__ csnap;          // C at the previous measured step (compact)
+    double *__restrict__ part;          // per-block partial sums (measured steps)
+    int64_t nent;
     int nx, ny, nz, nblk;
-    double sh0, slope;             // shift of the stored populations
-    double ab_in, ab_out;          // anti-bounce-back constants in the shifted form
+    double sh0, slope;                  // shift of the stored populations
+    double ab_in, ab_out;               // anti-bounce-back constants in the shifted form
     double c_in, c_out;
+    int react_outlet;                   // 1: zero-gradient outlet (no open links at x = nx - 1)
+    int open_inlet;                     // 1: open links at x = 0 (0 for the potential problem)
 };
 
 // Blocks are dealt round-robin to the 8 XCDs; give XCD k the k-th contiguous
-// eighth of the voxel range instead.
+// eighth of the list instead.
 __device__ __forceinline__ int64_t xcd_block(int b, int nblk) {
     if (nblk < 8) return b;
     const int q = nblk >> 3, r = nblk & 7, x = b & 7;
     return (int64_t)x * q + min(x, r) + (b >> 3);
 }
 
-// position of population i of voxel v in a lattice
-__host__ __device__ __forceinline__ int64_t fidx(int i, int64_t v) { return (v >> 6) * (kQ * 64) + i * 64 + (v & 63); }
+// position of population i of compact voxel j in a lattice
+__host__ __device__ __forceinline__ int64_t fidx(int i, int64_t j) { return (j >> 6) * (kQ * 64) + i * 64 + (j & 63); }
 
 // the same as a byte offset in 32 bits (a lattice is kept below 4 GiB), so that
 // loads and stores take the uniform base plus one 32-bit lane offset
-__device__ __forceinline__ uint32_t fbyte(int i, uint32_t v) {
-    return ((v >> 6) * (kQ * 64) + (uint32_t)i * 64 + (v & 63)) * 4u;
+__device__ __forceinline__ uint32_t fbyte(int i, uint32_t j) {
+    return ((j >> 6) * (kQ * 64) + (uint32_t)i * 64 + (j & 63)) * 4u;
 }
 
 __device__ __forceinline__ float ld(const float *base, uint32_t byte) {
@@ -93,108 +112,116 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// One step of Eq. (21) in pull form: gather the post-collision populations of the
-// previous step (half-way bounce-back, anti-bounce-back at open face links,
-// periodic y and z), relax toward a_i C with the sink a_i S, store.  MEASURE also
-// sums the fluxes of the links just crossed and the C, k n C of the new state.
+__device__ __forceinline__ uint32_t mbcnt64(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ bool bit64(uint64_t m, int l) { return ((m >> l) & 1ull) != 0; }
+
+// One step of Eq. (21) in pull form for the segments of the list, one wave each:
+// gather the post-collision populations of the previous step (half-way
+// bounce-back, anti-bounce-back at open face links, periodic y and z), relax
+// toward a_i C with the sink a_i S, store.  A face link is open when the voxel of
+// the face plane it passes (the source row's voxel at that face) is simulated.
+// MEASURE also sums the fluxes of the links just crossed and the C, k n C of the
+// new state.
 template <bool REACT, bool MEASURE>
 __global__ __launch_bounds__(kBlock) void k_d3q19(D19Args a) {
-    const int64_t v = xcd_block(blockIdx.x, a.nblk) * kBlock + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t e = xcd_block(blockIdx.x, a.nblk) * (kBlock / 64) + wave;
     double acc[kRed] = {0, 0, 0, 0, 0, 0, 0, 0};
-    const uint32_t m0 = v < a.N ? a.mask[v] : 0u;
-    const bool act = (m0 & kActive) != 0;
-    // A wave with any simulated voxel stores every lane, so that the lattice's
-    // cache lines leave L2 whole: a lane off the simulated voxels takes all its
-    // populations from its own zeros, and its omega and k n are 0, so it stores
-    // 0 (entries there are never read).
-    const uint32_t m = act ? m0 : (1u << kQ) - 1u;
-    const bool wave_live = __ballot(act) != 0;
-    if (v < a.N && wave_live) {
-        const uint32_t vv = (uint32_t)v, nx = (uint32_t)a.nx, ny = (uint32_t)a.ny, r = vv / nx;
-        const int x = (int)(vv - r * nx);
-        const int z = (int)(r / ny), y = (int)(r - (uint32_t)z * ny);
-        const uint32_t ym = y == 0 ? ny - 1 : y - 1, yp = y == (int)ny - 1 ? 0 : y + 1;
-        const uint32_t zm = z == 0 ? a.nz - 1 : z - 1, zp = z == a.nz - 1 ? 0 : z + 1;
-        const double csh = a.sh0 - a.slope * x;
-        // every lane loads each direction once, from its pull source or, when that
-        // source is missing, its own opposite population: one offset select per
-        // direction and no branch, so all nineteen loads are in flight together
-        const uint32_t plane = nx * ny;
-        const uint32_t z0 = (uint32_t)z * plane, zlo = zm * plane, zhi = zp * plane;
-        const uint32_t y0 = (uint32_t)y * nx, ylo = ym * nx, yhi = yp * nx;
-        float raw[kQ];
-#pragma unroll
-        for (int i = 0; i < kQ; ++i) {
-            const uint32_t oy = CY[i] == 1 ? ylo : (CY[i] == -1 ? yhi : y0);
-            const uint32_t oz = CZ[i] == 1 ? zlo : (CZ[i] == -1 ? zhi : z0);
-            const uint32_t pull = fbyte(i, oz + oy + (uint32_t)(x - CX[i]));
-            const uint32_t own = fbyte(OPP[i], vv);
-            raw[i] = ld(a.fin, ((m >> i) & 1u) ? own : pull);
-        }
-        double g[kQ];
-#pragma unroll
-        for (int i = 0; i < kQ; ++i) {
-            const double w = weight(i), r = (double)raw[i];
-            const bool blocked = (m >> i) & 1u;
-            bool anti = false;
-            double ab = 0.0;
-            if (CX[i] == 1) {
-                anti = x == 0 && ((m >> (19 + FACE_SLOT[i])) & 1u);
-                ab = a.ab_in;
-            } else if (CX[i] == -1) {
-                anti = x == a.nx - 1 && ((m >> (24 + FACE_SLOT[i])) & 1u);
-                ab = a.ab_out;
-            }
-            g[i] = blocked ? (anti ? -r + w * ab : r) : r + w * CX[i] * a.slope;
-        }
-        double sum = 0.0;
-#pragma unroll
-        for (int i = 0; i < kQ; ++i) sum += g[i];
-        const double C = csh + sum;
-        const double om = (double)a.omega[v];
-        const double knv = REACT ? (double)a.kn[v] : 0.0;
-        const double sv = a.src ? (double)a.src[v] : 0.0;
-        const double b = (om - knv) * C - om * csh + sv;
-        const double keep = 1.0 - om;
-#pragma unroll
-        for (int i = 0; i < kQ; ++i) st(a.fout, fbyte(i, vv), (float)(keep * g[i] + weight(i) * b));
-        if constexpr (MEASURE) {
+    if (e < a.nent) {
+        const D19Rec &R = a.rec[a.list[e]];
+        const uint64_t mown = R.m[4];
+        if (bit64(mown, lane)) {
+            const int x = (int)R.s * 64 + lane;
+            const uint32_t j = R.pre[4] + mbcnt64(mown);
+            const double csh = a.sh0 - a.slope * x;
+            // every lane loads each direction once, from its pull source or, when that
+            // source is missing, its own opposite population
+            float raw[kQ];
+            bool have[kQ];
 #pragma unroll
             for (int i = 0; i < kQ; ++i) {
-                if (CX[i] == 0) continue;
-                const double f = g[i] + weight(i) * csh;
-                if (!((m >> i) & 1u)) acc[2] += CX[i] * f;
-                if (CX[i] == 1 && x == 0 && ((m >> (19 + FACE_SLOT[i])) & 1u))
-                    acc[0] += 2.0 * f - 2.0 * weight(i) * a.c_in;
-                if (!REACT && CX[i] == -1 && x == a.nx - 1 && ((m >> (24 + FACE_SLOT[i])) & 1u))
-                    acc[1] += 2.0 * weight(i) * a.c_out - 2.0 * f;
+                const int k = ROW[i];
+                const uint64_t mr = R.m[k];
+                const uint32_t c = R.pre[k] + mbcnt64(mr);
+                bool fl;
+                uint32_t idx;
+                if (CX[i] == 0) {
+                    fl = bit64(mr, lane);
+                    idx = c;
+                } else if (CX[i] == 1) {  // source x - 1
+                    fl = lane ? bit64(mr, lane - 1) : ((R.edges >> (2 * k)) & 1u) != 0;
+                    idx = c - 1u;
+                } else {                  // source x + 1
+                    fl = lane < 63 ? bit64(mr, lane + 1) : ((R.edges >> (2 * k + 1)) & 1u) != 0;
+                    idx = c + (bit64(mr, lane) ? 1u : 0u);
+                }
+                have[i] = fl;
+                raw[i] = ld(a.fin, fl ? fbyte(i, idx) : fbyte(OPP[i], j));
             }
-            if (act) {
+            double g[kQ];
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) {
+                const double w = weight(i), r = (double)raw[i];
+                bool anti = false;
+                double ab = 0.0;
+                if (CX[i] == 1) {
+                    anti = a.open_inlet && x == 0 && bit64(R.m[ROW[i]], lane);
+                    ab = a.ab_in;
+                } else if (CX[i] == -1) {
+                    anti = !a.react_outlet && x == a.nx - 1 && bit64(R.m[ROW[i]], lane);
+                    ab = a.ab_out;
+                }
+                g[i] = have[i] ? r + w * CX[i] * a.slope : (anti ? -r + w * ab : r);
+            }
+            double sum = 0.0;
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) sum += g[i];
+            const double C = csh + sum;
+            const double om = (double)a.omega[j];
+            const double knv = REACT ? (double)a.kn[j] : 0.0;
+            const int64_t v = ((int64_t)R.z * a.ny + R.y) * a.nx + x;
+            const double sv = a.src ? (double)a.src[v] : 0.0;
+            const double b = (om - knv) * C - om * csh + sv;
+            const double keep = 1.0 - om;
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) st(a.fout, fbyte(i, j), (float)(keep * g[i] + weight(i) * b));
+            if constexpr (MEASURE) {
+#pragma unroll
+                for (int i = 0; i < kQ; ++i) {
+                    if (CX[i] == 0) continue;
+                    const double f = g[i] + weight(i) * csh;
+                    if (have[i]) acc[2] += CX[i] * f;
+                    if (CX[i] == 1 && a.open_inlet && x == 0 && bit64(R.m[ROW[i]], lane))
+                        acc[0] += 2.0 * f - 2.0 * weight(i) * a.c_in;
+                    if (CX[i] == -1 && !a.react_outlet && x == a.nx - 1 && bit64(R.m[ROW[i]], lane))
+                        acc[1] += 2.0 * weight(i) * a.c_out - 2.0 * f;
+                }
                 acc[3] = knv * C - sv;  // the net sink
                 acc[4] = C;
-                acc[5] = fabs(C - (double)a.csnap[v]);
-                a.csnap[v] = (float)C;
+                acc[5] = fabs(C - (double)a.csnap[j]);
+                a.csnap[j] = (float)C;
                 acc[6] = fabs(C);
                 acc[7] = (C == C) ? 0.0 : 1.0;
-            } else {
-                acc[0] = acc[1] = acc[2] = 0.0;
             }
         }
     }
     if constexpr (MEASURE) {
         __shared__ double red[kBlock / 64][kRed];
-        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
         for (int k = 0; k < kRed; ++k) {
-            const double s = (k == 5 || k == 6) ? wave_max(acc[k]) : wave_sum(acc[k]);
-            if (lane == 0) red[wv][k] = s;
+            const double sm = (k == 5 || k == 6) ? wave_max(acc[k]) : wave_sum(acc[k]);
+            if (lane == 0) red[wave][k] = sm;
         }
         __syncthreads();
         if (threadIdx.x < kRed) {
             const int k = threadIdx.x;
-            double s = red[0][k];
-            for (int w = 1; w < kBlock / 64; ++w) s = (k == 5 || k == 6) ? fmax(s, red[w][k]) : s + red[w][k];
-            a.part[(int64_t)blockIdx.x * kRed + k] = s;
+            double sm = red[0][k];
+            for (int w = 1; w < kBlock / 64; ++w) sm = (k == 5 || k == 6) ? fmax(sm, red[w][k]) : sm + red[w][k];
+            a.part[(int64_t)blockIdx.x * kRed + k] = sm;
         }
     }
 }
@@ -223,51 +250,52 @@ __global__ __launch_bounds__(kBlock) void k_d3q19_reduce(const double *__restric
     }
 }
 
-// Stored state from a concentration field (f_i = a_i C0, NULL: C0 = 0), and the
-// snapshot C used by the first window residual.  Entries off the simulated
-// voxels are never read by the step.
-__global__ __launch_bounds__(kBlock) void k_d3q19_init(float *__restrict__ f, const uint32_t *__restrict__ mask,
+// Stored state from a dense concentration field (f_i = a_i C0, NULL: C0 = 0), and
+// the snapshot C used by the first window residual.  cidx maps a voxel to its
+// compact index (-1 off the simulated voxels).
+__global__ __launch_bounds__(kBlock) void k_d3q19_init(float *__restrict__ f, const int32_t *__restrict__ cidx,
                                                        const float *__restrict__ c0, float *__restrict__ csnap,
                                                        int64_t N, int nx, double sh0, double slope) {
     const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (v >= N) return;
-    const bool act = (mask[v] & kActive) != 0;
-    const double C = act && c0 ? (double)c0[v] : 0.0;
+    const int32_t j = cidx[v];
+    if (j < 0) return;
+    const double C = c0 ? (double)c0[v] : 0.0;
     const double csh = sh0 - slope * (double)(v % nx);
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) f[fidx(i, v)] = act ? (float)(weight(i) * (C - csh)) : 0.f;
-    csnap[v] = (float)C;
+    for (int i = 0; i < kQ; ++i) f[fidx(i, j)] = (float)(weight(i) * (C - csh));
+    csnap[j] = (float)C;
 }
 
-// Unshifted FP64 populations of the stored (post-collision) state.
-__global__ __launch_bounds__(kBlock) void k_d3q19_unshift(const float *__restrict__ f, const uint32_t *__restrict__ mask,
+// Unshifted FP64 populations of the stored (post-collision) state, dense.
+__global__ __launch_bounds__(kBlock) void k_d3q19_unshift(const float *__restrict__ f, const int32_t *__restrict__ cidx,
                                                           double *__restrict__ out, int64_t N, int nx, double sh0,
                                                           double slope) {
     const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (v >= N) return;
-    const bool act = (mask[v] & kActive) != 0;
+    const int32_t j = cidx[v];
     const double csh = sh0 - slope * (double)(v % nx);
 #pragma unroll
-    for (int i = 0; i < kQ; ++i)
-        out[(int64_t)i * N + v] = act ? (double)f[fidx(i, v)] + weight(i) * csh : 0.0;
+    for (int i = 0; i < kQ; ++i) out[(int64_t)i * N + v] = j >= 0 ? (double)f[fidx(i, j)] + weight(i) * csh : 0.0;
 }
 
-// C of the state: the stored populations sum to (1 - k n) C + S after the collision.
-__global__ __launch_bounds__(kBlock) void k_d3q19_conc(const float *__restrict__ f, const uint32_t *__restrict__ mask,
+// C of the state, dense: the stored populations sum to (1 - k n) C + S after the collision.
+__global__ __launch_bounds__(kBlock) void k_d3q19_conc(const float *__restrict__ f, const int32_t *__restrict__ cidx,
                                                        const float *__restrict__ kn, const float *__restrict__ src,
-                                                       float *__restrict__ c, int64_t N,
-                                                       int nx, double sh0, double slope) {
+                                                       float *__restrict__ c, int64_t N, int nx, double sh0,
+                                                       double slope) {
     const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (v >= N) return;
-    if (!(mask[v] & kActive)) {
+    const int32_t j = cidx[v];
+    if (j < 0) {
         c[v] = 0.f;
         return;
     }
     double s = sh0 - slope * (double)(v % nx);
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) s += (double)f[fidx(i, v)];
+    for (int i = 0; i < kQ; ++i) s += (double)f[fidx(i, j)];
     if (src) s -= (double)src[v];
-    c[v] = (float)(kn ? s / (1.0 - (double)kn[v]) : s);
+    c[v] = (float)(kn ? s / (1.0 - (double)kn[j]) : s);
 }
 
 size_t align256(size_t v) { return (v + 255) / 256 * 256; }
@@ -280,14 +308,20 @@ struct lbm19_solver {
     cl::Prepared P;
     bool react = false;
     bool potential = false;        // the coupled potential problem (Dirichlet at x = L only)
-    const float *src = nullptr;    // a given per-voxel source (device), or null
-    int64_t N = 0;
-    int nblk = 0;
+    const float *src = nullptr;    // a given per-voxel source (device, dense), or null
+    int64_t N = 0;                 // voxels of the simulated grid
+    int64_t nf = 0, stride = 0;    // simulated voxels, and that count rounded up to 64
+    int64_t nent = 0;              // segments holding simulated voxels
+    int nblk = 0, nbd = 0;         // step blocks (four segments each), dense blocks
     double d0_lat = 0, ab_in = 0, ab_out = 0;
-    std::vector<uint32_t> mask;
-    std::vector<float> kn;
+    std::vector<uint32_t> mask;    // dense per-voxel bits (pull sources, open links), for the potential solve
+    std::vector<int32_t> cidx;     // dense voxel -> compact index, -1 off the simulated voxels
+    std::vector<D19Rec> rec;       // per row segment
+    std::vector<uint32_t> list;    // segments holding simulated voxels
+    std::vector<float> om_c, kn_c; // compact 1/tau and k n
     // workspace carve-up
-    size_t off_f[2] = {0, 0}, off_mask = 0, off_om = 0, off_kn = 0, off_cs = 0, off_part = 0, off_red = 0, need = 0;
+    size_t off_f[2] = {0, 0}, off_mask = 0, off_cidx = 0, off_rec = 0, off_list = 0, off_om = 0, off_kn = 0,
+           off_cs = 0, off_part = 0, off_red = 0, need = 0;
     char *ws = nullptr;
     hipStream_t st = nullptr;
     int device = 0;
@@ -304,13 +338,14 @@ struct lbm19_solver {
         D19Args a{};
         a.fin = at<float>(off_f[cur]);
         a.fout = at<float>(off_f[cur ^ 1]);
-        a.mask = at<uint32_t>(off_mask);
+        a.rec = at<D19Rec>(off_rec);
+        a.list = at<uint32_t>(off_list);
         a.omega = at<float>(off_om);
         a.kn = react ? at<float>(off_kn) : nullptr;
         a.src = src;
         a.csnap = at<float>(off_cs);
         a.part = measure ? at<double>(off_part) : nullptr;
-        a.N = N;
+        a.nent = nent;
         a.nx = P.nx;
         a.ny = P.ny;
         a.nz = P.nz;
@@ -321,21 +356,25 @@ struct lbm19_solver {
         a.ab_out = ab_out;
         a.c_in = P.params.c_in;
         a.c_out = P.params.c_out;
+        a.react_outlet = react ? 1 : 0;
+        a.open_inlet = potential ? 0 : 1;
         return a;
     }
 
     hipError_t launch(bool measure) {
         const D19Args a = args(measure);
-        if (react) {
-            if (measure)
-                k_d3q19<true, true><<<nblk, kBlock, 0, st>>>(a);
-            else
-                k_d3q19<true, false><<<nblk, kBlock, 0, st>>>(a);
-        } else {
-            if (measure)
-                k_d3q19<false, true><<<nblk, kBlock, 0, st>>>(a);
-            else
-                k_d3q19<false, false><<<nblk, kBlock, 0, st>>>(a);
+        if (nblk > 0) {
+            if (react) {
+                if (measure)
+                    k_d3q19<true, true><<<nblk, kBlock, 0, st>>>(a);
+                else
+                    k_d3q19<true, false><<<nblk, kBlock, 0, st>>>(a);
+            } else {
+                if (measure)
+                    k_d3q19<false, true><<<nblk, kBlock, 0, st>>>(a);
+                else
+                    k_d3q19<false, false><<<nblk, kBlock, 0, st>>>(a);
+            }
         }
         hipError_t e = hipGetLastError();
         if (e == hipSuccess && measure) {
@@ -419,15 +458,13 @@ static int create19(const lbm_grid *g, const uint8_t *phase, const lbm_params *p
             }
         }
         s->N = (int64_t)P.nx * P.ny * P.nz;
-        // one lattice below 4 GiB: byte offsets in 32 bits
-        if ((s->N + 63) / 64 * 64 * kQ * 4 >= ((int64_t)1 << 32)) return LBM_ERR_INVALID_ARG;
-        s->nblk = (int)((s->N + kBlock - 1) / kBlock);
+        s->nbd = (int)((s->N + kBlock - 1) / kBlock);
         s->d0_lat = (P.params.tau_ref - 0.5) * P.d0 / (3.0 * P.d_ref);
         s->ab_in = 2.0 * (P.params.c_in - P.sh0);
         s->ab_out = 2.0 * (P.params.c_out - (P.sh0 - P.slope * (P.nx - 1)));
         const int nx = P.nx, ny = P.ny, nz = P.nz;
+        // dense bits: missing pull sources, open face links, simulated (the potential solve reads them)
         s->mask.assign(s->N, 0u);
-        s->kn.assign(s->react ? s->N : 0, 0.f);
         for (int z = 0; z < nz; ++z)
             for (int y = 0; y < ny; ++y)
                 for (int x = 0; x < nx; ++x) {
@@ -444,28 +481,80 @@ static int create19(const lbm_grid *g, const uint8_t *phase, const lbm_params *p
                             m |= 1u << (24 + FACE_SLOT[i]);
                     }
                     s->mask[v] = m;
-                    if (s->react && ((P.params.reactive_fluids >> P.phase[v]) & 1u))
-                        s->kn[v] = (float)(P.params.k_lat * P.n_cat[v]);
                 }
-        // workspace: two lattices, mask, omega, k n, C snapshot, partials, result
+        // compact order (x fastest), segment masks and prefixes
+        const int nsx = (nx + 63) / 64;
+        const int64_t nseg = (int64_t)nsx * ny * nz;
+        std::vector<uint64_t> segm(nseg, 0ull);
+        std::vector<uint32_t> segp(nseg, 0u);
+        s->cidx.assign(s->N, -1);
+        int64_t nf = 0;
+        for (int64_t row = 0; row < (int64_t)ny * nz; ++row)
+            for (int sx = 0; sx < nsx; ++sx) {
+                const int64_t g = row * nsx + sx;
+                segp[g] = (uint32_t)nf;
+                for (int l = 0; l < 64 && sx * 64 + l < nx; ++l) {
+                    const int64_t v = row * nx + sx * 64 + l;
+                    if (!P.active[v]) continue;
+                    segm[g] |= 1ull << l;
+                    s->cidx[v] = (int32_t)nf++;
+                }
+            }
+        s->nf = nf;
+        s->stride = (nf + 63) / 64 * 64;
+        // one lattice below 4 GiB: byte offsets in 32 bits
+        if ((int64_t)kQ * 4 * std::max<int64_t>(s->stride, 64) >= ((int64_t)1 << 32)) return LBM_ERR_INVALID_ARG;
+        s->rec.assign(nseg, D19Rec{});
+        s->list.clear();
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int sx = 0; sx < nsx; ++sx) {
+                    const int64_t g = ((int64_t)z * ny + y) * nsx + sx;
+                    D19Rec &R = s->rec[g];
+                    R.s = (uint16_t)sx;
+                    R.y = (uint16_t)y;
+                    R.z = (uint16_t)z;
+                    for (int k = 0; k < 9; ++k) {
+                        const int ry = k / 3 - 1, rz = k % 3 - 1;
+                        const int64_t gr = ((int64_t)wrapi(z + rz, nz) * ny + wrapi(y + ry, ny)) * nsx + sx;
+                        R.m[k] = segm[gr];
+                        R.pre[k] = segp[gr];
+                        if (sx > 0 && ((segm[gr - 1] >> 63) & 1ull)) R.edges |= 1u << (2 * k);
+                        if (sx + 1 < nsx && (segm[gr + 1] & 1ull)) R.edges |= 1u << (2 * k + 1);
+                    }
+                    if (segm[g]) s->list.push_back((uint32_t)g);
+                }
+        s->nent = (int64_t)s->list.size();
+        s->nblk = (int)((s->nent + kBlock / 64 - 1) / (kBlock / 64));
+        s->om_c.assign(std::max<int64_t>(nf, 1), 0.f);
+        s->kn_c.assign(s->react ? std::max<int64_t>(nf, 1) : 0, 0.f);
+        for (int64_t v = 0; v < s->N; ++v) {
+            const int32_t j = s->cidx[v];
+            if (j < 0) continue;
+            s->om_c[j] = P.omega_dense[v];
+            if (s->react && ((P.params.reactive_fluids >> P.phase[v]) & 1u))
+                s->kn_c[j] = (float)(P.params.k_lat * P.n_cat[v]);
+        }
+        // workspace: two lattices, the dense bits and compact map, records, list,
+        // 1/tau, k n, C snapshot, partials, result
         size_t o = 0;
-        const size_t fb = align256(sizeof(float) * kQ * 64 * (size_t)((s->N + 63) / 64)), nb4 = align256(4 * (size_t)s->N);
-        s->off_f[0] = o;
-        o += fb;
-        s->off_f[1] = o;
-        o += fb;
-        s->off_mask = o;
-        o += nb4;
-        s->off_om = o;
-        o += nb4;
-        s->off_kn = o;
-        o += s->react ? nb4 : 0;
-        s->off_cs = o;
-        o += nb4;
-        s->off_part = o;
-        o += align256(sizeof(double) * kRed * (size_t)s->nblk);
-        s->off_red = o;
-        o += align256(sizeof(double) * kRed);
+        auto take = [&](size_t bytes) {
+            const size_t r = o;
+            o += align256(std::max<size_t>(bytes, 1));
+            return r;
+        };
+        const size_t fb = sizeof(float) * kQ * (size_t)std::max<int64_t>(s->stride, 64);
+        s->off_f[0] = take(fb);
+        s->off_f[1] = take(fb);
+        s->off_mask = take(4 * (size_t)s->N);
+        s->off_cidx = take(4 * (size_t)s->N);
+        s->off_rec = take(sizeof(D19Rec) * (size_t)nseg);
+        s->off_list = take(4 * std::max<size_t>(s->list.size(), 1));
+        s->off_om = take(4 * (size_t)std::max<int64_t>(nf, 1));
+        s->off_kn = s->react ? take(4 * (size_t)std::max<int64_t>(nf, 1)) : 0;
+        s->off_cs = take(4 * (size_t)std::max<int64_t>(nf, 1));
+        s->off_part = take(sizeof(double) * kRed * (size_t)std::max(s->nblk, 1));
+        s->off_red = take(sizeof(double) * kRed);
         s->need = o;
         *out = s.release();
         return LBM_OK;
@@ -480,14 +569,17 @@ namespace {
 // ---- coupled oxygen / proton-potential problem (Eqs. 15-18b, Tafel Eq. 17b)
 
 // O2 sink of each reaction site from the potential: k n = k_ref n exp(beta (phi - phi_ref))
-__global__ __launch_bounds__(kBlock) void k_cpl_rate(float *__restrict__ kn_o2, const float *__restrict__ n_site,
-                                                     const float *__restrict__ phi, int64_t Ns, int nx, int nx_o,
-                                                     int off, double k_ref, double beta, double phi_ref) {
+__global__ __launch_bounds__(kBlock) void k_cpl_rate(float *__restrict__ kn_o2, const int32_t *__restrict__ cidx_o2,
+                                                     const float *__restrict__ n_site, const float *__restrict__ phi,
+                                                     int64_t Ns, int nx, int nx_o, int off, double k_ref, double beta,
+                                                     double phi_ref) {
     const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (v >= Ns) return;
     const int64_t row = v / nx, x = v - row * nx;
+    const int32_t j = cidx_o2[row * nx_o + x + off];
+    if (j < 0) return;
     const double n = (double)n_site[v];
-    kn_o2[row * nx_o + x + off] = n > 0.0 ? (float)(k_ref * n * exp(beta * ((double)phi[v] - phi_ref))) : 0.f;
+    kn_o2[j] = n > 0.0 ? (float)(k_ref * n * exp(beta * ((double)phi[v] - phi_ref))) : 0.f;
 }
 
 // proton source of each site (Eq. 18b) from C and the potential, as the LBM source
@@ -805,13 +897,15 @@ int lbm19_bind(lbm19_solver *s, void *ws, size_t bytes, void *stream) {
     s->ws = static_cast<char *>(ws);
     s->st = static_cast<hipStream_t>(stream);
     hipError_t e = hipGetDevice(&s->device);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(s->at<uint32_t>(s->off_mask), s->mask.data(), 4 * (size_t)s->N, hipMemcpyHostToDevice, s->st);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(s->at<float>(s->off_om), s->P.omega_dense.data(), 4 * (size_t)s->N, hipMemcpyHostToDevice,
-                           s->st);
-    if (e == hipSuccess && s->react)
-        e = hipMemcpyAsync(s->at<float>(s->off_kn), s->kn.data(), 4 * (size_t)s->N, hipMemcpyHostToDevice, s->st);
+    auto up = [&](size_t off, const void *src, size_t n) {
+        if (e == hipSuccess && n) e = hipMemcpyAsync(s->ws + off, src, n, hipMemcpyHostToDevice, s->st);
+    };
+    up(s->off_mask, s->mask.data(), 4 * s->mask.size());
+    up(s->off_cidx, s->cidx.data(), 4 * s->cidx.size());
+    up(s->off_rec, s->rec.data(), sizeof(D19Rec) * s->rec.size());
+    up(s->off_list, s->list.data(), 4 * s->list.size());
+    up(s->off_om, s->om_c.data(), 4 * s->om_c.size());
+    if (s->react) up(s->off_kn, s->kn_c.data(), 4 * s->kn_c.size());
     if (e == hipSuccess) e = hipStreamSynchronize(s->st);
     if (e != hipSuccess) {
         s->ws = nullptr;
@@ -823,10 +917,9 @@ int lbm19_bind(lbm19_solver *s, void *ws, size_t bytes, void *stream) {
 int lbm19_set_initial_concentration(lbm19_solver *s, const float *c_dev) {
     if (!s) return LBM_ERR_INVALID_ARG;
     if (!s->ws) return LBM_ERR_UNBOUND;
-    const int nb = (int)((s->N + kBlock - 1) / kBlock);
     s->cur = 0;
-    k_d3q19_init<<<nb, kBlock, 0, s->st>>>(s->at<float>(s->off_f[0]), s->at<uint32_t>(s->off_mask), c_dev,
-                                           s->at<float>(s->off_cs), s->N, s->P.nx, s->P.sh0, s->P.slope);
+    k_d3q19_init<<<s->nbd, kBlock, 0, s->st>>>(s->at<float>(s->off_f[0]), s->at<int32_t>(s->off_cidx), c_dev,
+                                               s->at<float>(s->off_cs), s->N, s->P.nx, s->P.sh0, s->P.slope);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s->st);
     s->steps = 0;
@@ -935,9 +1028,8 @@ int lbm19_reaction_rate(const lbm19_solver *s, double *rate, double *jin) {
 int lbm19_get_populations(const lbm19_solver *s, double *f_dev) {
     if (!s || !f_dev) return LBM_ERR_INVALID_ARG;
     if (!s->ws) return LBM_ERR_UNBOUND;
-    const int nb = (int)((s->N + kBlock - 1) / kBlock);
-    k_d3q19_unshift<<<nb, kBlock, 0, s->st>>>(s->at<float>(s->off_f[s->cur]), s->at<uint32_t>(s->off_mask), f_dev,
-                                              s->N, s->P.nx, s->P.sh0, s->P.slope);
+    k_d3q19_unshift<<<s->nbd, kBlock, 0, s->st>>>(s->at<float>(s->off_f[s->cur]), s->at<int32_t>(s->off_cidx), f_dev,
+                                                  s->N, s->P.nx, s->P.sh0, s->P.slope);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s->st);
     return e == hipSuccess ? LBM_OK : cl::record_error(e, "lbm19_get_populations");
@@ -946,10 +1038,9 @@ int lbm19_get_populations(const lbm19_solver *s, double *f_dev) {
 int lbm19_concentration(const lbm19_solver *s, float *c_dev) {
     if (!s || !c_dev) return LBM_ERR_INVALID_ARG;
     if (!s->ws) return LBM_ERR_UNBOUND;
-    const int nb = (int)((s->N + kBlock - 1) / kBlock);
-    k_d3q19_conc<<<nb, kBlock, 0, s->st>>>(s->at<float>(s->off_f[s->cur]), s->at<uint32_t>(s->off_mask),
-                                           s->react ? s->at<float>(s->off_kn) : nullptr, s->src, c_dev, s->N,
-                                           s->P.nx, s->P.sh0, s->P.slope);
+    k_d3q19_conc<<<s->nbd, kBlock, 0, s->st>>>(s->at<float>(s->off_f[s->cur]), s->at<int32_t>(s->off_cidx),
+                                               s->react ? s->at<float>(s->off_kn) : nullptr, s->src, c_dev, s->N,
+                                               s->P.nx, s->P.sh0, s->P.slope);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s->st);
     return e == hipSuccess ? LBM_OK : cl::record_error(e, "lbm19_concentration");
@@ -1160,7 +1251,8 @@ int lbm19_coupled_run(lbm19_coupled *c, lbm_coupled_info *info) {
     int inner = LBM_OK;
     for (int it = 1; it <= cp.max_iter; ++it) {
         // O2 with the Tafel rate of the current potential
-        k_cpl_rate<<<c->nb, kBlock, 0, c->st>>>(c->o2->at<float>(c->o2->off_kn), c->at<float>(c->off_n),
+        k_cpl_rate<<<c->nb, kBlock, 0, c->st>>>(c->o2->at<float>(c->o2->off_kn), c->o2->at<int32_t>(c->o2->off_cidx),
+                                                c->at<float>(c->off_n),
                                                 c->at<float>(c->off_phi), c->Ns, c->nx, c->nx_o, c->off, cp.k_ref,
                                                 cp.beta, cp.phi_ref);
         hipError_t e = hipGetLastError();

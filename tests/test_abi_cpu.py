@@ -280,8 +280,11 @@ def test_d3q19_entry_points_on_the_host():
         assert info.d0_lat == pytest.approx((0.8 - 0.5) / 3 * info.d0 / info.d_ref, rel=1e-15)
         n = ctypes.c_size_t()
         assert L.lbm19_workspace_bytes(h, ctypes.byref(n)) == 0
-        N = 8 * 5 * 4
-        assert n.value >= 2 * 19 * 4 * N + 3 * 4 * N
+        N, nf = 8 * 5 * 4, 4 * 4 * 8
+        # two compact lattices of the simulated voxels (rounded up to 64), the dense
+        # bits and voxel-to-compact map, and compact 1/tau and C snapshot
+        assert n.value >= 2 * 19 * 4 * 128 + 2 * 4 * N + 2 * 4 * nf
+        assert n.value < 2 * 19 * 4 * N + 64 * 1024
         assert L.lbm19_step(h, 1) == lbm.ERR_UNBOUND
         assert L.lbm19_step(h, -1) == lbm.ERR_INVALID_ARG
         d = ctypes.c_double()
