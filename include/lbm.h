@@ -144,7 +144,8 @@ int lbm_create(const lbm_grid *g, const uint8_t *phase_host, const lbm_params *p
  * lbm_prep_scratch_bytes bytes, 256-byte aligned, free for other use again when
  * the call returns; stream: a hipStream_t (NULL: the null stream), synchronised
  * before the call returns.  Errors: those of lbm_create, LBM_ERR_WORKSPACE for a
- * missing, small or misaligned scratch, LBM_ERR_HIP for a failed device call.
+ * missing, small or misaligned scratch, LBM_ERR_HIP for a failed device call
+ * (lbm_last_error names it).
  * lbm_batch_create_device is the same for lbm_batch_create: instances are
  * prepared on parallel host threads that take turns on the device.
  * lbm_prep_scratch_bytes: the scratch these calls need for n structures (the

@@ -841,13 +841,20 @@ int lbm_prep_scratch_bytes(int32_t n, const lbm_grid *grids, const lbm_params *p
 static int create_device(int32_t n, const lbm_grid *grids, const uint8_t *const *phases, const lbm_params *params,
                          void *scratch, size_t bytes, void *stream, std::unique_ptr<cl::Engine> &E) {
     if (!scratch || (reinterpret_cast<uintptr_t>(scratch) & 255)) return LBM_ERR_WORKSPACE;
+    if (n <= 0 || n > 65535 || !grids || !phases || !params) return LBM_ERR_INVALID_ARG;
+    size_t need = 0;
+    for (int i = 0; i < n; ++i) {
+        if (grids[i].nx <= 0 || grids[i].ny <= 0 || grids[i].nz <= 0) return LBM_ERR_INVALID_ARG;
+        need = std::max(need, cl::prep_scratch_bytes(grids[i], params[i]));
+    }
+    if (bytes < need) return LBM_ERR_WORKSPACE;  // before any device call
+    cl::g_last_error[0] = 0;
     std::mutex mu;
     cl::DeviceAssist d;
     d.scratch = scratch;
     d.bytes = bytes;
     d.stream = stream;
     d.mu = &mu;
-    cl::g_last_error[0] = 0;
     return cl::make_engine(n, grids, phases, params, E, &d);
 }
 

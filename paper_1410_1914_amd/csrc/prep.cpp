@@ -15,6 +15,9 @@
 #include <numeric>
 
 namespace cl {
+
+int record_error(hipError_t e, const char *where);  // the engine's error record (lbm_last_error)
+
 namespace {
 
 constexpr double kR = 8.314;  // J/(mol K), as used with Eq. (8)
@@ -77,22 +80,20 @@ ScratchParts scratch_parts(int64_t Ns, int64_t N) {
     return s;
 }
 
-int dev_status(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_ERR_HIP; }
-
 int device_pore_size(const DeviceAssist &d, int nx, int ny, int nz, const std::vector<uint8_t> &pore,
                      std::vector<double> &dp, const ScratchParts &sp) {
     const int64_t N = (int64_t)nx * ny * nz;
     hipStream_t st = static_cast<hipStream_t>(d.stream);
     char *base = static_cast<char *>(d.scratch);
     hipError_t e = hipMemcpyAsync(base + sp.pore, pore.data(), (size_t)N, hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return LBM_ERR_HIP;
+    if (e != hipSuccess) return record_error(e, "device pore size: upload");
     const int s = lbm_pore_size_device(reinterpret_cast<const uint8_t *>(base + sp.pore), nx, ny, nz,
                                        reinterpret_cast<double *>(base + sp.dp), d.stream);
     if (s != LBM_OK) return s;
     dp.resize((size_t)N);
     e = hipMemcpyAsync(dp.data(), base + sp.dp, sizeof(double) * (size_t)N, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    return dev_status(e);
+    return record_error(e, "device pore size: download");
 }
 
 // hit = pass voxels connected to the x = 0 face (faces & 1) and/or x = nx - 1 (faces & 2)
@@ -103,14 +104,14 @@ int device_reach(const DeviceAssist &d, int nx, int ny, int nz, const std::vecto
     char *base = static_cast<char *>(d.scratch);
     hipError_t e = hipSuccess;
     if (upload) e = hipMemcpyAsync(base + sp.pass, pass.data(), (size_t)N, hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return LBM_ERR_HIP;
+    if (e != hipSuccess) return record_error(e, "device reach: upload");
     const int s = lbm_reach_device(reinterpret_cast<const uint8_t *>(base + sp.pass), nx, ny, nz, faces,
                                    reinterpret_cast<uint8_t *>(base + sp.hit), nullptr, d.stream);
     if (s != LBM_OK) return s;
     hit.resize((size_t)N);
     e = hipMemcpyAsync(hit.data(), base + sp.hit, (size_t)N, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    return dev_status(e);
+    return record_error(e, "device reach: download");
 }
 
 }  // namespace

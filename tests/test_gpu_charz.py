@@ -175,3 +175,37 @@ def test_device_preparation_of_the_256_cube():
     assert ia.n_active == ib.n_active
     for x, y in zip(fa, fb):
         assert np.array_equal(x, y)
+
+
+_FIRST_USE = r"""
+import sys
+sys.path.insert(0, sys.argv[1])
+import numpy as np
+import structgen as sg
+from oracle import lbm as O
+from paper_1410_1914_amd import lbm as hip
+
+hip.require_gpu()
+ph = sg.npmc_cl(1, n=256)
+p = hip.lbm_params_default(mode=1, knudsen=1, k_lat=1e-4, catalyst_phases=(1 << O.CARBON) | (1 << O.PT))
+b = hip.lbm_create(ph, p, 1e-9, device_prep=True)  # the process's first device call
+a = hip.lbm_create(ph, p, 1e-9)
+fa, fb = hip.lbm_get_host_fields(a), hip.lbm_get_host_fields(b)
+assert all(np.array_equal(x, y) for x, y in zip(fa, fb))
+print("first-use device preparation: OK,", hip.lbm_get_info(b).n_active, "simulated voxels", flush=True)
+"""
+
+
+def test_device_preparation_as_the_first_device_call_of_a_process():
+    """The 256^3 benchmark structure prepared with device assistance as the very
+    first device work of a fresh process (no earlier copy or kernel has set up the
+    runtime), bit-identical to the host route."""
+    import os
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", _FIRST_USE, root], capture_output=True, text=True, timeout=600)
+    print(r.stdout[-2000:], r.stderr[-2000:], flush=True)
+    assert r.returncode == 0
+    assert "first-use device preparation: OK" in r.stdout
