@@ -80,9 +80,12 @@ def log(*a):
 
 
 def kernel_source_hash():
+    """Hash of the step kernel's source and of the engine that orders its work
+    (the order of the segment list decides how much of the traffic the L2 keeps)."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_1410_1914_amd", "csrc", "kernels.hip"), "rb") as fh:
-        h.update(fh.read())
+    for name in ("kernels.hip", "engine.hip"):
+        with open(os.path.join(ROOT, "paper_1410_1914_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 

@@ -78,7 +78,10 @@ struct Engine {
     float *csnap = nullptr;
     int cur = 0;
 
+    static constexpr int kXcds = 8;  // MI355X: 8 XCDs, each with its own L2
     int waves = 4, spw = 1, xcd = 1;
+    // Rows per y slab of the one-instance step list (0: grid order); set at creation.
+    int slab_rows = 0;
     // Alternate the direction in which one-step launches walk the segment list.
     int alt_order = 1;
     // Two steps per launch (one instance only): rows per tile (0 = off), planes per chunk.
@@ -188,6 +191,24 @@ struct Engine {
                     sb.push_back((uint32_t)(seg_base[i] + g));
                     if (ninst > 1) si.push_back((uint32_t)i);
                 }
+        }
+        // One instance: walk it as kXcds slabs of consecutive rows in y, each slab
+        // plane by plane in z.  With the XCD-aware block order each XCD then steps
+        // one slab, and the rows a segment pulls from (y -+ 1 in its plane, the
+        // same row in z -+ 1) were touched a slab plane earlier, a few hundred
+        // segments back, still in that XCD's L2.  In grid order an XCD steps a slab
+        // of whole planes, and the plane before is too far back for its L2.
+        if (live.size() == 1 && slab_rows > 0) {
+            const Prepared &p = P[live[0]];
+            const int64_t nsx = p.nsx, ny = p.ny;
+            const int64_t base = seg_base[live[0]], yb = slab_rows;
+            const int64_t per_slab = (int64_t)p.nz * yb * nsx;
+            auto key = [&](uint32_t gs) {
+                const int64_t g = (int64_t)gs - base;
+                const int64_t sx = g % nsx, y = (g / nsx) % ny, z = g / (nsx * ny);
+                return (y / yb) * per_slab + (z * yb + y % yb) * nsx + sx;
+            };
+            std::sort(sb.begin(), sb.end(), [&](uint32_t a, uint32_t b) { return key(a) < key(b); });
         }
         step_nent = (int)sb.size();
         const int per = waves * spw;
@@ -752,6 +773,9 @@ int make_engine(int n, const lbm_grid *grids, const uint8_t *const *phases, cons
     E->knudsen = E->P[0].knudsen;
     E->react = E->mode == LBM_MODE_REACT;
     E->check_every = params[0].check_every;
+    // one y slab of the step list per XCD, when the slabs are at least two rows
+    if (n == 1 && E->P[0].ny >= 2 * Engine::kXcds)
+        E->slab_rows = (E->P[0].ny + Engine::kXcds - 1) / Engine::kXcds;
     E->layout();
     // segment indices are 32-bit; population byte offsets are 32-bit (buffer resources)
     if (E->nseg_total > (int64_t)INT32_MAX || 28 * E->stride >= ((int64_t)1 << 32) - 64) return LBM_ERR_INVALID_ARG;

@@ -357,7 +357,15 @@ def test_predict_is_features_forward_and_inverse_target(U):
 
 def test_train_step_is_forward_backward_adam(U):
     """unet_train_step equals unet_forward, unet_mse, unet_backward and
-    unet_adam_step called one by one (two networks from the same parameters)."""
+    unet_adam_step called one by one (two networks from the same parameters).
+
+    The weight gradients and the loss are sums over voxels that thread blocks add
+    with FP32 atomics, so their last bits depend on the order the blocks finish in
+    and two runs need not be bit-identical.  Adam turns a gradient into a step of
+    +-lr whatever its size, so a rounding-level difference moves a parameter by
+    rounding only, except where the gradient itself is at rounding level and its
+    sign can flip: almost every parameter must agree to 1e-7, and none may differ by
+    more than two steps."""
     import torch
 
     rng = np.random.default_rng(23)
@@ -376,8 +384,10 @@ def test_train_step_is_forward_backward_adam(U):
         b.backward(feat, g, shape)
         b.adam_step(shape, 1e-3)
         torch.cuda.synchronize()
-        assert torch.equal(la, lb), step
-        assert torch.equal(a.params, b.params), step
+        assert float(la) == pytest.approx(float(lb), rel=1e-6), step
+        d = (a.params - b.params).abs()
+        assert float(d.max()) <= 2 * 2e-3, step
+        assert float((d > 1e-7).float().mean()) < 1e-3, step
     assert a.t == b.t == 2
     # a step moved the parameters
     assert not torch.equal(a.params, U.UNet(seed=7).params)
