@@ -524,6 +524,18 @@ static int create19(const lbm_grid *g, const uint8_t *phase, const lbm_params *p
                     }
                     if (segm[g]) s->list.push_back((uint32_t)g);
                 }
+        // Walk the list as four y slabs, each plane by plane: with the XCD-aware block
+        // order each XCD then steps half a slab, and the rows a segment pulls from
+        // (y -+ 1, z -+ 1 and the four yz diagonals) were touched a slab plane
+        // earlier, still in its L2 (4 slabs measured faster than 8 or 16 here).
+        if (ny >= 8) {
+            const int64_t yb = (ny + 3) / 4, per_slab = (int64_t)nz * yb * nsx;
+            auto key = [&](uint32_t g) {
+                const int64_t sx = g % nsx, y = (g / nsx) % ny, z = g / ((int64_t)nsx * ny);
+                return (y / yb) * per_slab + (z * yb + y % yb) * nsx + sx;
+            };
+            std::sort(s->list.begin(), s->list.end(), [&](uint32_t a, uint32_t b) { return key(a) < key(b); });
+        }
         s->nent = (int64_t)s->list.size();
         s->nblk = (int)((s->nent + kBlock / 64 - 1) / (kBlock / 64));
         s->om_c.assign(std::max<int64_t>(nf, 1), 0.f);
