@@ -98,21 +98,9 @@ def algorithmic_bytes(info, knudsen: bool) -> float:
 
 def metadata_bytes(n_listed: int) -> float:
     """Bytes of the layout's own bookkeeping per launch, reported apart from the
-    algorithmic bytes: per listed 64-voxel segment its 120-byte record and 4-byte
-    list entry."""
+    algorithmic bytes: per listed segment (a window of up to 64 voxels, one wave)
+    its 120-byte record and 4-byte list entry."""
     return n_listed * 124.0
-
-
-def listed_segments(active):
-    """Number of 64-voxel row segments holding at least one simulated voxel: the
-    segments the stream-collide launch visits (one wave each)."""
-    import numpy as np
-
-    nz, ny, nx = active.shape
-    nsx = (nx + 63) // 64
-    pad = np.zeros((nz, ny, nsx * 64), bool)
-    pad[:, :, :nx] = active.astype(bool)
-    return int(pad.reshape(nz, ny, nsx, 64).any(axis=3).sum())
 
 
 def traffic_from_profiles(kernel_sha: str, workload: str):
@@ -172,7 +160,7 @@ def headline(args, lbm, structgen):
     per_launch_s = kms / 1e3 / steps_timed * spl
     # one launch, of either form, must read and write the lattice once
     alg = algorithmic_bytes(info, knudsen=True)
-    meta = metadata_bytes(listed_segments(s.host_fields()[0]))
+    meta = metadata_bytes(info.n_listed)
     achieved = alg / per_launch_s / 1e9
     log(f"[bench] {steps_timed} LBM steps in {wall:.3f}s: {mlups:.0f} MLUPS; kernel mean {per_launch_s*1e6:.1f} us "
         f"per launch ({spl} step(s)), {achieved:.0f} GB/s algorithmic")

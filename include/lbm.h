@@ -117,12 +117,17 @@ typedef struct {
     int32_t nx, ny, nz;    /* simulated grid (REACT with reservoir: nx + 1)       */
     int32_t nx_struct;     /* structure size along x                              */
     int64_t n_active;      /* simulated voxels (transport, connected)             */
-    int64_t n_segments;    /* 64-voxel row segments of the simulated grid         */
+    int64_t n_segments;    /* segments: windows of up to 64 voxels consecutive in
+                              grid order, each row cut into its own windows, or
+                              (rows of 64 k + 1 voxels) windows running on across
+                              row ends within a plane                              */
     double d0;             /* D0 (m^2/s; 1 in proton mode)                        */
     double d_ref;          /* D_ref (same units)                                  */
     double d0_lat;         /* D0 in lattice units                                 */
     int32_t percolates;    /* transport path joins the Dirichlet faces            */
     int32_t mode;
+    int64_t n_listed;      /* segments holding simulated voxels: the waves of one
+                              stream-collide launch                                */
 } lbm_info;
 
 /* Fill *p with the defaults listed above.  Returns LBM_ERR_INVALID_ARG on NULL. */
@@ -230,7 +235,9 @@ int lbm_autotune(lbm_solver *s, int32_t steps_per_trial, double *ms_best);
  * are rounded to FP32 exactly as a stored lattice is, so the results are
  * bit-identical to two single-step launches.  rows_per_tile 0 returns to one step
  * per launch (the default); an odd step count ends with one single-step launch.
- * Returns LBM_ERR_INVALID_ARG for other values. */
+ * Returns LBM_ERR_INVALID_ARG for other values, and for rows_per_tile > 0 on a
+ * grid whose rows are 64 k + 1 voxels long (its segments run across row ends,
+ * see lbm_info.n_segments; the tiles need each row cut into its own). */
 int lbm_set_temporal(lbm_solver *s, int32_t rows_per_tile, int32_t planes_per_chunk);
 int lbm_get_temporal(const lbm_solver *s, int32_t *rows_per_tile, int32_t *planes_per_chunk);
 

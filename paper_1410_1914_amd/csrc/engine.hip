@@ -200,13 +200,12 @@ struct Engine {
         // of whole planes, and the plane before is too far back for its L2.
         if (live.size() == 1 && slab_rows > 0) {
             const Prepared &p = P[live[0]];
-            const int64_t nsx = p.nsx, ny = p.ny;
+            const int64_t nx = p.nx, ny = p.ny, nz = p.nz, plane = ny * nx;
             const int64_t base = seg_base[live[0]], yb = slab_rows;
-            const int64_t per_slab = (int64_t)p.nz * yb * nsx;
-            auto key = [&](uint32_t gs) {
-                const int64_t g = (int64_t)gs - base;
-                const int64_t sx = g % nsx, y = (g / nsx) % ny, z = g / (nsx * ny);
-                return (y / yb) * per_slab + (z * yb + y % yb) * nsx + sx;
+            auto key = [&](uint32_t gs) {  // (slab of the window's first row, plane, grid index)
+                const int64_t v0 = p.win_v0[(int64_t)gs - base];
+                const int64_t row = v0 / nx, y = row % ny, z = row / ny;
+                return ((y / yb) * nz + z) * plane + (v0 - z * plane);
             };
             std::sort(sb.begin(), sb.end(), [&](uint32_t a, uint32_t b) { return key(a) < key(b); });
         }
@@ -237,33 +236,61 @@ struct Engine {
         return e;
     }
 
-    // Segment records of instance i (see SegRec): masks and compact prefixes of the
-    // segment and of its four neighbour rows, and the reaction bit planes.
+    // Segment records of instance i (see SegRec and Prepared): masks and compact
+    // prefixes of the window and of its four neighbour windows (the same lanes
+    // moved one row in y or one plane in z, periodic), and the reaction bit planes.
     void build_records(int i, SegRec *out) const {
         const Prepared &p = P[i];
-        const int nsx = p.nsx, ny = p.ny, nz = p.nz;
-        const int64_t rs = nsx, ps = (int64_t)ny * nsx;
+        const int nx = p.nx, ny = p.ny, nz = p.nz;
+        const int64_t N = (int64_t)nx * ny * nz, plane = (int64_t)ny * nx;
+        // the fluid map as a bit string in grid order, and its rank per word
+        const int64_t nw = N / 64 + 2;
+        std::vector<uint64_t> fb(nw, 0ull);
+        std::vector<int64_t> rank(nw, 0);
+        for (int64_t v = 0; v < N; ++v)
+            if (p.active[v]) fb[v >> 6] |= 1ull << (v & 63);
+        for (int64_t w = 1; w < nw; ++w) rank[w] = rank[w - 1] + __builtin_popcountll(fb[w - 1]);
+        auto bits = [&](int64_t pos, int len) {  // fluid bits of grid indices pos .. pos + len - 1
+            const int64_t w = pos >> 6;
+            const int sh = (int)(pos & 63);
+            uint64_t v = fb[w] >> sh;
+            if (sh) v |= fb[w + 1] << (64 - sh);
+            return len >= 64 ? v : v & ((1ull << len) - 1ull);
+        };
+        auto rank_at = [&](int64_t pos) {  // fluid voxels before grid index pos
+            const int sh = (int)(pos & 63);
+            return rank[pos >> 6] + (sh ? __builtin_popcountll(fb[pos >> 6] & ((1ull << sh) - 1ull)) : 0);
+        };
         for (int64_t g = 0; g < p.nseg; ++g) {
             SegRec r{};
-            const int s = (int)(g % nsx);
-            const int64_t row = g / nsx;
-            const int y = (int)(row % ny), z = (int)(row / ny);
+            const int64_t v0 = p.win_v0[g];
+            const int len = p.win_len[g];
+            const int64_t row = v0 / nx;
+            const int x0 = (int)(v0 - row * nx), y = (int)(row % ny), z = (int)(row / ny);
+            const int brk = x0 + len > nx ? nx - x0 : 64;  // first lane of the next row
             const uint64_t m = p.m_fluid[g];
-            const uint64_t mp = s > 0 ? p.m_fluid[g - 1] : 0ull;
-            const uint64_t mn = s + 1 < nsx ? p.m_fluid[g + 1] : 0ull;
-            const int64_t gn[4] = {g + (y == 0 ? (int64_t)(ny - 1) * rs : -rs), g + (y == ny - 1 ? -(int64_t)(ny - 1) * rs : rs),
-                                   g + (z == 0 ? (int64_t)(nz - 1) * ps : -ps), g + (z == nz - 1 ? -(int64_t)(nz - 1) * ps : ps)};
+            const uint64_t inside = len >= 64 ? ~0ull : (1ull << len) - 1ull;
+            // lanes at x = 0 and at x = nx - 1
+            uint64_t at0 = 0ull, at1 = 0ull;
+            if (x0 == 0) at0 |= 1ull;
+            if (brk < len) at0 |= 1ull << brk;
+            if (nx - 1 - x0 < len) at1 |= 1ull << (nx - 1 - x0);
+            const uint64_t before = (m << 1) | (v0 > 0 ? (fb[(v0 - 1) >> 6] >> ((v0 - 1) & 63)) & 1ull : 0ull);
+            const uint64_t after = (m >> 1) | (v0 + len < N ? ((fb[(v0 + len) >> 6] >> ((v0 + len) & 63)) & 1ull) << (len - 1) : 0ull);
             r.m = m;
-            r.left = (m << 1) | (mp >> 63);
-            r.right = (m >> 1) | (mn << 63);
+            r.left = before & inside & ~at0;
+            r.right = after & inside & ~at1;
+            const int64_t off[4] = {y == 0 ? (int64_t)(ny - 1) * nx : -(int64_t)nx,
+                                    y == ny - 1 ? -(int64_t)(ny - 1) * nx : (int64_t)nx,
+                                    z == 0 ? (int64_t)(nz - 1) * plane : -plane,
+                                    z == nz - 1 ? -(int64_t)(nz - 1) * plane : plane};
             for (int k = 0; k < 4; ++k) {
-                r.nb[k] = p.m_fluid[gn[k]];
-                r.pnb[k] = (uint32_t)(fluid_base[i] + p.prefix[gn[k]]);
+                r.nb[k] = bits(v0 + off[k], len);
+                r.pnb[k] = (uint32_t)(fluid_base[i] + rank_at(v0 + off[k]));
             }
             r.ion = p.m_ion[g];
             const uint64_t mr = p.m_react[g];
-            const int64_t v0 = row * p.nx + (int64_t)s * kSeg;
-            for (int l = 0; l < kSeg && s * kSeg + l < p.nx; ++l) {
+            for (int l = 0; l < len; ++l) {
                 if (!((mr >> l) & 1ull)) continue;
                 const int n = p.n_cat[v0 + l];
                 if (n & 1) r.n0 |= 1ull << l;
@@ -271,9 +298,10 @@ struct Engine {
                 if (n & 4) r.n2 |= 1ull << l;
             }
             r.pre = (uint32_t)(fluid_base[i] + p.prefix[g]);
-            r.s = (uint16_t)s;
-            r.y = (uint16_t)y;
-            r.z = (uint16_t)z;
+            r.v0 = (uint32_t)v0;
+            r.x0 = (uint16_t)x0;
+            r.brk = (uint8_t)brk;
+            r.len = (uint8_t)len;
             r.inst = (uint16_t)i;
             out[g] = r;
         }
@@ -377,6 +405,8 @@ struct Engine {
     }
 
     bool two_step() const { return t2_by > 0 && ninst == 1; }
+    // the two-step kernel tiles rows of segments: the row layout only (Prepared)
+    bool two_step_possible() const { return ninst == 1 && !P[0].flat; }
 
     Step2Launch step2_launch() const {
         const Prepared &p = P[0];
@@ -719,6 +749,8 @@ struct Engine {
         o.nx_struct = p.nx_struct;
         o.n_active = p.n_fluid;
         o.n_segments = p.nseg;
+        o.n_listed = 0;
+        for (int64_t g = 0; g < p.nseg; ++g) o.n_listed += p.m_fluid[g] != 0ull;
         o.d0 = p.d0;
         o.d_ref = p.d_ref;
         o.d0_lat = p.d0_lat;
@@ -1177,7 +1209,7 @@ static int autotune(cl::Engine &E, int32_t steps_per_trial, double *ms_best) {
                 }
             }
     // two steps per launch (one instance): rows per tile x planes per chunk x XCD order
-    if (E.ninst == 1) {
+    if (E.two_step_possible()) {
         E.spw = bs;
         E.waves = bw;
         const int bys[3] = {4, 6, 8};
@@ -1234,6 +1266,7 @@ int lbm_set_temporal(lbm_solver *s, int32_t rows_per_tile, int32_t planes_per_ch
         return LBM_ERR_INVALID_ARG;
     if (rows_per_tile && (planes_per_chunk < 1 || planes_per_chunk > 64)) return LBM_ERR_INVALID_ARG;
     cl::Engine &E = *s->E;
+    if (rows_per_tile && !E.two_step_possible()) return LBM_ERR_INVALID_ARG;
     E.t2_by = rows_per_tile;
     if (rows_per_tile) E.t2_zc = planes_per_chunk;
     E.g_valid = false;  // captured windows hold the previous form

@@ -23,19 +23,25 @@ struct alignas(64) InstDev {
     float om_pore, om_ion;    // relaxation rates when not stored per voxel
 };
 
-// Everything a wave needs to update one 64-voxel row segment (one bit per lane).
-// Built once on the host; the stream-collide kernel reads it with a few scalar
-// loads instead of recomputing neighbour rows and bit shifts per step.
+// Everything a wave needs to update one segment, a window of up to 64 voxels
+// consecutive in grid order (one bit per lane; see Prepared for the two ways the
+// grid is cut into windows).  Built once on the host; the stream-collide kernel
+// reads it with a few scalar loads instead of recomputing neighbour rows and bit
+// shifts per step.  Lane l lies at x = x0 + l, or at x = l - brk on the next row
+// for l >= brk.
 struct SegRec {
     uint64_t m;              // lanes that are simulated (fluid)
     uint64_t left, right;    // lanes whose x-1 / x+1 neighbour is fluid (x faces excluded)
-    uint64_t nb[4];          // fluid masks of the rows y-1, y+1, z-1, z+1 over the same x range
+    uint64_t nb[4];          // fluid masks of the lanes' neighbours in y-1, y+1, z-1, z+1
     uint64_t ion;            // ionomer lanes (relaxation rate from the phase)
     uint64_t n0, n1, n2;     // bit planes of n, the catalyst face-neighbour count, of reacting lanes
     uint32_t pre;            // global compact index of the first fluid lane
-    uint32_t pnb[4];         // the same for the four neighbour rows
-    uint16_t s, y, z, inst;  // segment position: x0 = 64 s, row y, plane z; its instance
-    uint32_t pad;
+    uint32_t pnb[4];         // the same for the four neighbour windows
+    uint32_t v0;             // grid index (within the instance) of lane 0
+    uint16_t x0;             // x of lane 0
+    uint8_t brk;             // first lane on the next row (64: none)
+    uint8_t len;             // lanes inside the grid
+    uint16_t inst, pad;      // instance
 };
 static_assert(sizeof(SegRec) == 120, "SegRec layout");
 

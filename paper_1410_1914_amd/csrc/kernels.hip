@@ -81,6 +81,11 @@ __device__ __forceinline__ int logical_block_reversed(int b, int nblk, int remap
     return x * q + min(x, r) + (len - 1 - (b >> 3));
 }
 
+// x of a lane of a segment (lanes from brk on lie on the next row)
+__device__ __forceinline__ int lane_x(const SegRec &R, int lane) {
+    return lane < (int)R.brk ? (int)R.x0 + lane : lane - (int)R.brk;
+}
+
 // catalyst face-neighbour count of reacting lanes, from the record's bit planes
 __device__ __forceinline__ int react_n(const SegRec &R, int lane) {
     return bit(R.n0, lane) + 2 * bit(R.n1, lane) + 4 * bit(R.n2, lane);
@@ -186,7 +191,7 @@ template <bool KNUDSEN, bool REACT>
 __device__ __forceinline__ void collide_store(const SegRec &R, const InstDev &I, __amdgpu_buffer_rsrc_t rout,
                                               int lane, const float (&r)[8], uint32_t j4) {
     float o[7];
-    collide7<REACT>(I, (int)R.s * 64 + lane, bit(R.left, lane), bit(R.right, lane), lane_omega<KNUDSEN>(R, I, r[7]),
+    collide7<REACT>(I, lane_x(R, lane), bit(R.left, lane), bit(R.right, lane), lane_omega<KNUDSEN>(R, I, r[7]),
                     REACT ? react_n(R, lane) : 0, r, o);
 #pragma unroll
     for (int i = 0; i < 7; ++i) st(o[i], rout, j4, 256u * i);
@@ -482,7 +487,7 @@ __global__ __launch_bounds__(kMeasWaves * 64) void k_measure(Lattice L, MeasureL
         if (m == 0ull) continue;
         if (!bit(m, lane)) continue;
         const int64_t j = (int64_t)R.pre + mbcnt64(m);
-        const int x = (int)R.s * 64 + lane;
+        const int x = lane_x(R, lane);
         double cs = 0.0;
 #pragma unroll
         for (int i = 0; i < 7; ++i) cs += (double)f[pidx(i, j)];
@@ -538,7 +543,7 @@ __global__ __launch_bounds__(64) void k_finish(const double *__restrict__ partia
 // ------------------------------------------------------------------ conversions
 
 // Calls fn(instance, I, dense voxel index v, compact index j or -1, catalyst count
-// of reacting lanes) for every lane of the segment whose x lies inside the grid.
+// of reacting lanes) for every lane of the segment that lies inside the grid.
 template <typename Fn>
 __device__ __forceinline__ void for_lanes(const Lattice &L, const int2 *blk, Fn fn) {
     const int lane = threadIdx.x & 63;
@@ -548,9 +553,8 @@ __device__ __forceinline__ void for_lanes(const Lattice &L, const int2 *blk, Fn 
     const int64_t sl = (int64_t)t.y + wave;
     if (sl >= I.nseg) return;
     const SegRec &R = L.rec[I.seg_base + sl];
-    const int x = (int)R.s * 64 + lane;
-    if (x >= I.nx) return;
-    const int64_t v = ((int64_t)R.z * I.ny + R.y) * I.nx + x;
+    if (lane >= (int)R.len) return;
+    const int64_t v = (int64_t)R.v0 + lane;
     const bool fluid = bit(R.m, lane);
     const int64_t j = fluid ? (int64_t)R.pre + mbcnt64(R.m) : -1;
     fn(t.x, I, v, j, (double)react_n(R, lane));

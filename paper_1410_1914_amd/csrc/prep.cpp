@@ -340,9 +340,32 @@ int prepare(const lbm_grid &g, const uint8_t *phase, const lbm_params &p, Prepar
                     return LBM_ERR_UNSTABLE;
             }
 
-    // segment bitmasks and compact indices
+    // segments (see Prepared), their bitmasks and compact indices
     o.nsx = (nx + kSeg - 1) / kSeg;
-    o.nseg = (int64_t)o.nsx * ny * nz;
+    o.flat = nx > kSeg && nx % kSeg == 1;
+    o.win_v0.clear();
+    o.win_len.clear();
+    auto tile = [&](int64_t a, int64_t b) {  // windows over grid indices [a, b)
+        for (int64_t v = a; v < b; v += kSeg) {
+            o.win_v0.push_back((uint32_t)v);
+            o.win_len.push_back((uint8_t)std::min<int64_t>(kSeg, b - v));
+        }
+    };
+    const int64_t plane = (int64_t)ny * nx;
+    if (N >= (int64_t)UINT32_MAX) return LBM_ERR_INVALID_ARG;
+    for (int z = 0; z < nz; ++z) {
+        const int64_t p0 = (int64_t)z * plane;
+        if (!o.flat) {
+            for (int64_t r = 0; r < ny; ++r) tile(p0 + r * nx, p0 + (r + 1) * nx);
+        } else {
+            // rows 0, 1 .. ny - 2 and ny - 1 apart (y wraps between them)
+            const int64_t cut1 = std::min<int64_t>(1, ny - 1), cut2 = std::max<int64_t>(cut1, ny - 1);
+            tile(p0, p0 + cut1 * nx);
+            tile(p0 + cut1 * nx, p0 + cut2 * nx);
+            tile(p0 + cut2 * nx, p0 + plane);
+        }
+    }
+    o.nseg = (int64_t)o.win_v0.size();
     o.m_fluid.assign(o.nseg, 0);
     o.m_ion.assign(o.nseg, 0);
     o.m_react.assign(o.nseg, 0);
@@ -350,10 +373,8 @@ int prepare(const lbm_grid &g, const uint8_t *phase, const lbm_params &p, Prepar
     o.prefix.assign(o.nseg, 0);
     int64_t count = 0;
     for (int64_t sg = 0; sg < o.nseg; ++sg) {
-        const int s = (int)(sg % o.nsx);
-        const int64_t row = sg / o.nsx;
-        const int64_t base = row * nx + (int64_t)s * kSeg;
-        const int len = std::min(kSeg, nx - s * kSeg);
+        const int64_t base = o.win_v0[sg];
+        const int len = o.win_len[sg];
         uint64_t mf = 0, mi = 0, mr = 0, mc = 0;
         for (int l = 0; l < len; ++l) {
             const int64_t v = base + l;

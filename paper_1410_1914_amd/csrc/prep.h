@@ -30,7 +30,16 @@ struct Prepared {
     std::vector<uint8_t> phase;  // phase ids, the reservoir plane included
     std::vector<uint8_t> active, n_cat;
     std::vector<float> omega_dense;
-    // per segment
+    // Segments: windows of up to 64 voxels consecutive in x-fastest (grid) order,
+    // one wave each.  Row layout: every row starts a window (nsx windows per row,
+    // the last one short when nx is not a multiple of 64).  Flat layout (rows of
+    // 64 k + 1 voxels, i.e. the reservoir plane's 257): windows run on across row
+    // ends, restarting only at each plane and at rows 1 and ny - 1, so a window
+    // spans at most two rows and its y and z neighbours lie at one flat offset
+    // for all its lanes; no one-voxel segment is left at the end of each row.
+    bool flat = false;
+    std::vector<uint32_t> win_v0;  // grid index of lane 0
+    std::vector<uint8_t> win_len;  // lanes inside the grid
     std::vector<uint64_t> m_fluid, m_ion, m_react, m_cat;
     std::vector<uint32_t> prefix;  // compact index of the first fluid voxel of the segment
     // compact (fluid voxels in x-fastest order)

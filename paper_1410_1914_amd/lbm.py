@@ -58,7 +58,7 @@ class lbm_info(ctypes.Structure):
     _fields_ = [("nx", c_int32), ("ny", c_int32), ("nz", c_int32), ("nx_struct", c_int32),
                 ("n_active", c_int64), ("n_segments", c_int64),
                 ("d0", c_double), ("d_ref", c_double), ("d0_lat", c_double),
-                ("percolates", c_int32), ("mode", c_int32)]
+                ("percolates", c_int32), ("mode", c_int32), ("n_listed", c_int64)]
 
 
 class lbm_coupling(ctypes.Structure):

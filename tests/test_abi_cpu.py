@@ -143,6 +143,43 @@ def test_segment_count_and_reservoir_plane():
     lbm.lbm_destroy(h)
 
 
+def _flat_windows(nx, ny, nz):
+    """Windows of the flat layout by brute force: consecutive grid indices, cut
+    at every plane start and at the starts of rows 1 and ny - 1, 64 at most."""
+    starts = set()
+    for z in range(nz):
+        for y in {0, min(1, ny - 1), max(min(1, ny - 1), ny - 1)}:
+            starts.add((z * ny + y) * nx)
+    wins, cur = [], None
+    for v in range(nx * ny * nz):
+        if v in starts or cur is None or v - cur[0] == 64:
+            cur = [v, 0]
+            wins.append(cur)
+        cur[1] += 1
+    return wins
+
+
+@pytest.mark.parametrize("shape,mode", [((5, 7, 64), 1), ((3, 1, 128), 1), ((4, 2, 64), 1), ((3, 3, 193), 0),
+                                        ((5, 7, 64), 0), ((2, 3, 130), 1)])
+def test_segment_windows_of_both_layouts(shape, mode):
+    """Rows of 64 k + 1 voxels give flat windows (counted by brute force), others
+    one window per 64 voxels of each row; n_listed counts those holding simulated
+    voxels."""
+    ph = sg.pt_cl(3, shape=shape)
+    h = lbm.lbm_create(ph, lbm.lbm_params_default(mode=mode, k_lat=0.01))
+    i = lbm.lbm_get_info(h)
+    act, _, _ = lbm.lbm_get_host_fields(h)
+    lbm.lbm_destroy(h)
+    nx, ny, nz = i.nx, i.ny, i.nz
+    if nx > 64 and nx % 64 == 1:
+        wins = _flat_windows(nx, ny, nz)
+    else:
+        wins = [[(r * nx) + s0, min(64, nx - s0)] for r in range(ny * nz) for s0 in range(0, nx, 64)]
+    assert i.n_segments == len(wins)
+    flat = act.ravel()
+    assert i.n_listed == sum(bool(flat[v0:v0 + n].any()) for v0, n in wins)
+
+
 def _depth_reference(phase_sim, active, react):
     """Breadth-first distances, written out plainly: seeds are pore voxels joined to
     a Dirichlet face through pore voxels (6-neighbours, periodic y and z)."""

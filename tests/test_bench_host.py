@@ -13,19 +13,6 @@ class _Info:
         self.n_active = n_active
 
 
-def test_listed_segments_brute_force():
-    rng = np.random.default_rng(5)
-    active = rng.random((3, 4, 150)) < 0.02
-    want = 0
-    for z in range(3):
-        for y in range(4):
-            for s0 in range(0, 150, 64):
-                want += bool(active[z, y, s0:s0 + 64].any())
-    assert bench.listed_segments(active) == want
-    assert bench.listed_segments(np.ones((2, 2, 64), bool)) == 4
-    assert bench.listed_segments(np.zeros((2, 2, 65), bool)) == 0
-
-
 def test_algorithmic_bytes():
     # 7 FP32 reads + 7 FP32 writes per fluid update, +4 B of 1/tau with Knudsen,
     # and 120 B record + 4 B list entry per visited segment

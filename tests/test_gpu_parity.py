@@ -57,6 +57,20 @@ STEP_CASES = [
 ]
 
 
+# Rows of 64 k + 1 voxels (the reservoir plane of a reactive problem on a 64 k
+# structure, or a Dirichlet grid of that length) are cut into windows that run on
+# across row ends (the flat layout): windows spanning two rows, the cuts at rows 1
+# and ny - 1 where y wraps, ny of 1, 2 and 3, and x faces inside a window.
+FLAT_CASES = [
+    ("pt", 11, (5, 7, 64), 1, dict(knudsen=1, k_lat=0.05)),
+    ("pt", 12, (3, 1, 128), 1, dict(k_lat=0.1)),
+    ("pt", 13, (4, 2, 64), 1, dict(knudsen=1, k_lat=0.02, catalyst_phases=(1 << 2) | (1 << 1))),
+    ("pt", 14, (3, 3, 193), 0, dict(knudsen=1)),
+    ("two", 5, (6, 9, 65), 0, dict(tau_ref=0.8)),
+    ("ion", 6, (5, 6, 129), 2, dict()),
+]
+
+
 def _phase(kind, seed, shape):
     if kind == "pt":
         return sg.pt_cl(seed, shape=shape)
@@ -67,7 +81,7 @@ def _phase(kind, seed, shape):
     return sg.two_phase(seed, shape=shape)
 
 
-@pytest.mark.parametrize("kind,seed,shape,mode,kw", STEP_CASES)
+@pytest.mark.parametrize("kind,seed,shape,mode,kw", STEP_CASES + FLAT_CASES)
 def test_steps_match_oracle(hip, kind, seed, shape, mode, kw):
     """Random state, n fused stream-collide steps on the GPU vs n oracle steps."""
     import torch
@@ -89,7 +103,7 @@ def test_steps_match_oracle(hip, kind, seed, shape, mode, kw):
         assert err < 2e-6, (n, err)
 
 
-@pytest.mark.parametrize("kind,seed,shape,mode,kw", STEP_CASES[:5])
+@pytest.mark.parametrize("kind,seed,shape,mode,kw", STEP_CASES[:5] + FLAT_CASES)
 def test_measure_matches_oracle(hip, kind, seed, shape, mode, kw):
     """FP64 reductions of a random state: fluxes, sink and mass."""
     import torch
@@ -134,6 +148,8 @@ STEADY_CASES = [
     ("pt", 8, (8, 9, 66), 1, dict(k_lat=0.1)),
     ("ion", 5, (8, 9, 66), 2, dict()),
     ("ion", 12, (8, 9, 66), 2, dict(tau_ref=0.8)),
+    ("pt", 8, (8, 9, 64), 1, dict(k_lat=0.1)),          # flat layout (65-voxel rows)
+    ("pt", 2, (10, 12, 65), 0, dict(knudsen=1)),
 ]
 
 
@@ -212,6 +228,7 @@ TILINGS = [(spw, w, x) for spw in (1, 2, 4) for w in (1, 2, 4, 8) for x in (0, 1
     ("pt", 3, (9, 10, 130), 1, dict(knudsen=1, k_lat=0.05)),
     ("two", 2, (12, 13, 70), 0, dict(tau_ref=0.8)),
     ("ion", 4, (8, 9, 66), 2, dict()),
+    ("pt", 15, (7, 9, 128), 1, dict(knudsen=1, k_lat=0.05)),  # flat layout
 ])
 def test_every_tiling_gives_identical_steps(hip, kind, seed, shape, mode, kw):
     """The launch forms (segments per wave, waves per block, XCD order) do the same
@@ -265,6 +282,23 @@ def test_two_step_launches_match_single_steps(hip, kind, seed, shape, mode, kw):
             s.step(n)
             got = s.populations().cpu().numpy()
             assert np.array_equal(got[:, act], ref[n][:, act]), (by, zc, n)
+
+
+def test_two_steps_per_launch_are_refused_on_the_flat_layout(hip):
+    """The two-step kernel tiles rows of segments; on a grid of 65-voxel rows
+    (flat windows) lbm_set_temporal refuses it and the solver keeps one step per
+    launch, and the autotuner does not try it."""
+    ph = _phase("pt", 11, (5, 7, 64))
+    prob, s = _both(hip, ph, 1, k_lat=0.05)
+    with pytest.raises(hip.LbmError):
+        s.set_temporal(6, 16)
+    assert s.temporal()[0] == 0
+    s.autotune(4)
+    assert s.temporal()[0] == 0
+    info = hip.lbm_get_info(s.h)
+    # windows per plane: row 0 (65 voxels: 2), rows 1..5 (325 voxels: 6), row 6 (2)
+    assert info.n_segments == 5 * (2 + 6 + 2)
+    assert info.n_listed <= info.n_segments
 
 
 def _advance(prob, f, n):
