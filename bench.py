@@ -252,7 +252,12 @@ def other_form(s, args, chosen):
     launch with a 6-row, 16-plane tile, or one step per launch), on the same state;
     the chosen form is restored afterwards."""
     alt = (0, 0) if chosen[0] else (6, 16)
-    s.set_temporal(*alt)
+    try:
+        s.set_temporal(*alt)
+    except Exception as e:  # the two-step kernel tiles rows: not on flat windows (rows of 64 k + 1)
+        log(f"[bench] other form (two steps per launch): not available on this grid ({e})")
+        return {"form": "two steps per launch", "available": False,
+                "reason": "rows of 64k+1 voxels use flat segment windows, which the two-step tiles do not cover"}
     _, r0 = s.advance(args.lbm_steps)
     _, r1 = s.advance(4 * args.lbm_steps)
     us = (r1.kernel_ms - r0.kernel_ms) * 1e3 / (r1.kernel_launches - r0.kernel_launches)
