@@ -29,14 +29,20 @@ int status(hipError_t e) { return e == hipSuccess ? 0 : -6; }
 
 // ------------------------------------------------------------------ conv3d forward
 //
-// Implicit GEMM: rows = voxels, columns = output channels, K = 27 taps x cin.
-// Each wave owns 16 consecutive voxels and a slice of 16 * NT output channels
-// (blockIdx.y picks the slice); per K
-// chunk of 32 it loads one A fragment (8 channels of one voxel at one tap, 16 B)
-// and NT B fragments (8 consecutive k of one output channel, 16 B), then issues
-// NT v_mfma_f32_16x16x32_bf16.  Fragment mapping (pinned by unet_mfma_selftest):
+// Implicit GEMM: rows = voxels, columns = output channels, K = 27 taps x cin, on
+// v_mfma_f32_16x16x32_bf16.  Fragment mapping (pinned by unet_mfma_selftest):
 //   A[m][k]: lane l holds m = l % 16, k = 8 (l / 16) + j;  B[k][n]: n = l % 16, same k;
 //   D[m][n]: lane l holds m = 4 (l / 16) + i, n = l % 16.
+// A workgroup (4 waves) owns kTY rows of kTX voxels in ZC consecutive planes and
+// 16 * NT output channels (blockIdx.z picks the slice).  Per stage of 16 input
+// channels it marches through its planes: LDS holds a ring of four input planes
+// ((kTY + 2) rows x (kTX + 2) voxels each, halo included), so each input plane is
+// copied in once per stage rather than once for every output plane that reads it,
+// and the next plane's loads are in flight while a plane's products run.  Each
+// wave takes one row: per K chunk of 32 (two taps of the 16 channels) it reads four
+// A fragments from LDS (four 16-voxel tiles) and NT B fragments (weights, the same
+// for every wave) and issues 4 x NT MFMAs, so an A fragment feeds NT products and a
+// B fragment four.
 struct ConvArgs {
     const uint16_t *x;
     const uint16_t *w;
@@ -47,57 +53,161 @@ struct ConvArgs {
     int nz, ny, nx, cin, cout, kpad, relu;
 };
 
+constexpr int kTX = 64, kTY = 4;            // voxels of a workgroup in each of its planes: 4 rows of 64
+constexpr int kBX = kTX + 2, kBY = kTY + 2; // an input plane, halo included
+constexpr int kPlane = kBX * kBY;           // 396 voxels
+constexpr int kCC = 16;                     // input channels per stage
+constexpr int kVS = 24;  // LDS elements per voxel: 16 channels + 8 of padding, so that 16 lanes
+                         // reading 16 consecutive voxels hit distinct banks
+constexpr int kKC = 14;  // K chunks of 32 per stage: 27 taps x 16 channels, the last half empty
+constexpr int kPS = (2 * kPlane + 255) / 256;  // 16-byte loads per thread and input plane
+
+// output planes per workgroup: the accumulators of ZC planes and the stage's weight
+// fragments stay in registers
+__host__ __device__ constexpr int conv_planes(int nt) { return nt == 1 ? 2 : 1; }
+
 template <int NT>
-__global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int co0 = blockIdx.y * 16 * NT;  // this workgroup's slice of output channels
-    const int64_t nvox = (int64_t)a.nz * a.ny * a.nx;
-    const int64_t vbase = (int64_t)blockIdx.x * 64 + wave * 16;
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_conv_fwd(ConvArgs a) {
+    constexpr int ZC = conv_planes(NT);
+    __shared__ __attribute__((aligned(16))) uint16_t ring[4 * kPlane * kVS];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nxt = (a.nx + kTX - 1) / kTX;
+    const int x0 = (int)(blockIdx.x % nxt) * kTX, y0 = (int)(blockIdx.x / nxt) * kTY;
+    const int z0 = (int)blockIdx.y * ZC;
+    const int co0 = (int)blockIdx.z * 16 * NT;
     const int m = lane & 15, kb = lane >> 4;
-    const int64_t va = vbase + m;
-    const bool rowok = va < nvox;
-    int x = 0, y = 0, z = 0;
-    if (rowok) {
-        x = (int)(va % a.nx);
-        const int64_t r = va / a.nx;
-        y = (int)(r % a.ny);
-        z = (int)(r / a.ny);
-    }
-    f32x4 acc[NT];
+    f32x4 acc[ZC][4][NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    const int nchunk = a.kpad / 32;
-    for (int q = 0; q < nchunk; ++q) {
-        const int k = 32 * q + 8 * kb;
-        const int tap = k / a.cin, ci = k - tap * a.cin;
-        uint4 av = make_uint4(0u, 0u, 0u, 0u);
-        if (rowok && tap < 27) {
-            const int zz = z + tap / 9 - 1, yy = y + (tap / 3) % 3 - 1, xx = x + tap % 3 - 1;
-            if (zz >= 0 && zz < a.nz && yy >= 0 && yy < a.ny && xx >= 0 && xx < a.nx) {
-                const int64_t nb = ((int64_t)zz * a.ny + yy) * a.nx + xx;
-                av = *reinterpret_cast<const uint4 *>(a.x + nb * a.ldx + a.offx + ci);
+    for (int p = 0; p < ZC; ++p)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int n = 0; n < NT; ++n) acc[p][t][n] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    // this lane's two taps per K chunk: tap = 2 q + (kb >> 1), channels 8 (kb & 1) .. + 7
+    const int chan = 8 * (kb & 1);
+    const uint16_t *wrow[NT];
+#pragma unroll
+    for (int n = 0; n < NT; ++n) wrow[n] = a.w + (int64_t)(co0 + 16 * n + m) * a.kpad + chan;
+    // this thread's share of one input plane (zeros outside the grid)
+    auto load_plane = [&](int zz, int c0, uint4(&v)[kPS]) {
+#pragma unroll
+        for (int it = 0; it < kPS; ++it) {
+            const int e = tid + 256 * it;
+            v[it] = make_uint4(0u, 0u, 0u, 0u);
+            if (e < 2 * kPlane && zz >= 0 && zz < a.nz) {
+                const int bv = e >> 1, h = e & 1;
+                const int xx = x0 + bv % kBX - 1, yy = y0 + bv / kBX - 1;
+                if (xx >= 0 && xx < a.nx && yy >= 0 && yy < a.ny) {
+                    const int64_t nb = ((int64_t)zz * a.ny + yy) * a.nx + xx;
+                    v[it] = *reinterpret_cast<const uint4 *>(a.x + nb * a.ldx + a.offx + c0 + 8 * h);
+                }
             }
         }
-        const bf16x8 A = __builtin_bit_cast(bf16x8, av);
+    };
+    auto store_plane = [&](int slot, const uint4(&v)[kPS]) {
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const int co = co0 + 16 * t + m;
-            const uint4 bv = *reinterpret_cast<const uint4 *>(a.w + (int64_t)co * a.kpad + k);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, __builtin_bit_cast(bf16x8, bv), acc[t], 0, 0, 0);
+        for (int it = 0; it < kPS; ++it) {
+            const int e = tid + 256 * it;
+            if (e < 2 * kPlane) *reinterpret_cast<uint4 *>(&ring[(slot * kPlane + (e >> 1)) * kVS + 8 * (e & 1)]) = v[it];
+        }
+    };
+    for (int c0 = 0; c0 < a.cin; c0 += kCC) {
+        // the stage's weight fragments: K chunk q, output tile n (zero past the 27th tap)
+        bf16x8 B[kKC][NT];
+#pragma unroll
+        for (int q = 0; q < kKC; ++q) {
+            const int tap = 2 * q + (kb >> 1);
+#pragma unroll
+            for (int n = 0; n < NT; ++n) {
+                uint4 bv = make_uint4(0u, 0u, 0u, 0u);
+                if (tap < 27) bv = *reinterpret_cast<const uint4 *>(wrow[n] + tap * a.cin + c0);
+                B[q][n] = __builtin_bit_cast(bf16x8, bv);
+            }
+        }
+        uint4 v[kPS];
+        __syncthreads();  // the previous stage's reads of the ring are done
+        // input plane z0 - 1 + i sits in ring slot i & 3
+        load_plane(z0 - 1, c0, v);
+        store_plane(0, v);
+        load_plane(z0, c0, v);
+        store_plane(1, v);
+        load_plane(z0 + 1, c0, v);
+#pragma unroll
+        for (int p = 0; p < ZC; ++p) {
+            // Slot (p + 2) & 3 last held plane z0 + p - 3, read by the products of
+            // output plane p - 2, which every wave finished before the barrier of
+            // step p - 1: one barrier per plane suffices.
+            store_plane((p + 2) & 3, v);  // input plane z0 + p + 1
+            __syncthreads();
+            if (p + 1 < ZC) load_plane(z0 + p + 2, c0, v);  // in flight during the products below
+            // A fragments of K chunk q from the ring (zero past the 27th tap)
+            auto read_a = [&](int q, bf16x8(&A)[4]) {
+                const int tap = 2 * q + (kb >> 1);
+                const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;  // 0..2: offsets within the ring
+                const int base = ((p + dz) & 3) * kPlane + (wave + dy) * kBX + m + dx;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    uint4 av = make_uint4(0u, 0u, 0u, 0u);
+                    if (tap < 27) av = *reinterpret_cast<const uint4 *>(&ring[(base + 16 * t) * kVS + chan]);
+                    A[t] = __builtin_bit_cast(bf16x8, av);
+                }
+            };
+            // one K chunk ahead: the next chunk's LDS reads run under this chunk's products
+            bf16x8 Ac[4], An[4];
+            read_a(0, Ac);
+#pragma unroll
+            for (int q = 0; q < kKC; ++q) {
+                if (q + 1 < kKC) read_a(q + 1, An);
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int n = 0; n < NT; ++n)
+                        acc[p][t][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ac[t], B[q][n], acc[p][t][n], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);  // keep later chunks' reads out of this one
+#pragma unroll
+                for (int t = 0; t < 4; ++t) Ac[t] = An[t];
+            }
         }
     }
+    // Epilogue: bias and ReLU, then BF16 results through LDS so that each lane
+    // stores whole 16-byte runs of 8 channels (the MFMA result puts one channel of
+    // four voxels in a lane).  The ring is free once every wave is past this barrier.
+    __syncthreads();
+    constexpr int kOC = 16 * NT;  // output channels of the workgroup
+    uint16_t *stage = ring + wave * (ZC * kTX * kOC);
+    const int yy = y0 + wave;
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        const int co = co0 + 16 * t + m;
-        const float bias = a.b ? a.b[co] : 0.f;
+    for (int p = 0; p < ZC; ++p)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int64_t vm = vbase + 4 * kb + i;
-            if (vm >= nvox) continue;
-            float v = acc[t][i] + bias;
-            if (a.relu) v = fmaxf(v, 0.f);
-            a.y[vm * a.ldy + a.offy + co] = f2bf(v);
-            if (a.y32) a.y32[vm * a.cout + co] = v;
+        for (int n = 0; n < NT; ++n) {
+            const int c = 16 * n + m;
+            const float bias = a.b ? a.b[co0 + c] : 0.f;
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int vx = 16 * t + 4 * kb + i;
+                    float v = acc[p][t][n][i] + bias;
+                    if (a.relu) v = fmaxf(v, 0.f);
+                    stage[(p * kTX + vx) * kOC + c] = f2bf(v);
+                    const int xx = x0 + vx, zz = z0 + p;
+                    if (a.y32 && xx < a.nx && yy < a.ny && zz < a.nz)
+                        a.y32[(((int64_t)zz * a.ny + yy) * a.nx + xx) * a.cout + co0 + c] = v;
+                }
+        }
+    __builtin_amdgcn_wave_barrier();  // the wave's LDS writes above precede its reads below
+    if (yy >= a.ny) return;
+    constexpr int kRuns = kOC / 8;  // 16-byte runs per voxel
+#pragma unroll
+    for (int p = 0; p < ZC; ++p) {
+        const int zz = z0 + p;
+        if (zz >= a.nz) break;
+        for (int r = lane; r < kTX * kRuns; r += 64) {
+            const int vx = r / kRuns, part = r % kRuns, xx = x0 + vx;
+            if (xx >= a.nx) continue;
+            const int64_t vm = ((int64_t)zz * a.ny + yy) * a.nx + xx;
+            *reinterpret_cast<uint4 *>(a.y + vm * a.ldy + a.offy + co0 + 8 * part) =
+                *reinterpret_cast<const uint4 *>(&stage[(p * kTX + vx) * kOC + 8 * part]);
         }
     }
 }
@@ -467,22 +577,19 @@ int unet_conv3d_fwd(const uint16_t *x, int32_t ldx, int32_t offx, const uint16_t
                     int32_t ldy, int32_t offy, float *y32, int32_t nz, int32_t ny, int32_t nx, int32_t cin,
                     int32_t cout, int32_t relu, void *stream) {
     if (!x || !w || !y || nz <= 0 || ny <= 0 || nx <= 0 || cin % 16 || !ch_ok(ldx, offx, cin) ||
-        !ch_ok(ldy, offy, cout) || (ldx % 8) || (offx % 8))
+        !ch_ok(ldy, offy, cout) || (ldx % 8) || (offx % 8) || (ldy % 8) || (offy % 8))
         return -1;
-    if (cout % 16) return -1;
+    if (cout % 16 || nz > 65535) return -1;
     const int tiles = cout / 16;
-    const int nt = tiles % 4 == 0 ? 4 : tiles % 3 == 0 ? 3 : tiles % 2 == 0 ? 2 : 1;
+    const int nt = 1;  // one 16-channel tile per wave: its 14 weight fragments stay in registers
     ConvArgs a{x, w, b, y, y32, ldx, offx, ldy, offy, nz, ny, nx, cin, cout, kpad_of(cin), relu};
-    const int64_t nvox = (int64_t)nz * ny * nx;
-    const dim3 g((unsigned)((nvox + 63) / 64), (unsigned)(tiles / nt)), blk(256);
+    const int64_t nxy = (int64_t)((nx + kTX - 1) / kTX) * ((ny + kTY - 1) / kTY);
+    if (nxy > 0x7fffffff) return -1;
+    const int zc = conv_planes(nt);
+    const dim3 g((unsigned)nxy, (unsigned)((nz + zc - 1) / zc), (unsigned)(tiles / nt)), blk(256);
     hipStream_t st = static_cast<hipStream_t>(stream);
     (void)hipGetLastError();
-    switch (nt) {
-        case 1: hipLaunchKernelGGL(k_conv_fwd<1>, g, blk, 0, st, a); break;
-        case 2: hipLaunchKernelGGL(k_conv_fwd<2>, g, blk, 0, st, a); break;
-        case 3: hipLaunchKernelGGL(k_conv_fwd<3>, g, blk, 0, st, a); break;
-        default: hipLaunchKernelGGL(k_conv_fwd<4>, g, blk, 0, st, a); break;
-    }
+    hipLaunchKernelGGL(k_conv_fwd<1>, g, blk, 0, st, a);
     return status(hipGetLastError());
 }
 

@@ -79,6 +79,25 @@ def pt_cl_cube(n, modes=("react", "deff")):
             "cases": out}
 
 
+def pt_cl_react_64x64x63():
+    """The reactive Pt layer on a 64 x 64 x 63 structure (structgen.pt_cl(1, shape=(64,
+    64, 63))): with its inlet reservoir plane the simulated grid is 64^3, a grid the
+    warm-start network takes (each size a multiple of 8).  Knudsen, 2 nm voxels, k = 1e-2
+    per Pt face; the certified GMRES route as for the cubes."""
+    ph = sg.pt_cl(1, shape=(64, 64, 63))
+    t = time.time()
+    prob = O.prepare(ph, O.Params(mode=O.MODE_REACT, knudsen=True, voxel_m=2e-9, k_lat=1e-2))
+    s = O.solve_fixed_point(prob, "gmres", tol=1e-13)
+    case = {"seed": 1, "shape": [64, 64, 63], "mode": O.MODE_REACT, "k_lat": 1e-2, "rate": s.rate,
+            "j_in": s.fluxes.j_in, "n_active": int(prob.active.sum()), "seconds": round(time.time() - t, 1)}
+    print(case, flush=True)
+    return {"workload": "Pt CL 64 x 64 x 63 at 2 nm (64^3 simulated with the reservoir plane), Knudsen, "
+                        "ionomer 1e-3 D0, reactive k 1e-2 per Pt face",
+            "generator": "structgen.pt_cl(1, shape=(64, 64, 63))",
+            "solver": "oracle.lbm.solve_fixed_point(method='gmres', tol=1e-13), certified by one plain step",
+            "cases": [case]}
+
+
 def coupled_16():
     """The coupled O2 / proton-potential problem (Eqs. 15-18b, Tafel Eq. 17b) on a
     16^3 Pt catalyst layer whose membrane face is ionomer (structgen.pt_cl(5,
@@ -103,7 +122,7 @@ def coupled_16():
 
 
 GOLDEN = {"oracle_two_phase_32.json": two_phase_32, "oracle_pt_cl_slab.json": pt_cl_slab,
-          "oracle_coupled_16.json": coupled_16,
+          "oracle_coupled_16.json": coupled_16, "oracle_pt_cl_react_64x64x63.json": pt_cl_react_64x64x63,
           "oracle_pt_cl_64.json": lambda: pt_cl_cube(64), "oracle_pt_cl_128.json": lambda: pt_cl_cube(128)}
 
 if __name__ == "__main__":
