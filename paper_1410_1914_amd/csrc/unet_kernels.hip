@@ -400,6 +400,65 @@ __global__ void k_up_bwd(const uint16_t *dy, int ldy, int offy, uint16_t *dx, in
     dx[p * ldx + offx + ch] = f2bf(s);
 }
 
+// The same three layers on runs of 8 channels (16 bytes) per thread, for channel
+// counts, row lengths and offsets that are multiples of 8 (every call the network
+// makes); 32-bit index arithmetic (grids below 2^32 voxel-runs).
+__device__ __forceinline__ void bf8_to_f(uint4 u, float (&f)[8]) {
+    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        f[2 * k] = __uint_as_float(w[k] << 16);
+        f[2 * k + 1] = __uint_as_float(w[k] & 0xffff0000u);
+    }
+}
+
+__global__ void k_pool_fwd8(const uint16_t *x, int ldx, int offx, uint16_t *y, int ldy, int offy, uint32_t nz,
+                            uint32_t ny, uint32_t nx, uint32_t c8) {
+    const uint32_t hy = ny / 2, hx = nx / 2;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if ((uint64_t)i >= (uint64_t)(nz / 2) * hy * hx * c8) return;
+    const uint32_t g = i % c8, p = i / c8;
+    const uint32_t X = p % hx, Y = (p / hx) % hy, Z = p / (hx * hy);
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+        const uint64_t v = ((uint64_t)(2 * Z + (d >> 2)) * ny + 2 * Y + ((d >> 1) & 1)) * nx + 2 * X + (d & 1);
+        float f[8];
+        bf8_to_f(*reinterpret_cast<const uint4 *>(x + v * ldx + offx + 8 * g), f);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s[k] += f[k];
+    }
+    uint16_t o[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) o[k] = f2bf(0.125f * s[k]);
+    *reinterpret_cast<uint4 *>(y + (uint64_t)p * ldy + offy + 8 * g) = *reinterpret_cast<const uint4 *>(o);
+}
+
+__global__ void k_up_fwd8(const uint16_t *x, int ldx, int offx, uint16_t *y, int ldy, int offy, uint32_t nz,
+                          uint32_t ny, uint32_t nx, uint32_t c8) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if ((uint64_t)i >= (uint64_t)nz * ny * nx * c8) return;
+    const uint32_t g = i % c8, v = i / c8;
+    const uint32_t xx = v % nx, yy = (v / nx) % ny, zz = v / (nx * ny);
+    const uint64_t p = ((uint64_t)(zz / 2) * (ny / 2) + yy / 2) * (nx / 2) + xx / 2;
+    *reinterpret_cast<uint4 *>(y + (uint64_t)v * ldy + offy + 8 * g) =
+        *reinterpret_cast<const uint4 *>(x + p * ldx + offx + 8 * g);
+}
+
+__global__ void k_head_fwd8(const uint16_t *x, int ldx, const float *w, const float *b, const float *base, float *out,
+                            int64_t nvox, int c8) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nvox) return;
+    float s = b[0] + (base ? base[v] : 0.f);
+    for (int g = 0; g < c8; ++g) {
+        float f[8];
+        bf8_to_f(*reinterpret_cast<const uint4 *>(x + v * ldx + 8 * g), f);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s = fmaf(w[8 * g + k], f[k], s);
+    }
+    out[v] = s;
+}
+
 __global__ void k_head_fwd(const uint16_t *x, int ldx, const float *w, const float *b, const float *base, float *out,
                            int64_t nvox, int c) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -567,6 +626,9 @@ dim3 grid1(int64_t n, int bs = 256) { return dim3((unsigned)((n + bs - 1) / bs))
 
 bool ch_ok(int ld, int off, int c) { return ld > 0 && off >= 0 && c > 0 && off + c <= ld; }
 
+// channel count, row lengths and offsets all in runs of 8 (16-byte loads and stores)
+bool runs8(int c, int ld1, int off1, int ld2, int off2) { return ((c | ld1 | off1 | ld2 | off2) & 7) == 0; }
+
 }  // namespace
 
 extern "C" {
@@ -641,8 +703,13 @@ int unet_pool_fwd(const uint16_t *x, int32_t ldx, int32_t offx, uint16_t *y, int
                   int32_t ny, int32_t nx, int32_t c, void *stream) {
     if (!x || !y || (nz | ny | nx) & 1 || nz <= 0 || !ch_ok(ldx, offx, c) || !ch_ok(ldy, offy, c)) return -1;
     (void)hipGetLastError();
-    hipLaunchKernelGGL(k_pool_fwd, grid1((int64_t)nz * ny * nx / 8 * c), dim3(256), 0,
-                       static_cast<hipStream_t>(stream), x, ldx, offx, y, ldy, offy, nz, ny, nx, c);
+    if (runs8(c, ldx, offx, ldy, offy) && (int64_t)nz * ny * nx / 8 * (c / 8) < ((int64_t)1 << 32))
+        hipLaunchKernelGGL(k_pool_fwd8, grid1((int64_t)nz * ny * nx / 8 * (c / 8)), dim3(256), 0,
+                           static_cast<hipStream_t>(stream), x, ldx, offx, y, ldy, offy, (uint32_t)nz, (uint32_t)ny,
+                           (uint32_t)nx, (uint32_t)(c / 8));
+    else
+        hipLaunchKernelGGL(k_pool_fwd, grid1((int64_t)nz * ny * nx / 8 * c), dim3(256), 0,
+                           static_cast<hipStream_t>(stream), x, ldx, offx, y, ldy, offy, nz, ny, nx, c);
     return status(hipGetLastError());
 }
 
@@ -659,8 +726,13 @@ int unet_up_fwd(const uint16_t *x, int32_t ldx, int32_t offx, uint16_t *y, int32
                 int32_t ny, int32_t nx, int32_t c, void *stream) {
     if (!x || !y || (nz | ny | nx) & 1 || nz <= 0 || !ch_ok(ldx, offx, c) || !ch_ok(ldy, offy, c)) return -1;
     (void)hipGetLastError();
-    hipLaunchKernelGGL(k_up_fwd, grid1((int64_t)nz * ny * nx * c), dim3(256), 0, static_cast<hipStream_t>(stream), x,
-                       ldx, offx, y, ldy, offy, nz, ny, nx, c);
+    if (runs8(c, ldx, offx, ldy, offy) && (int64_t)nz * ny * nx * (c / 8) < ((int64_t)1 << 32))
+        hipLaunchKernelGGL(k_up_fwd8, grid1((int64_t)nz * ny * nx * (c / 8)), dim3(256), 0,
+                           static_cast<hipStream_t>(stream), x, ldx, offx, y, ldy, offy, (uint32_t)nz, (uint32_t)ny,
+                           (uint32_t)nx, (uint32_t)(c / 8));
+    else
+        hipLaunchKernelGGL(k_up_fwd, grid1((int64_t)nz * ny * nx * c), dim3(256), 0, static_cast<hipStream_t>(stream),
+                           x, ldx, offx, y, ldy, offy, nz, ny, nx, c);
     return status(hipGetLastError());
 }
 
@@ -677,8 +749,12 @@ int unet_head_fwd(const uint16_t *x, int32_t ldx, const float *w, const float *b
                   int64_t nvox, int32_t c, void *stream) {
     if (!x || !w || !b || !out || nvox <= 0 || c <= 0 || ldx < c) return -1;
     (void)hipGetLastError();
-    hipLaunchKernelGGL(k_head_fwd, grid1(nvox), dim3(256), 0, static_cast<hipStream_t>(stream), x, ldx, w, b, base,
-                       out, nvox, c);
+    if (runs8(c, ldx, 0, 8, 0))
+        hipLaunchKernelGGL(k_head_fwd8, grid1(nvox), dim3(256), 0, static_cast<hipStream_t>(stream), x, ldx, w, b,
+                           base, out, nvox, c / 8);
+    else
+        hipLaunchKernelGGL(k_head_fwd, grid1(nvox), dim3(256), 0, static_cast<hipStream_t>(stream), x, ldx, w, b, base,
+                           out, nvox, c);
     return status(hipGetLastError());
 }
 
