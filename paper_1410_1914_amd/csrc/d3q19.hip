@@ -6,10 +6,14 @@
 // f[(j >> 6) * 19 * 64 + i * 64 + (j & 63)], FP32, holding the post-collision
 // value shifted by a_i * c_sh(x) (c_sh = sh0 - slope * x, the empty-box profile
 // between Dirichlet faces, or half the inlet value when reacting), two lattices
-// A/B.  A wave updates one 64-voxel row segment; its record (D19Rec) holds the
-// fluid masks and compact prefixes of the nine rows it pulls from, (y + ry,
-// z + rz) for ry, rz in {-1, 0, 1}, so the compact index of any pull source is a
-// prefix plus a count of mask bits, and no per-voxel neighbour table exists.
+// A/B.  A wave updates one segment, a window of up to 64 voxels consecutive in
+// grid order cut as for the D3Q7 solver (each row into its own windows, or, for
+// rows of 64 k + 1 voxels, windows running on across row ends within a plane, cut
+// at rows 1 and ny - 1); its record (D19Rec) holds the fluid masks and compact
+// prefixes of the nine windows it pulls from, the same lanes moved by (ry, rz)
+// rows and planes for ry, rz in {-1, 0, 1}, so the compact index of any pull
+// source is a prefix plus a count of mask bits, and no per-voxel neighbour table
+// exists.
 // Relaxation rates, sink coefficients and the concentration snapshot are compact
 // too; a dense map from voxel to compact index serves the conversions.  The
 // collision is evaluated in FP64 and rounded once to FP32.
@@ -43,15 +47,19 @@ constexpr uint32_t kActive = 1u << 31;
 
 __host__ __device__ constexpr double weight(int i) { return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
 
-// Segment record of the compact layout: the nine rows a wave pulls from, row k
-// being (y + ry, z + rz) with k = (ry + 1) * 3 + (rz + 1) (k = 4 is the
-// segment's own row).
+// Segment record of the compact layout: the nine windows a wave pulls from,
+// window k being the segment's lanes moved by (ry, rz) rows and planes with
+// k = (ry + 1) * 3 + (rz + 1) (k = 4 is the segment itself).  Lane l lies at
+// x = x0 + l, or at x = l - brk on the next row for l >= brk.
 struct alignas(16) D19Rec {
-    uint64_t m[9];       // simulated voxels of row k over the segment's x range
-    uint32_t pre[9];     // compact index of the first simulated voxel of that range
-    uint32_t edges;      // bit 2k: the voxel before row k's range is simulated; bit 2k + 1: the one after
-    uint16_t s, y, z, pad;  // x0 = 64 s, row y, plane z
-    uint32_t pad2[2];
+    uint64_t m[9];       // simulated voxels of window k
+    uint32_t pre[9];     // compact index of the first simulated voxel of that window
+    uint32_t edges;      // bit 2k: the voxel at x - 1 of window k's lane 0 is simulated; bit 2k + 1:
+                         // the one at x + 1 of its lane 63
+    uint32_t v0;         // grid index of lane 0
+    uint16_t x0;         // x of lane 0
+    uint8_t brk, len;    // first lane on the next row (64: none); lanes inside the grid
+    uint32_t pad;
 };
 static_assert(sizeof(D19Rec) == 128, "D19Rec layout");
 
@@ -135,7 +143,7 @@ __global__ __launch_bounds__(kBlock) void k_d3q19(D19Args a) {
         const D19Rec &R = a.rec[a.list[e]];
         const uint64_t mown = R.m[4];
         if (bit64(mown, lane)) {
-            const int x = (int)R.s * 64 + lane;
+            const int x = lane < (int)R.brk ? (int)R.x0 + lane : lane - (int)R.brk;
             const uint32_t j = R.pre[4] + mbcnt64(mown);
             const double csh = a.sh0 - a.slope * x;
             // every lane loads each direction once, from its pull source or, when that
@@ -152,11 +160,11 @@ __global__ __launch_bounds__(kBlock) void k_d3q19(D19Args a) {
                 if (CX[i] == 0) {
                     fl = bit64(mr, lane);
                     idx = c;
-                } else if (CX[i] == 1) {  // source x - 1
-                    fl = lane ? bit64(mr, lane - 1) : ((R.edges >> (2 * k)) & 1u) != 0;
+                } else if (CX[i] == 1) {  // source x - 1 (none at x = 0)
+                    fl = x > 0 && (lane ? bit64(mr, lane - 1) : ((R.edges >> (2 * k)) & 1u) != 0);
                     idx = c - 1u;
-                } else {                  // source x + 1
-                    fl = lane < 63 ? bit64(mr, lane + 1) : ((R.edges >> (2 * k + 1)) & 1u) != 0;
+                } else {                  // source x + 1 (none at x = nx - 1)
+                    fl = x < a.nx - 1 && (lane < 63 ? bit64(mr, lane + 1) : ((R.edges >> (2 * k + 1)) & 1u) != 0);
                     idx = c + (bit64(mr, lane) ? 1u : 0u);
                 }
                 have[i] = fl;
@@ -183,7 +191,7 @@ __global__ __launch_bounds__(kBlock) void k_d3q19(D19Args a) {
             const double C = csh + sum;
             const double om = (double)a.omega[j];
             const double knv = REACT ? (double)a.kn[j] : 0.0;
-            const int64_t v = ((int64_t)R.z * a.ny + R.y) * a.nx + x;
+            const int64_t v = (int64_t)R.v0 + lane;
             const double sv = a.src ? (double)a.src[v] : 0.0;
             const double b = (om - knv) * C - om * csh + sv;
             const double keep = 1.0 - om;
@@ -482,57 +490,76 @@ static int create19(const lbm_grid *g, const uint8_t *phase, const lbm_params *p
                     }
                     s->mask[v] = m;
                 }
-        // compact order (x fastest), segment masks and prefixes
-        const int nsx = (nx + 63) / 64;
-        const int64_t nseg = (int64_t)nsx * ny * nz;
-        std::vector<uint64_t> segm(nseg, 0ull);
-        std::vector<uint32_t> segp(nseg, 0u);
+        // compact order (x fastest) and rank of every grid position among the simulated voxels
         s->cidx.assign(s->N, -1);
         int64_t nf = 0;
-        for (int64_t row = 0; row < (int64_t)ny * nz; ++row)
-            for (int sx = 0; sx < nsx; ++sx) {
-                const int64_t g = row * nsx + sx;
-                segp[g] = (uint32_t)nf;
-                for (int l = 0; l < 64 && sx * 64 + l < nx; ++l) {
-                    const int64_t v = row * nx + sx * 64 + l;
-                    if (!P.active[v]) continue;
-                    segm[g] |= 1ull << l;
-                    s->cidx[v] = (int32_t)nf++;
-                }
+        const int64_t nw = s->N / 64 + 2;
+        std::vector<uint64_t> sb(nw, 0ull);
+        std::vector<int64_t> rank(nw, 0);
+        for (int64_t v = 0; v < s->N; ++v)
+            if (P.active[v]) {
+                s->cidx[v] = (int32_t)nf++;
+                sb[v >> 6] |= 1ull << (v & 63);
             }
+        for (int64_t w = 1; w < nw; ++w) rank[w] = rank[w - 1] + __builtin_popcountll(sb[w - 1]);
+        auto bits = [&](int64_t pos, int len) {  // simulated bits of grid indices pos .. pos + len - 1
+            const int64_t w = pos >> 6;
+            const int sh = (int)(pos & 63);
+            uint64_t v = sb[w] >> sh;
+            if (sh) v |= sb[w + 1] << (64 - sh);
+            return len >= 64 ? v : v & ((1ull << len) - 1ull);
+        };
+        auto rank_at = [&](int64_t pos) {
+            const int sh = (int)(pos & 63);
+            return rank[pos >> 6] + (sh ? __builtin_popcountll(sb[pos >> 6] & ((1ull << sh) - 1ull)) : 0);
+        };
+        auto sim = [&](int64_t pos) { return pos >= 0 && pos < s->N && ((sb[pos >> 6] >> (pos & 63)) & 1ull); };
         s->nf = nf;
         s->stride = (nf + 63) / 64 * 64;
         // one lattice below 4 GiB: byte offsets in 32 bits
         if ((int64_t)kQ * 4 * std::max<int64_t>(s->stride, 64) >= ((int64_t)1 << 32)) return LBM_ERR_INVALID_ARG;
+        if (s->N >= ((int64_t)1 << 32)) return LBM_ERR_INVALID_ARG;
+        // segments: the windows of the D3Q7 layout (Prepared::win_v0, win_len)
+        const int64_t nseg = (int64_t)P.win_v0.size();
+        const int64_t plane = (int64_t)ny * nx;
         s->rec.assign(nseg, D19Rec{});
         s->list.clear();
-        for (int z = 0; z < nz; ++z)
-            for (int y = 0; y < ny; ++y)
-                for (int sx = 0; sx < nsx; ++sx) {
-                    const int64_t g = ((int64_t)z * ny + y) * nsx + sx;
-                    D19Rec &R = s->rec[g];
-                    R.s = (uint16_t)sx;
-                    R.y = (uint16_t)y;
-                    R.z = (uint16_t)z;
-                    for (int k = 0; k < 9; ++k) {
-                        const int ry = k / 3 - 1, rz = k % 3 - 1;
-                        const int64_t gr = ((int64_t)wrapi(z + rz, nz) * ny + wrapi(y + ry, ny)) * nsx + sx;
-                        R.m[k] = segm[gr];
-                        R.pre[k] = segp[gr];
-                        if (sx > 0 && ((segm[gr - 1] >> 63) & 1ull)) R.edges |= 1u << (2 * k);
-                        if (sx + 1 < nsx && (segm[gr + 1] & 1ull)) R.edges |= 1u << (2 * k + 1);
-                    }
-                    if (segm[g]) s->list.push_back((uint32_t)g);
-                }
+        for (int64_t g = 0; g < nseg; ++g) {
+            D19Rec &R = s->rec[g];
+            const int64_t v0 = P.win_v0[g];
+            const int len = P.win_len[g];
+            const int64_t row = v0 / nx;
+            const int x0 = (int)(v0 - row * nx), y = (int)(row % ny), z = (int)(row / ny);
+            const int brk = x0 + len > nx ? nx - x0 : 64;
+            const int x63 = 63 < brk ? x0 + 63 : 63 - brk;  // x of lane 63 when the window is full
+            R.v0 = (uint32_t)v0;
+            R.x0 = (uint16_t)x0;
+            R.brk = (uint8_t)brk;
+            R.len = (uint8_t)len;
+            for (int k = 0; k < 9; ++k) {
+                const int ry = k / 3 - 1, rz = k % 3 - 1;
+                // one offset for every lane: windows never straddle the rows where y wraps
+                const int64_t oy = ry == 0 ? 0 : (ry < 0 ? (y == 0 ? (int64_t)(ny - 1) * nx : -(int64_t)nx)
+                                                         : (y == ny - 1 ? -(int64_t)(ny - 1) * nx : (int64_t)nx));
+                const int64_t oz = rz == 0 ? 0 : (rz < 0 ? (z == 0 ? (int64_t)(nz - 1) * plane : -plane)
+                                                         : (z == nz - 1 ? -(int64_t)(nz - 1) * plane : plane));
+                const int64_t w0 = v0 + oy + oz;
+                R.m[k] = bits(w0, len);
+                R.pre[k] = (uint32_t)rank_at(w0);
+                if (x0 > 0 && sim(w0 - 1)) R.edges |= 1u << (2 * k);
+                if (len == 64 && x63 < nx - 1 && sim(w0 + 64)) R.edges |= 1u << (2 * k + 1);
+            }
+            if (R.m[4]) s->list.push_back((uint32_t)g);
+        }
         // Walk the list as four y slabs, each plane by plane: with the XCD-aware block
         // order each XCD then steps half a slab, and the rows a segment pulls from
         // (y -+ 1, z -+ 1 and the four yz diagonals) were touched a slab plane
         // earlier, still in its L2 (4 slabs measured faster than 8 or 16 here).
         if (ny >= 8) {
-            const int64_t yb = (ny + 3) / 4, per_slab = (int64_t)nz * yb * nsx;
-            auto key = [&](uint32_t g) {
-                const int64_t sx = g % nsx, y = (g / nsx) % ny, z = g / ((int64_t)nsx * ny);
-                return (y / yb) * per_slab + (z * yb + y % yb) * nsx + sx;
+            const int64_t yb = (ny + 3) / 4;
+            auto key = [&](uint32_t g) {  // (slab of the window's first row, plane, grid index)
+                const int64_t v0 = s->rec[g].v0, row = v0 / nx, y = row % ny, z = row / ny;
+                return ((y / yb) * nz + z) * plane + (v0 - z * plane);
             };
             std::sort(s->list.begin(), s->list.end(), [&](uint32_t a, uint32_t b) { return key(a) < key(b); });
         }

@@ -33,6 +33,11 @@ STEP_CASES = [
      dict(knudsen=1, k_lat=0.02, catalyst_phases=(1 << L.CARBON) | (1 << L.PT))),
     ("pt_cl", 5, (12, 18, 40), L.MODE_PROTON, {}),
     ("empty", 0, (1, 3, 33), L.MODE_DEFF, dict(tau_ref=1.3)),
+    # rows of 64 k + 1 voxels: flat segment windows running on across row ends
+    ("pt_cl", 11, (5, 7, 64), L.MODE_REACT, dict(knudsen=1, k_lat=0.05)),
+    ("pt_cl", 12, (3, 2, 64), L.MODE_REACT, dict(k_lat=0.02)),
+    ("pt_cl", 13, (4, 3, 129), L.MODE_DEFF, dict(knudsen=1)),
+    ("pt_cl", 14, (3, 1, 128), L.MODE_REACT, dict(k_lat=0.02)),
 ]
 
 
@@ -142,3 +147,17 @@ def test_mass_balance_at_full_size(hip):
         print(f"[d3q19] 256^3: dmass {dm:.6e}, (J_in - J_out - R) A {flux:.6e}", flush=True)
         assert abs(dm - flux) < 1e-5 * abs(flux) + 2e-8 * m.mass
         prev = m
+
+
+def test_steady_state_on_flat_windows_matches_oracle_fixed_point(hip):
+    """A reactive layer whose reservoir plane makes 65-voxel rows (flat segment
+    windows) against the oracle's exact fixed point."""
+    ph = sg.pt_cl(6, shape=(8, 9, 64))
+    prob, s = _pair(hip, ph, L.MODE_REACT, check_every=200, knudsen=1, k_lat=1e-2)
+    assert prob.percolates
+    ref = O.solve_fixed_point(prob)
+    st, info = s.run_to_steady()
+    assert st == 0
+    rate = s.reaction_rate()[1]
+    print(f"[d3q19] flat steady: {rate:.10g} vs oracle {ref.rate:.10g}, {info.steps} steps", flush=True)
+    assert rate == pytest.approx(ref.rate, rel=1e-4)
