@@ -40,9 +40,11 @@ int status(hipError_t e) { return e == hipSuccess ? 0 : -6; }
 // copied in once per stage rather than once for every output plane that reads it,
 // and the next plane's loads are in flight while a plane's products run.  Each
 // wave takes one row: per K chunk of 32 (two taps of the 16 channels) it reads four
-// A fragments from LDS (four 16-voxel tiles) and NT B fragments (weights, the same
-// for every wave) and issues 4 x NT MFMAs, so an A fragment feeds NT products and a
-// B fragment four.
+// input fragments from LDS (four 16-voxel tiles), holds NT weight fragments (the
+// same for every wave) and issues 4 x NT MFMAs, so an input fragment feeds NT
+// products and a weight fragment four.  The weights are the MFMA's A operand and
+// the inputs its B operand, so a lane's result is four consecutive output channels
+// of one voxel, which leave as one 8-byte store.
 struct ConvArgs {
     const uint16_t *x;
     const uint16_t *w;
@@ -57,14 +59,16 @@ constexpr int kTX = 64, kTY = 4;            // voxels of a workgroup in each of 
 constexpr int kBX = kTX + 2, kBY = kTY + 2; // an input plane, halo included
 constexpr int kPlane = kBX * kBY;           // 396 voxels
 constexpr int kCC = 16;                     // input channels per stage
-constexpr int kVS = 24;  // LDS elements per voxel: 16 channels + 8 of padding, so that 16 lanes
-                         // reading 16 consecutive voxels hit distinct banks
+constexpr int kVS = 16;  // LDS elements per voxel: the 16 channels, unpadded.  A 32-byte voxel
+                         // stride reads at the full LDS rate on gfx950 (the lanes' 16-byte
+                         // reads tile whole 512-byte spans); a padded 48-byte stride ran 1.5x slower
 constexpr int kKC = 14;  // K chunks of 32 per stage: 27 taps x 16 channels, the last half empty
 constexpr int kPS = (2 * kPlane + 255) / 256;  // 16-byte loads per thread and input plane
 
 // output planes per workgroup: the accumulators of ZC planes and the stage's weight
-// fragments stay in registers
-__host__ __device__ constexpr int conv_planes(int nt) { return nt == 1 ? 2 : 1; }
+// fragments stay in registers (254 VGPRs at ZC = 3); each stage's first loads are
+// exposed once per ZC planes
+__host__ __device__ constexpr int conv_planes(int nt) { return nt == 1 ? 3 : 1; }
 
 template <int NT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_conv_fwd(ConvArgs a) {
@@ -125,13 +129,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             }
         }
         uint4 v[kPS];
-        __syncthreads();  // the previous stage's reads of the ring are done
-        // input plane z0 - 1 + i sits in ring slot i & 3
-        load_plane(z0 - 1, c0, v);
-        store_plane(0, v);
-        load_plane(z0, c0, v);
-        store_plane(1, v);
-        load_plane(z0 + 1, c0, v);
+        {
+            // the three planes of the first output plane's brick, their loads in flight together
+            uint4 v0[kPS], v1[kPS];
+            load_plane(z0 - 1, c0, v0);
+            load_plane(z0, c0, v1);
+            load_plane(z0 + 1, c0, v);
+            __syncthreads();  // the previous stage's reads of the ring are done
+            // input plane z0 - 1 + i sits in ring slot i & 3
+            store_plane(0, v0);
+            store_plane(1, v1);
+        }
 #pragma unroll
         for (int p = 0; p < ZC; ++p) {
             // Slot (p + 2) & 3 last held plane z0 + p - 3, read by the products of
@@ -162,52 +170,43 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                 for (int t = 0; t < 4; ++t)
 #pragma unroll
                     for (int n = 0; n < NT; ++n)
-                        acc[p][t][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ac[t], B[q][n], acc[p][t][n], 0, 0, 0);
+                        acc[p][t][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(B[q][n], Ac[t], acc[p][t][n], 0, 0, 0);
                 __builtin_amdgcn_sched_barrier(0);  // keep later chunks' reads out of this one
 #pragma unroll
                 for (int t = 0; t < 4; ++t) Ac[t] = An[t];
             }
         }
     }
-    // Epilogue: bias and ReLU, then BF16 results through LDS so that each lane
-    // stores whole 16-byte runs of 8 channels (the MFMA result puts one channel of
-    // four voxels in a lane).  The ring is free once every wave is past this barrier.
-    __syncthreads();
-    constexpr int kOC = 16 * NT;  // output channels of the workgroup
-    uint16_t *stage = ring + wave * (ZC * kTX * kOC);
+    // Epilogue: with the weights as the A operand each lane holds four consecutive
+    // output channels of one voxel, stored as one 8-byte run (16 bytes for FP32)
     const int yy = y0 + wave;
-#pragma unroll
-    for (int p = 0; p < ZC; ++p)
-#pragma unroll
-        for (int n = 0; n < NT; ++n) {
-            const int c = 16 * n + m;
-            const float bias = a.b ? a.b[co0 + c] : 0.f;
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int vx = 16 * t + 4 * kb + i;
-                    float v = acc[p][t][n][i] + bias;
-                    if (a.relu) v = fmaxf(v, 0.f);
-                    stage[(p * kTX + vx) * kOC + c] = f2bf(v);
-                    const int xx = x0 + vx, zz = z0 + p;
-                    if (a.y32 && xx < a.nx && yy < a.ny && zz < a.nz)
-                        a.y32[(((int64_t)zz * a.ny + yy) * a.nx + xx) * a.cout + co0 + c] = v;
-                }
-        }
-    __builtin_amdgcn_wave_barrier();  // the wave's LDS writes above precede its reads below
     if (yy >= a.ny) return;
-    constexpr int kRuns = kOC / 8;  // 16-byte runs per voxel
 #pragma unroll
     for (int p = 0; p < ZC; ++p) {
         const int zz = z0 + p;
         if (zz >= a.nz) break;
-        for (int r = lane; r < kTX * kRuns; r += 64) {
-            const int vx = r / kRuns, part = r % kRuns, xx = x0 + vx;
-            if (xx >= a.nx) continue;
-            const int64_t vm = ((int64_t)zz * a.ny + yy) * a.nx + xx;
-            *reinterpret_cast<uint4 *>(a.y + vm * a.ldy + a.offy + co0 + 8 * part) =
-                *reinterpret_cast<const uint4 *>(&stage[(p * kTX + vx) * kOC + 8 * part]);
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+            const int c = co0 + 16 * n + 4 * kb;
+            float bias[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) bias[i] = a.b ? a.b[c + i] : 0.f;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int xx = x0 + 16 * t + m;
+                if (xx >= a.nx) continue;
+                const int64_t vm = ((int64_t)zz * a.ny + yy) * a.nx + xx;
+                float v[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    v[i] = acc[p][t][n][i] + bias[i];
+                    if (a.relu) v[i] = fmaxf(v[i], 0.f);
+                }
+                const uint2 o = make_uint2((uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16),
+                                           (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16));
+                *reinterpret_cast<uint2 *>(a.y + vm * a.ldy + a.offy + c) = o;
+                if (a.y32) *reinterpret_cast<float4 *>(a.y32 + vm * a.cout + c) = make_float4(v[0], v[1], v[2], v[3]);
+            }
         }
     }
 }
@@ -642,6 +641,9 @@ int unet_conv3d_fwd(const uint16_t *x, int32_t ldx, int32_t offx, const uint16_t
         !ch_ok(ldy, offy, cout) || (ldx % 8) || (offx % 8) || (ldy % 8) || (offy % 8))
         return -1;
     if (cout % 16 || nz > 65535) return -1;
+    if ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(w) | reinterpret_cast<uintptr_t>(y) |
+         reinterpret_cast<uintptr_t>(y32)) & 15)
+        return -1;  // 16-byte vector loads and stores
     const int tiles = cout / 16;
     const int nt = 1;  // one 16-channel tile per wave: its 14 weight fragments stay in registers
     ConvArgs a{x, w, b, y, y32, ldx, offx, ldy, offy, nz, ny, nx, cin, cout, kpad_of(cin), relu};

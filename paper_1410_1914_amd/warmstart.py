@@ -412,6 +412,40 @@ def time_network(w: Workload, reps=10, log=print):
     return res
 
 
+def time_layers(shape, reps=20, log=print):
+    """Times each distinct convolution of a forward pass on a (nz, ny, nx) grid on
+    its own (random BF16 activations and weights, HIP events over reps launches);
+    returns {"n^3 cin->cout": microseconds}."""
+    import torch
+
+    level = {"e1": 0, "d1": 0, "e2": 1, "d2": 1, "e3": 2, "d3": 2, "b4": 3}
+    g = torch.Generator(device="cuda").manual_seed(0)
+    out = {}
+    for name, cin, cout in unet.layer_specs():
+        dims = tuple(s // 2 ** level[name[:2]] for s in shape)
+        key = f"{'x'.join(map(str, dims))} {cin}->{cout}"
+        if key in out:
+            continue
+        nv = int(np.prod(dims))
+        x = torch.randn(nv * cin, device="cuda", generator=g).to(torch.bfloat16)
+        w = (torch.randn(cout * unet.unet_kpad(cin), device="cuda", generator=g) * 0.05).to(torch.bfloat16)
+        b = torch.zeros(cout, device="cuda")
+        y = torch.empty(nv * cout, device="cuda", dtype=torch.bfloat16)
+        for _ in range(3):
+            unet.unet_conv3d_fwd(x, cin, 0, w, b, y, cout, 0, None, dims, cin, cout, True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            unet.unet_conv3d_fwd(x, cin, 0, w, b, y, cout, 0, None, dims, cin, cout, True)
+        e1.record()
+        e1.synchronize()
+        us = e0.elapsed_time(e1) / reps * 1e3
+        tflops = 2 * 27 * cin * cout * nv / us / 1e6
+        out[key] = us
+        log(f"[layer] {key}: {us:.1f} us, {tflops:.0f} TFLOP/s, {tflops / 25:.1f}% of the BF16 peak")
+    return out
+
+
 def main(argv):
     """python -m paper_1410_1914_amd.warmstart train <react|deff> [n_samples] [epochs]
     python -m paper_1410_1914_amd.warmstart eval <react|deff> [seed ...]
@@ -449,6 +483,7 @@ def main(argv):
     elif argv[0] == "time":
         lbm.require_gpu()
         time_network(w, log=log)
+        time_layers(w.test_shape, log=log)
     else:
         seeds = tuple(int(a) for a in argv[2:]) or (20000, 20001)
         lbm.require_gpu()
