@@ -39,10 +39,10 @@ int32_t unet_kpad(int32_t cin);
  * accumulation.  Output is BF16; when y32 is not NULL the FP32 result is also
  * written to y32[v * cout + co].  Activations are NDHWC rows of ldx / ldy
  * elements; cin and cout are multiples of 16, ldx, offx, ldy and offy multiples
- * of 8 (16-byte runs), x, w, y and y32 16-byte aligned, else -1.  b may be NULL
- * (no bias).  Each workgroup stages the input planes its 4 x 64 voxels in three
- * planes read (halo included) in LDS, 16 channels at a time, and keeps the
- * weights of those channels in registers. */
+ * of 8 (16-byte runs), x, w, y and y32 16-byte aligned, x and w each below 2 GiB,
+ * else -1.  b may be NULL (no bias).  Each workgroup copies the input planes its
+ * 4 x 64 voxels in three planes read (halo included) straight into LDS, 16
+ * channels at a time, and keeps the weights of those channels in registers. */
 int unet_conv3d_fwd(const uint16_t *x, int32_t ldx, int32_t offx, const uint16_t *w, const float *b,
                     uint16_t *y, int32_t ldy, int32_t offy, float *y32, int32_t nz, int32_t ny, int32_t nx,
                     int32_t cin, int32_t cout, int32_t relu, void *stream);

@@ -35,10 +35,10 @@ int status(hipError_t e) { return e == hipSuccess ? 0 : -6; }
 //   D[m][n]: lane l holds m = 4 (l / 16) + i, n = l % 16.
 // A workgroup (4 waves) owns kTY rows of kTX voxels in ZC consecutive planes and
 // 16 * NT output channels (blockIdx.z picks the slice).  Per stage of 16 input
-// channels it marches through its planes: LDS holds a ring of four input planes
-// ((kTY + 2) rows x (kTX + 2) voxels each, halo included), so each input plane is
-// copied in once per stage rather than once for every output plane that reads it,
-// and the next plane's loads are in flight while a plane's products run.  Each
+// channels it copies the ZC + 2 input planes its planes read ((kTY + 2) rows x
+// (kTX + 2) voxels each, halo included) straight from global memory into LDS, all
+// in flight at once and with no registers in between, so each input plane is copied
+// once per stage rather than once for every output plane that reads it.  Each
 // wave takes one row: per K chunk of 32 (two taps of the 16 channels) it reads four
 // input fragments from LDS (four 16-voxel tiles), holds NT weight fragments (the
 // same for every wave) and issues 4 x NT MFMAs, so an input fragment feeds NT
@@ -53,7 +53,19 @@ struct ConvArgs {
     float *y32;
     int ldx, offx, ldy, offy;
     int nz, ny, nx, cin, cout, kpad, relu;
+    uint32_t xbytes, plane_bytes;  // bytes of x and of one of its planes
+    uint32_t wbytes;               // bytes of w
 };
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// dword 3 of a raw (untyped, unswizzled) buffer resource on the gfx9 family
+constexpr int kRawBuffer = 0x00020000;
+// Input planes and weights are read through buffer resources with 32-bit offsets:
+// x and w stay below 2 GiB so that kNoOff lies past their ends, and a load at kNoOff
+// returns zeros (the staged entries outside the grid, the weights past the 27th tap).
+constexpr int64_t kMaxX = ((int64_t)1 << 31) - 16;
+constexpr uint32_t kNoOff = 0x80000000u;
 
 constexpr int kTX = 64, kTY = 4;            // voxels of a workgroup in each of its planes: 4 rows of 64
 constexpr int kBX = kTX + 2, kBY = kTY + 2; // an input plane, halo included
@@ -66,14 +78,14 @@ constexpr int kKC = 14;  // K chunks of 32 per stage: 27 taps x 16 channels, the
 constexpr int kPS = (2 * kPlane + 255) / 256;  // 16-byte loads per thread and input plane
 
 // output planes per workgroup: the accumulators of ZC planes and the stage's weight
-// fragments stay in registers (254 VGPRs at ZC = 3); each stage's first loads are
-// exposed once per ZC planes
+// fragments stay in registers (218 VGPRs at ZC = 3, two workgroups per CU); each
+// stage's loads are exposed once per ZC planes
 __host__ __device__ constexpr int conv_planes(int nt) { return nt == 1 ? 3 : 1; }
 
 template <int NT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_conv_fwd(ConvArgs a) {
     constexpr int ZC = conv_planes(NT);
-    __shared__ __attribute__((aligned(16))) uint16_t ring[4 * kPlane * kVS];
+    __shared__ __attribute__((aligned(16))) uint16_t slab[(ZC + 2) * kPlane * kVS];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nxt = (a.nx + kTX - 1) / kTX;
     const int x0 = (int)(blockIdx.x % nxt) * kTX, y0 = (int)(blockIdx.x / nxt) * kTY;
@@ -89,91 +101,87 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             for (int n = 0; n < NT; ++n) acc[p][t][n] = (f32x4){0.f, 0.f, 0.f, 0.f};
     // this lane's two taps per K chunk: tap = 2 q + (kb >> 1), channels 8 (kb & 1) .. + 7
     const int chan = 8 * (kb & 1);
-    const uint16_t *wrow[NT];
+    // weights through a buffer resource: this lane's byte offset of output channel
+    // co0 + 16 n + m, its tap parity kb >> 1 and channel half; the chunk's part is uniform
+    const __amdgpu_buffer_rsrc_t rw =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t *>(a.w), (short)0, (int)a.wbytes, kRawBuffer);
+    uint32_t woff[NT];
 #pragma unroll
-    for (int n = 0; n < NT; ++n) wrow[n] = a.w + (int64_t)(co0 + 16 * n + m) * a.kpad + chan;
-    // this thread's share of one input plane (zeros outside the grid)
-    auto load_plane = [&](int zz, int c0, uint4(&v)[kPS]) {
+    for (int n = 0; n < NT; ++n) woff[n] = 2u * (uint32_t)((co0 + 16 * n + m) * a.kpad + (kb >> 1) * a.cin + chan);
+    // One input plane straight from global memory into slot `slot` of the LDS slab:
+    // 16 bytes per lane, lanes landing on consecutive 16-byte LDS entries (voxel-major,
+    // two entries per voxel).  poff: this thread's byte offsets within a plane of x,
+    // or kNoOff outside the grid.
+    const __amdgpu_buffer_rsrc_t rx =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t *>(a.x), (short)0, (int)a.xbytes, kRawBuffer);
+    uint32_t poff[kPS];
+#pragma unroll
+    for (int it = 0; it < kPS; ++it) {
+        const int e = tid + 256 * it, bv = e >> 1, h = e & 1;
+        const int xx = x0 + bv % kBX - 1, yy = y0 + bv / kBX - 1;
+        const bool in = xx >= 0 && xx < a.nx && yy >= 0 && yy < a.ny;
+        poff[it] = in ? 2u * (uint32_t)((yy * a.nx + xx) * a.ldx + a.offx + 8 * h) : kNoOff;
+    }
+    auto dma_plane = [&](int zz, int c0, int slot) {
+        const bool zin = zz >= 0 && zz < a.nz;  // else the whole plane reads as zeros
+        const uint32_t zoff = zin ? (uint32_t)zz * a.plane_bytes + 2u * (uint32_t)c0 : 0u;
 #pragma unroll
         for (int it = 0; it < kPS; ++it) {
-            const int e = tid + 256 * it;
-            v[it] = make_uint4(0u, 0u, 0u, 0u);
-            if (e < 2 * kPlane && zz >= 0 && zz < a.nz) {
-                const int bv = e >> 1, h = e & 1;
-                const int xx = x0 + bv % kBX - 1, yy = y0 + bv / kBX - 1;
-                if (xx >= 0 && xx < a.nx && yy >= 0 && yy < a.ny) {
-                    const int64_t nb = ((int64_t)zz * a.ny + yy) * a.nx + xx;
-                    v[it] = *reinterpret_cast<const uint4 *>(a.x + nb * a.ldx + a.offx + c0 + 8 * h);
-                }
-            }
-        }
-    };
-    auto store_plane = [&](int slot, const uint4(&v)[kPS]) {
-#pragma unroll
-        for (int it = 0; it < kPS; ++it) {
-            const int e = tid + 256 * it;
-            if (e < 2 * kPlane) *reinterpret_cast<uint4 *>(&ring[(slot * kPlane + (e >> 1)) * kVS + 8 * (e & 1)]) = v[it];
+            const int e0 = 256 * it + 64 * wave, e = e0 + lane;
+            if (e0 >= 2 * kPlane) break;  // wave-uniform
+            if (e < 2 * kPlane)
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rx, (lds_void *)(slab + (slot * kPlane * kVS + 8 * e0)), 16,
+                                                         zin ? poff[it] : kNoOff, zoff, 0, 0);
         }
     };
     for (int c0 = 0; c0 < a.cin; c0 += kCC) {
-        // the stage's weight fragments: K chunk q, output tile n (zero past the 27th tap)
+        __syncthreads();  // the previous stage's reads of the slab are done
+        // every input plane of the stage in flight at once (plane z0 - 1 + s in slot s),
+        // and with them the stage's weight fragments: K chunk q, output tile n (zero
+        // past the 27th tap)
+#pragma unroll
+        for (int s = 0; s < ZC + 2; ++s) dma_plane(z0 - 1 + s, c0, s);
         bf16x8 B[kKC][NT];
 #pragma unroll
         for (int q = 0; q < kKC; ++q) {
             const int tap = 2 * q + (kb >> 1);
 #pragma unroll
             for (int n = 0; n < NT; ++n) {
-                uint4 bv = make_uint4(0u, 0u, 0u, 0u);
-                if (tap < 27) bv = *reinterpret_cast<const uint4 *>(wrow[n] + tap * a.cin + c0);
-                B[q][n] = __builtin_bit_cast(bf16x8, bv);
+                // past the 27th tap the offset lies past w: zeros
+                const uint32_t vo = tap < 27 ? woff[n] : kNoOff;
+                B[q][n] = __builtin_bit_cast(
+                    bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rw, vo, 2u * (uint32_t)(2 * q * a.cin + c0), 0));
             }
         }
-        uint4 v[kPS];
-        {
-            // the three planes of the first output plane's brick, their loads in flight together
-            uint4 v0[kPS], v1[kPS];
-            load_plane(z0 - 1, c0, v0);
-            load_plane(z0, c0, v1);
-            load_plane(z0 + 1, c0, v);
-            __syncthreads();  // the previous stage's reads of the ring are done
-            // input plane z0 - 1 + i sits in ring slot i & 3
-            store_plane(0, v0);
-            store_plane(1, v1);
-        }
+        __syncthreads();  // waits for the copies (vmcnt) and publishes them
 #pragma unroll
         for (int p = 0; p < ZC; ++p) {
-            // Slot (p + 2) & 3 last held plane z0 + p - 3, read by the products of
-            // output plane p - 2, which every wave finished before the barrier of
-            // step p - 1: one barrier per plane suffices.
-            store_plane((p + 2) & 3, v);  // input plane z0 + p + 1
-            __syncthreads();
-            if (p + 1 < ZC) load_plane(z0 + p + 2, c0, v);  // in flight during the products below
-            // A fragments of K chunk q from the ring (zero past the 27th tap)
+            // A fragments of K chunk q from the slab (zero past the 27th tap)
             auto read_a = [&](int q, bf16x8(&A)[4]) {
                 const int tap = 2 * q + (kb >> 1);
-                const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;  // 0..2: offsets within the ring
-                const int base = ((p + dz) & 3) * kPlane + (wave + dy) * kBX + m + dx;
+                const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;  // dz 0..2 from the output plane's slot
+                const int base = (p + dz) * kPlane + (wave + dy) * kBX + m + dx;
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     uint4 av = make_uint4(0u, 0u, 0u, 0u);
-                    if (tap < 27) av = *reinterpret_cast<const uint4 *>(&ring[(base + 16 * t) * kVS + chan]);
+                    if (tap < 27) av = *reinterpret_cast<const uint4 *>(&slab[(base + 16 * t) * kVS + chan]);
                     A[t] = __builtin_bit_cast(bf16x8, av);
                 }
             };
-            // one K chunk ahead: the next chunk's LDS reads run under this chunk's products
-            bf16x8 Ac[4], An[4];
-            read_a(0, Ac);
+            // one K chunk ahead, into the other of two fragment sets (chunk parity, no
+            // copies): the next chunk's LDS reads run under this chunk's products
+            bf16x8 Af[2][4];
+            read_a(0, Af[0]);
 #pragma unroll
             for (int q = 0; q < kKC; ++q) {
-                if (q + 1 < kKC) read_a(q + 1, An);
+                if (q + 1 < kKC) read_a(q + 1, Af[(q + 1) & 1]);
+                __builtin_amdgcn_sched_barrier(0);  // the reads go out ahead of the products
 #pragma unroll
                 for (int t = 0; t < 4; ++t)
 #pragma unroll
                     for (int n = 0; n < NT; ++n)
-                        acc[p][t][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(B[q][n], Ac[t], acc[p][t][n], 0, 0, 0);
+                        acc[p][t][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(B[q][n], Af[q & 1][t], acc[p][t][n], 0, 0, 0);
                 __builtin_amdgcn_sched_barrier(0);  // keep later chunks' reads out of this one
-#pragma unroll
-                for (int t = 0; t < 4; ++t) Ac[t] = An[t];
             }
         }
     }
@@ -646,7 +654,11 @@ int unet_conv3d_fwd(const uint16_t *x, int32_t ldx, int32_t offx, const uint16_t
         return -1;  // 16-byte vector loads and stores
     const int tiles = cout / 16;
     const int nt = 1;  // one 16-channel tile per wave: its 14 weight fragments stay in registers
-    ConvArgs a{x, w, b, y, y32, ldx, offx, ldy, offy, nz, ny, nx, cin, cout, kpad_of(cin), relu};
+    const int64_t plane_bytes = 2 * (int64_t)ny * nx * ldx, xbytes = plane_bytes * nz;
+    const int64_t wbytes = 2 * (int64_t)cout * kpad_of(cin);
+    if (xbytes > kMaxX || wbytes > kMaxX) return -1;
+    ConvArgs a{x, w, b, y, y32, ldx, offx, ldy, offy, nz, ny, nx, cin, cout, kpad_of(cin), relu,
+               (uint32_t)xbytes, (uint32_t)plane_bytes, (uint32_t)wbytes};
     const int64_t nxy = (int64_t)((nx + kTX - 1) / kTX) * ((ny + kTY - 1) / kTY);
     if (nxy > 0x7fffffff) return -1;
     const int zc = conv_planes(nt);
