@@ -434,6 +434,30 @@ def test_unet_handle_layout_on_the_host():
     lib.unet_destroy(None)
 
 
+def test_convolution_refuses_bad_operands_without_touching_the_device():
+    """unet_conv3d_fwd checks its operands before any device call: channel counts
+    and strides off their multiples, pointers that are not 16-byte aligned, and an
+    input or weight array of 2 GiB or more (its loads use 32-bit offsets) are -1.
+    The pointers are never dereferenced."""
+    from paper_1410_1914_amd import unet
+
+    lib = unet.load()
+    base = 1 << 20  # 16-byte aligned, never read
+
+    def conv(x=base, w=base, y=base, y32=None, ldx=16, offx=0, ldy=16, offy=0, shape=(4, 4, 4), cin=16, cout=16):
+        return lib.unet_conv3d_fwd(x, ldx, offx, w, None, y, ldy, offy, y32, *shape, cin, cout, 1, None)
+
+    assert conv(cin=24) == -1 and conv(cout=8) == -1
+    assert conv(ldx=20) == -1 and conv(offy=4, ldy=24) == -1 and conv(ldx=16, offx=8) == -1
+    for bad in (dict(x=base + 8), dict(w=base + 2), dict(y=base + 4), dict(y32=base + 8)):
+        assert conv(**bad) == -1, bad
+    # 2 GiB of input: 1024 x 1024 x 64 voxels of 16 BF16 channels; and of weights
+    assert conv(shape=(64, 1024, 1024)) == -1
+    cout = 16 * 150000  # cout x unet_kpad(16) BF16 weights: 2.15 GB
+    assert 2 * cout * unet.unet_kpad(16) >= 1 << 31
+    assert conv(cout=cout, ldy=cout) == -1
+
+
 def test_device_preparation_refuses_a_bad_scratch_without_touching_the_device():
     """lbm_create_device checks the caller's scratch before any device call: a
     misaligned or too small scratch is LBM_ERR_WORKSPACE."""
