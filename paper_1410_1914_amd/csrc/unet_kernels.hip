@@ -34,8 +34,8 @@ int status(hipError_t e) { return e == hipSuccess ? 0 : -6; }
 //   A[m][k]: lane l holds m = l % 16, k = 8 (l / 16) + j;  B[k][n]: n = l % 16, same k;
 //   D[m][n]: lane l holds m = 4 (l / 16) + i, n = l % 16.
 // A workgroup (4 waves) owns kTY rows of kTX voxels in ZC consecutive planes and
-// 16 * NT output channels (blockIdx.z picks the slice).  Per stage of 16 input
-// channels it copies the ZC + 2 input planes its planes read ((kTY + 2) rows x
+// 16 * NT output channels (a channel slice).  Per stage of 16 input channels it
+// copies the ZC + 2 input planes its planes read ((kTY + 2) rows x
 // (kTX + 2) voxels each, halo included) straight from global memory into LDS, all
 // in flight at once and with no registers in between, so each input plane is copied
 // once per stage rather than once for every output plane that reads it.  Each
@@ -77,20 +77,39 @@ constexpr int kVS = 16;  // LDS elements per voxel: the 16 channels, unpadded.  
 constexpr int kKC = 14;  // K chunks of 32 per stage: 27 taps x 16 channels, the last half empty
 constexpr int kPS = (2 * kPlane + 255) / 256;  // 16-byte loads per thread and input plane
 
-// output planes per workgroup: the accumulators of ZC planes and the stage's weight
-// fragments stay in registers (218 VGPRs at ZC = 3, two workgroups per CU); each
-// stage's loads are exposed once per ZC planes
-__host__ __device__ constexpr int conv_planes(int nt) { return nt == 1 ? 3 : 1; }
+// ZC output planes per workgroup: the accumulators of ZC planes and the stage's
+// weight fragments stay in registers (218 VGPRs at ZC = 3, 256 at ZC = 4; two
+// workgroups per CU, 63 or 76 KB of LDS each).  A tile re-reads (ZC + 2) / ZC of its
+// input planes, and each stage's loads are exposed once per ZC planes, so larger
+// grids take ZC = 4; small ones keep ZC = 3 for more workgroups.
+constexpr int kZcLargeGrid = 2048;  // workgroups at ZC = 4 from which ZC = 4 is used
 
-template <int NT>
+template <int NT, int ZC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_conv_fwd(ConvArgs a) {
-    constexpr int ZC = conv_planes(NT);
     __shared__ __attribute__((aligned(16))) uint16_t slab[(ZC + 2) * kPlane * kVS];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nxt = (a.nx + kTX - 1) / kTX;
-    const int x0 = (int)(blockIdx.x % nxt) * kTX, y0 = (int)(blockIdx.x / nxt) * kTY;
-    const int z0 = (int)blockIdx.y * ZC;
-    const int co0 = (int)blockIdx.z * 16 * NT;
+    // Workgroups reach the 8 XCDs round-robin by launch index b; XCD b % 8 takes a
+    // contiguous eighth of the tile order below, so that tiles sharing input rows
+    // and planes run together under one L2 (the input copies are the kernel's
+    // bottleneck: each tile reads 5/3 x 6/4 of its own input).
+    const int nblk = (int)(gridDim.x * gridDim.y * gridDim.z);
+    const int b = (int)(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z));
+    const int xcd = b % 8, per = nblk / 8, extra = nblk % 8;
+    const int t = xcd * per + min(xcd, extra) + b / 8;
+    // Within a channel slice the tiles go in bands of kYB tile rows in y: x fastest,
+    // then y within the band, then the plane chunks, then the bands (the last band
+    // may be shorter), so that tiles sharing input rows or planes are close in order.
+    constexpr int kYB = 4;
+    const int nyt = (int)gridDim.x / nxt, nzc = (int)gridDim.y;
+    const int per_slice = (int)gridDim.x * nzc;
+    const int slice = t / per_slice, rem = t % per_slice;
+    const int band = rem / (nxt * kYB * nzc), in_band = rem % (nxt * kYB * nzc);
+    const int h = min(kYB, nyt - band * kYB);
+    const int xt = in_band % nxt, yin = (in_band / nxt) % h, zc = in_band / (nxt * h);
+    const int x0 = xt * kTX, y0 = (band * kYB + yin) * kTY;
+    const int z0 = zc * ZC;
+    const int co0 = slice * 16 * NT;
     const int m = lane & 15, kb = lane >> 4;
     f32x4 acc[ZC][4][NT];
 #pragma unroll
@@ -661,11 +680,15 @@ int unet_conv3d_fwd(const uint16_t *x, int32_t ldx, int32_t offx, const uint16_t
                (uint32_t)xbytes, (uint32_t)plane_bytes, (uint32_t)wbytes};
     const int64_t nxy = (int64_t)((nx + kTX - 1) / kTX) * ((ny + kTY - 1) / kTY);
     if (nxy > 0x7fffffff) return -1;
-    const int zc = conv_planes(nt);
+    const bool large = nxy * ((nz + 3) / 4) * (tiles / nt) >= kZcLargeGrid;
+    const int zc = large ? 4 : 3;
     const dim3 g((unsigned)nxy, (unsigned)((nz + zc - 1) / zc), (unsigned)(tiles / nt)), blk(256);
     hipStream_t st = static_cast<hipStream_t>(stream);
     (void)hipGetLastError();
-    hipLaunchKernelGGL(k_conv_fwd<1>, g, blk, 0, st, a);
+    if (large)
+        hipLaunchKernelGGL((k_conv_fwd<1, 4>), g, blk, 0, st, a);
+    else
+        hipLaunchKernelGGL((k_conv_fwd<1, 3>), g, blk, 0, st, a);
     return status(hipGetLastError());
 }
 
