@@ -47,6 +47,21 @@ int unet_conv3d_fwd(const uint16_t *x, int32_t ldx, int32_t offx, const uint16_t
                     uint16_t *y, int32_t ldy, int32_t offy, float *y32, int32_t nz, int32_t ny, int32_t nx,
                     int32_t cin, int32_t cout, int32_t relu, void *stream);
 
+/* unet_conv3d_fwd over the concatenation of a full-resolution tensor and a
+ * nearest-upsampled half-resolution one, without storing it: input channels
+ * 0 .. cin1 - 1 are x (rows of ldx elements at offx on the nz x ny x nx grid) and
+ * channels cin1 .. cin - 1 are x2 (rows of ldx2 at offx2 on the nz/2 x ny/2 x nx/2
+ * grid; voxel (z, y, x) reads x2 at (z/2, y/2, x/2)).  This is the U-Net decoder's
+ * input; the results equal unet_up_fwd into the rows of a concatenation followed by
+ * unet_conv3d_fwd on them.  w is [cout][unet_kpad(cin)] over the concatenated
+ * channels.  nz, ny and nx even, cin1 and cin - cin1 positive multiples of 16, x2
+ * 16-byte aligned and below 2 GiB, ldx2 and offx2 multiples of 8; the rest as for
+ * unet_conv3d_fwd; else -1. */
+int unet_conv3d_fwd_cat(const uint16_t *x, int32_t ldx, int32_t offx, int32_t cin1, const uint16_t *x2,
+                        int32_t ldx2, int32_t offx2, const uint16_t *w, const float *b, uint16_t *y, int32_t ldy,
+                        int32_t offy, float *y32, int32_t nz, int32_t ny, int32_t nx, int32_t cin, int32_t cout,
+                        int32_t relu, void *stream);
+
 /* Weights of the backward-data convolution: wt[ci, tap' * cout + co] =
  * w[co, (26 - tap') * cin + ci]; wt has kpad = unet_kpad(cout).  Running
  * unet_conv3d_fwd with wt (cin and cout swapped, no bias, no ReLU) on dy gives dx. */

@@ -55,6 +55,12 @@ struct ConvArgs {
     int nz, ny, nx, cin, cout, kpad, relu;
     uint32_t xbytes, plane_bytes;  // bytes of x and of one of its planes
     uint32_t wbytes;               // bytes of w
+    // Input channels [cin1, cin) come from x2 instead (the concatenation of a skip
+    // tensor and an upsampled one, never stored): rows of ldx2 at offset offx2, at
+    // half resolution in every direction when up2 (nearest upsampling).
+    const uint16_t *x2;
+    int ldx2, offx2, cin1, up2;
+    uint32_t x2bytes, plane2_bytes;
 };
 
 typedef __attribute__((address_space(3))) void lds_void;
@@ -129,31 +135,41 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     for (int n = 0; n < NT; ++n) woff[n] = 2u * (uint32_t)((co0 + 16 * n + m) * a.kpad + (kb >> 1) * a.cin + chan);
     // One input plane straight from global memory into slot `slot` of the LDS slab:
     // 16 bytes per lane, lanes landing on consecutive 16-byte LDS entries (voxel-major,
-    // two entries per voxel).  poff: this thread's byte offsets within a plane of x,
-    // or kNoOff outside the grid.
+    // two entries per voxel).  poff: this thread's byte offsets within a plane of the
+    // stage's source, or kNoOff outside the grid.
     const __amdgpu_buffer_rsrc_t rx =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t *>(a.x), (short)0, (int)a.xbytes, kRawBuffer);
+    const __amdgpu_buffer_rsrc_t rx2 =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t *>(a.x2), (short)0, (int)a.x2bytes, kRawBuffer);
     uint32_t poff[kPS];
+    auto source_offsets = [&](bool second) {
+        const int sh = second && a.up2 ? 1 : 0, ld = second ? a.ldx2 : a.ldx, off = second ? a.offx2 : a.offx;
 #pragma unroll
-    for (int it = 0; it < kPS; ++it) {
-        const int e = tid + 256 * it, bv = e >> 1, h = e & 1;
-        const int xx = x0 + bv % kBX - 1, yy = y0 + bv / kBX - 1;
-        const bool in = xx >= 0 && xx < a.nx && yy >= 0 && yy < a.ny;
-        poff[it] = in ? 2u * (uint32_t)((yy * a.nx + xx) * a.ldx + a.offx + 8 * h) : kNoOff;
-    }
+        for (int it = 0; it < kPS; ++it) {
+            const int e = tid + 256 * it, bv = e >> 1, h = e & 1;
+            const int xx = x0 + bv % kBX - 1, yy = y0 + bv / kBX - 1;
+            const bool in = xx >= 0 && xx < a.nx && yy >= 0 && yy < a.ny;
+            poff[it] = in ? 2u * (uint32_t)(((yy >> sh) * (a.nx >> sh) + (xx >> sh)) * ld + off + 8 * h) : kNoOff;
+        }
+    };
     auto dma_plane = [&](int zz, int c0, int slot) {
+        const bool second = c0 >= a.cin1;
         const bool zin = zz >= 0 && zz < a.nz;  // else the whole plane reads as zeros
-        const uint32_t zoff = zin ? (uint32_t)zz * a.plane_bytes + 2u * (uint32_t)c0 : 0u;
+        const uint32_t zoff = !zin ? 0u
+                              : second ? (uint32_t)(a.up2 ? zz >> 1 : zz) * a.plane2_bytes + 2u * (uint32_t)(c0 - a.cin1)
+                                       : (uint32_t)zz * a.plane_bytes + 2u * (uint32_t)c0;
 #pragma unroll
         for (int it = 0; it < kPS; ++it) {
             const int e0 = 256 * it + 64 * wave, e = e0 + lane;
             if (e0 >= 2 * kPlane) break;  // wave-uniform
             if (e < 2 * kPlane)
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(rx, (lds_void *)(slab + (slot * kPlane * kVS + 8 * e0)), 16,
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(second ? rx2 : rx,
+                                                         (lds_void *)(slab + (slot * kPlane * kVS + 8 * e0)), 16,
                                                          zin ? poff[it] : kNoOff, zoff, 0, 0);
         }
     };
     for (int c0 = 0; c0 < a.cin; c0 += kCC) {
+        if (c0 == 0 || c0 == a.cin1) source_offsets(c0 >= a.cin1);
         __syncthreads();  // the previous stage's reads of the slab are done
         // every input plane of the stage in flight at once (plane z0 - 1 + s in slot s),
         // and with them the stage's weight fragments: K chunk q, output tile n (zero
@@ -661,23 +677,30 @@ extern "C" {
 
 int32_t unet_kpad(int32_t cin) { return kpad_of(cin); }
 
-int unet_conv3d_fwd(const uint16_t *x, int32_t ldx, int32_t offx, const uint16_t *w, const float *b, uint16_t *y,
-                    int32_t ldy, int32_t offy, float *y32, int32_t nz, int32_t ny, int32_t nx, int32_t cin,
-                    int32_t cout, int32_t relu, void *stream) {
-    if (!x || !w || !y || nz <= 0 || ny <= 0 || nx <= 0 || cin % 16 || !ch_ok(ldx, offx, cin) ||
-        !ch_ok(ldy, offy, cout) || (ldx % 8) || (offx % 8) || (ldy % 8) || (offy % 8))
+// both convolution entry points: a.x2 is a.x and a.cin1 a.cin for a single input
+static int launch_conv(ConvArgs a, int64_t nx2, int64_t ny2, int64_t nz2, void *stream) {
+    const int nx = a.nx, ny = a.ny, nz = a.nz, cin = a.cin, cout = a.cout;
+    if (!a.x || !a.x2 || !a.w || !a.y || nz <= 0 || ny <= 0 || nx <= 0 || cin % 16 || a.cin1 % 16 || a.cin1 <= 0 ||
+        a.cin1 > cin || !ch_ok(a.ldx, a.offx, a.cin1) || (a.cin1 < cin && !ch_ok(a.ldx2, a.offx2, cin - a.cin1)) ||
+        !ch_ok(a.ldy, a.offy, cout) || (a.ldx % 8) || (a.offx % 8) || (a.ldx2 % 8) || (a.offx2 % 8) || (a.ldy % 8) ||
+        (a.offy % 8))
         return -1;
     if (cout % 16 || nz > 65535) return -1;
-    if ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(w) | reinterpret_cast<uintptr_t>(y) |
-         reinterpret_cast<uintptr_t>(y32)) & 15)
+    if ((reinterpret_cast<uintptr_t>(a.x) | reinterpret_cast<uintptr_t>(a.x2) | reinterpret_cast<uintptr_t>(a.w) |
+         reinterpret_cast<uintptr_t>(a.y) | reinterpret_cast<uintptr_t>(a.y32)) & 15)
         return -1;  // 16-byte vector loads and stores
     const int tiles = cout / 16;
     const int nt = 1;  // one 16-channel tile per wave: its 14 weight fragments stay in registers
-    const int64_t plane_bytes = 2 * (int64_t)ny * nx * ldx, xbytes = plane_bytes * nz;
+    const int64_t plane_bytes = 2 * (int64_t)ny * nx * a.ldx, xbytes = plane_bytes * nz;
+    const int64_t plane2_bytes = 2 * ny2 * nx2 * a.ldx2, x2bytes = plane2_bytes * nz2;
     const int64_t wbytes = 2 * (int64_t)cout * kpad_of(cin);
-    if (xbytes > kMaxX || wbytes > kMaxX) return -1;
-    ConvArgs a{x, w, b, y, y32, ldx, offx, ldy, offy, nz, ny, nx, cin, cout, kpad_of(cin), relu,
-               (uint32_t)xbytes, (uint32_t)plane_bytes, (uint32_t)wbytes};
+    if (xbytes > kMaxX || x2bytes > kMaxX || wbytes > kMaxX) return -1;
+    a.kpad = kpad_of(cin);
+    a.xbytes = (uint32_t)xbytes;
+    a.plane_bytes = (uint32_t)plane_bytes;
+    a.x2bytes = (uint32_t)x2bytes;
+    a.plane2_bytes = (uint32_t)plane2_bytes;
+    a.wbytes = (uint32_t)wbytes;
     const int64_t nxy = (int64_t)((nx + kTX - 1) / kTX) * ((ny + kTY - 1) / kTY);
     if (nxy > 0x7fffffff) return -1;
     const bool large = nxy * ((nz + 3) / 4) * (tiles / nt) >= kZcLargeGrid;
@@ -690,6 +713,25 @@ int unet_conv3d_fwd(const uint16_t *x, int32_t ldx, int32_t offx, const uint16_t
     else
         hipLaunchKernelGGL((k_conv_fwd<1, 3>), g, blk, 0, st, a);
     return status(hipGetLastError());
+}
+
+int unet_conv3d_fwd(const uint16_t *x, int32_t ldx, int32_t offx, const uint16_t *w, const float *b, uint16_t *y,
+                    int32_t ldy, int32_t offy, float *y32, int32_t nz, int32_t ny, int32_t nx, int32_t cin,
+                    int32_t cout, int32_t relu, void *stream) {
+    ConvArgs a{x, w, b, y, y32, ldx, offx, ldy, offy, nz, ny, nx, cin, cout, 0, relu, 0, 0, 0,
+               x, ldx, offx, cin, 0, 0, 0};
+    return launch_conv(a, nx, ny, nz, stream);
+}
+
+int unet_conv3d_fwd_cat(const uint16_t *x, int32_t ldx, int32_t offx, int32_t cin1, const uint16_t *x2, int32_t ldx2,
+                        int32_t offx2, const uint16_t *w, const float *b, uint16_t *y, int32_t ldy, int32_t offy,
+                        float *y32, int32_t nz, int32_t ny, int32_t nx, int32_t cin, int32_t cout, int32_t relu,
+                        void *stream) {
+    if (nz % 2 || ny % 2 || nx % 2) return -1;  // x2 holds the half-resolution grid
+    ConvArgs a{x, w, b, y, y32, ldx, offx, ldy, offy, nz, ny, nx, cin, cout, 0, relu, 0, 0, 0,
+               x2, ldx2, offx2, cin1, 1, 0, 0};
+    if (cin1 >= cin) return -1;
+    return launch_conv(a, nx / 2, ny / 2, nz / 2, stream);
 }
 
 int unet_conv3d_wtrans(const uint16_t *w, uint16_t *wt, int32_t cin, int32_t cout, void *stream) {

@@ -134,12 +134,47 @@ struct unet_net {
                                       d[2], kSpec[l].cin, kSpec[l].cout, relu ? 1 : 0, st));
     }
 
+    // a decoder convolution of layer l on level lev over [skip x (c1 channels), the
+    // level below's x2 (c2 channels) upsampled], the concatenation never stored
+    hipError_t conv_cat(int l, const uint16_t *x, int c1, const uint16_t *x2, int c2, uint16_t *y, int lev) {
+        const int *d = dims[lev];
+        return to_hip(unet_conv3d_fwd_cat(x, c1, 0, c1, x2, c2, 0, pb() + P.w[l], p() + P.b[l], y, kSpec[l].cout, 0,
+                                          nullptr, d[0], d[1], d[2], kSpec[l].cin, kSpec[l].cout, 1, st));
+    }
+
     hipError_t forward(const uint16_t *feat, const float *base, float *out) {
         hipError_t e = hipSuccess;
         auto run = [&](hipError_t r) {
             if (e == hipSuccess) e = r;
         };
         const int *d0 = dims[0], *d1 = dims[1], *d2 = dims[2];
+        if (!train) {
+            // Inference: each skip tensor stays in rows of its own channels (in the
+            // front of its concatenation's buffer) and each decoder convolution reads
+            // the level below upsampled in place, so no concatenation is written and
+            // pooling reads whole rows.  Training keeps the concatenations: the weight
+            // gradients read them.
+            run(conv(E1A, feat, kIn, 0, act(A_A1), kC1, 0, 0, true));
+            run(conv(E1B, act(A_A1), kC1, 0, act(A_CAT1), kC1, 0, 0, true));
+            run(to_hip(unet_pool_fwd(act(A_CAT1), kC1, 0, act(A_P2), kC1, 0, d0[0], d0[1], d0[2], kC1, st)));
+            run(conv(E2A, act(A_P2), kC1, 0, act(A_A2), kC2, 0, 1, true));
+            run(conv(E2B, act(A_A2), kC2, 0, act(A_CAT2), kC2, 0, 1, true));
+            run(to_hip(unet_pool_fwd(act(A_CAT2), kC2, 0, act(A_P3), kC2, 0, d1[0], d1[1], d1[2], kC2, st)));
+            run(conv(E3A, act(A_P3), kC2, 0, act(A_A3), kC3, 0, 2, true));
+            run(conv(E3B, act(A_A3), kC3, 0, act(A_CAT3), kC3, 0, 2, true));
+            run(to_hip(unet_pool_fwd(act(A_CAT3), kC3, 0, act(A_P4), kC3, 0, d2[0], d2[1], d2[2], kC3, st)));
+            run(conv(B4A, act(A_P4), kC3, 0, act(A_B4A), kC4, 0, 3, true));
+            run(conv(B4B, act(A_B4A), kC4, 0, act(A_B4B), kC4, 0, 3, true));
+            run(conv_cat(D3A, act(A_CAT3), kC3, act(A_B4B), kC4, act(A_D3A), 2));
+            run(conv(D3B, act(A_D3A), kC3, 0, act(A_D3B), kC3, 0, 2, true));
+            run(conv_cat(D2A, act(A_CAT2), kC2, act(A_D3B), kC3, act(A_D2A), 1));
+            run(conv(D2B, act(A_D2A), kC2, 0, act(A_D2B), kC2, 0, 1, true));
+            run(conv_cat(D1A, act(A_CAT1), kC1, act(A_D2B), kC2, act(A_D1A), 0));
+            run(conv(D1B, act(A_D1A), kC1, 0, act(A_D1B), kC1, 0, 0, true));
+            run(to_hip(unet_head_fwd(act(A_D1B), kC1, p() + P.w[kLayers], p() + P.b[kLayers], base, out, vox[0],
+                                     kC1, st)));
+            return e;
+        }
         run(conv(E1A, feat, kIn, 0, act(A_A1), kC1, 0, 0, true));
         run(conv(E1B, act(A_A1), kC1, 0, act(A_CAT1), kC1 + kC2, 0, 0, true));
         run(to_hip(unet_pool_fwd(act(A_CAT1), kC1 + kC2, 0, act(A_P2), kC1, 0, d0[0], d0[1], d0[2], kC1, st)));

@@ -26,6 +26,8 @@ _i32, _i64, _f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
 SIGNATURES = {
     "unet_kpad": ([_i32], _i32),
     "unet_conv3d_fwd": ([_P, _i32, _i32, _P, _P, _P, _i32, _i32, _P, _i32, _i32, _i32, _i32, _i32, _i32, _P], _i32),
+    "unet_conv3d_fwd_cat": ([_P, _i32, _i32, _i32, _P, _i32, _i32, _P, _P, _P, _i32, _i32, _P, _i32, _i32, _i32, _i32,
+                             _i32, _i32, _P], _i32),
     "unet_conv3d_wtrans": ([_P, _P, _i32, _i32, _P], _i32),
     "unet_conv3d_wgrad": ([_P, _i32, _i32, _P, _i32, _i32, _i32, _i32, _i32, _i32, _i32, _P, _P, _P], _i32),
     "unet_relu_bwd": ([_P, _i32, _i32, _P, _i32, _i32, _i64, _i32, _P], _i32),
@@ -113,6 +115,12 @@ def unet_conv3d_fwd(x, ldx, offx, w, b, y, ldy, offy, y32, shape, cin, cout, rel
     nz, ny, nx = shape
     _call("unet_conv3d_fwd", _ptr(x), ldx, offx, _ptr(w), _ptr(b), _ptr(y), ldy, offy, _ptr(y32), nz, ny, nx, cin,
           cout, int(relu), _stream())
+
+
+def unet_conv3d_fwd_cat(x, ldx, offx, cin1, x2, ldx2, offx2, w, b, y, ldy, offy, y32, shape, cin, cout, relu):
+    nz, ny, nx = shape
+    _call("unet_conv3d_fwd_cat", _ptr(x), ldx, offx, cin1, _ptr(x2), ldx2, offx2, _ptr(w), _ptr(b), _ptr(y), ldy, offy,
+          _ptr(y32), nz, ny, nx, cin, cout, int(relu), _stream())
 
 
 def unet_conv3d_wtrans(w, wt, cin, cout):

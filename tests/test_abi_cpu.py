@@ -435,10 +435,11 @@ def test_unet_handle_layout_on_the_host():
 
 
 def test_convolution_refuses_bad_operands_without_touching_the_device():
-    """unet_conv3d_fwd checks its operands before any device call: channel counts
-    and strides off their multiples, pointers that are not 16-byte aligned, and an
-    input or weight array of 2 GiB or more (its loads use 32-bit offsets) are -1.
-    The pointers are never dereferenced."""
+    """unet_conv3d_fwd and unet_conv3d_fwd_cat check their operands before any device
+    call: channel counts and strides off their multiples, pointers that are not
+    16-byte aligned, an input or weight array of 2 GiB or more (the loads use 32-bit
+    offsets), and for the concatenation an odd grid or a missing part are -1.  The
+    pointers are never dereferenced."""
     from paper_1410_1914_amd import unet
 
     lib = unet.load()
@@ -456,6 +457,14 @@ def test_convolution_refuses_bad_operands_without_touching_the_device():
     cout = 16 * 150000  # cout x unet_kpad(16) BF16 weights: 2.15 GB
     assert 2 * cout * unet.unet_kpad(16) >= 1 << 31
     assert conv(cout=cout, ldy=cout) == -1
+
+    # the concatenation form: an even grid, both parts present, x2 aligned
+    def cat(shape=(4, 4, 4), cin1=16, cin=48, x2=base, ldx2=32):
+        return lib.unet_conv3d_fwd_cat(base, 16, 0, cin1, x2, ldx2, 0, base, None, base, 16, 0, None, *shape, cin,
+                                       16, 1, None)
+
+    assert cat(shape=(4, 5, 4)) == -1 and cat(cin1=48) == -1 and cat(cin1=0) == -1
+    assert cat(x2=base + 8) == -1 and cat(ldx2=24) == -1 and cat(cin=40) == -1
 
 
 def test_device_preparation_refuses_a_bad_scratch_without_touching_the_device():

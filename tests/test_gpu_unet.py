@@ -132,6 +132,43 @@ def test_conv3d_forward_on_a_large_grid(U):
     assert np.all(gotb[..., :offy] == -7.0) and np.all(gotb[..., offy + cout:] == -7.0)
 
 
+@pytest.mark.parametrize("shape,c1,c2,cout", [((6, 10, 70), 16, 32, 16), ((26, 258, 130), 16, 32, 32),
+                                               ((4, 8, 8), 64, 128, 64)])
+def test_conv3d_forward_over_a_concatenation_with_an_upsampled_tensor(U, shape, c1, c2, cout):
+    """unet_conv3d_fwd_cat (the decoder's input read in place) equals unet_up_fwd into
+    the rows of a concatenation followed by unet_conv3d_fwd, bit for bit, on a small
+    grid, a large ragged one (the four-plane launch form) and the bottom level's
+    channel counts; on the small grids also the oracle's convolution of [x, up(x2)]."""
+    import torch
+
+    rng = np.random.default_rng(c1 + c2 + shape[0])
+    half = tuple(n // 2 for n in shape)
+    cin = c1 + c2
+    x = _bf(rng, *shape, c1)
+    x2 = _bf(rng, *half, c2)
+    w = _bf(rng, cout, 27, cin, scale=0.2)
+    b = _bf(rng, cout)
+    wd, bd = _dev_bf16(_wmat(w, cin, U.unet_kpad(cin))), _dev_f32(b)
+    cat = torch.zeros(shape + (cin,), dtype=torch.bfloat16, device="cuda")
+    cat[..., :c1] = _dev_bf16(x)
+    U.unet_up_fwd(_dev_bf16(x2), c2, 0, cat, cin, c1, shape, c2)
+    outs = []
+    for fused in (False, True):
+        y = torch.full(shape + (cout,), -7.0, dtype=torch.bfloat16, device="cuda")
+        y32 = torch.full(shape + (cout,), -7.0, dtype=torch.float32, device="cuda")
+        if fused:
+            U.unet_conv3d_fwd_cat(_dev_bf16(x), c1, 0, c1, _dev_bf16(x2), c2, 0, wd, bd, y, cout, 0, y32, shape, cin,
+                                  cout, True)
+        else:
+            U.unet_conv3d_fwd(cat, cin, 0, wd, bd, y, cout, 0, y32, shape, cin, cout, True)
+        outs.append((_host(y), _host(y32)))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    assert np.all(outs[1][1] >= 0)  # every output written (ReLU; the sentinel is negative)
+    if np.prod(shape) <= 5000:
+        ref = C.conv3d(np.concatenate([x, C.up(x2)], axis=-1), w, b, relu=True)
+        assert np.allclose(outs[1][1], ref, rtol=1e-4, atol=1e-4)
+
+
 @pytest.mark.parametrize("cin,cout", [(16, 16), (48, 16), (32, 64), (192, 64)])
 def test_conv3d_backward_data(U, cin, cout):
     import torch
