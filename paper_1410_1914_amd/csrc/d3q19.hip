@@ -83,6 +83,7 @@ struct D19Args {
     double c_in, c_out;
     int react_outlet;                   // 1: zero-gradient outlet (no open links at x = nx - 1)
     int open_inlet;                     // 1: open links at x = 0 (0 for the potential problem)
+    int reverse;                        // 1: each XCD walks its eighth of the list backwards
 };
 
 // Blocks are dealt round-robin to the 8 XCDs; give XCD k the k-th contiguous
@@ -91,6 +92,15 @@ __device__ __forceinline__ int64_t xcd_block(int b, int nblk) {
     if (nblk < 8) return b;
     const int q = nblk >> 3, r = nblk & 7, x = b & 7;
     return (int64_t)x * q + min(x, r) + (b >> 3);
+}
+
+// The same with each XCD walking its eighth backwards.  Steps alternate between
+// the two, so a step starts on the rows the previous step wrote last, still in the
+// XCD's L2 and the last-level cache.
+__device__ __forceinline__ int64_t xcd_block_reversed(int b, int nblk) {
+    if (nblk < 8) return nblk - 1 - b;
+    const int q = nblk >> 3, r = nblk & 7, x = b & 7, len = q + (x < r ? 1 : 0);
+    return (int64_t)x * q + min(x, r) + (len - 1 - (b >> 3));
 }
 
 // position of population i of compact voxel j in a lattice
@@ -137,7 +147,10 @@ template <bool REACT, bool MEASURE>
 __global__ __launch_bounds__(kBlock) void k_d3q19(D19Args a) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t e = xcd_block(blockIdx.x, a.nblk) * (kBlock / 64) + wave;
+    // lb: the logical block, which also indexes the partial sums, so that a measured
+    // step sums the same blocks in the same order in either direction
+    const int64_t lb = a.reverse ? xcd_block_reversed(blockIdx.x, a.nblk) : xcd_block(blockIdx.x, a.nblk);
+    const int64_t e = lb * (kBlock / 64) + wave;
     double acc[kRed] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (e < a.nent) {
         const D19Rec &R = a.rec[a.list[e]];
@@ -229,7 +242,7 @@ __global__ __launch_bounds__(kBlock) void k_d3q19(D19Args a) {
             const int k = threadIdx.x;
             double sm = red[0][k];
             for (int w = 1; w < kBlock / 64; ++w) sm = (k == 5 || k == 6) ? fmax(sm, red[w][k]) : sm + red[w][k];
-            a.part[(int64_t)blockIdx.x * kRed + k] = sm;
+            a.part[lb * kRed + k] = sm;
         }
     }
 }
@@ -366,6 +379,7 @@ struct lbm19_solver {
         a.c_out = P.params.c_out;
         a.react_outlet = react ? 1 : 0;
         a.open_inlet = potential ? 0 : 1;
+        a.reverse = (int)(steps & 1);
         return a;
     }
 
