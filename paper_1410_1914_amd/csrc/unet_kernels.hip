@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <algorithm>
 
 #include "../../include/unet.h"
 
@@ -89,23 +90,26 @@ constexpr int kPS = (2 * kPlane + 255) / 256;  // 16-byte loads per thread and i
 // input planes, and each stage's loads are exposed once per ZC planes, so larger
 // grids take ZC = 4; small ones keep ZC = 3 for more workgroups.
 constexpr int kZcLargeGrid = 2048;  // workgroups at ZC = 4 from which ZC = 4 is used
+constexpr int kZmWorkgroups = 3072; // the z-marching form aims for about this many workgroups
+// s_waitcnt vmcnt(0) (expcnt and lgkmcnt at their maxima: not waited for) on gfx9
+constexpr int kWaitVmcnt0 = 0x0F70;
 
-template <int NT, int ZC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_conv_fwd(ConvArgs a) {
-    __shared__ __attribute__((aligned(16))) uint16_t slab[(ZC + 2) * kPlane * kVS];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int nxt = (a.nx + kTX - 1) / kTX;
-    // Workgroups reach the 8 XCDs round-robin by launch index b; XCD b % 8 takes a
-    // contiguous eighth of the tile order below, so that tiles sharing input rows
-    // and planes run together under one L2 (the input copies are the kernel's
-    // bottleneck: each tile reads 5/3 x 6/4 of its own input).
+// The tile of this workgroup: x and y origin, plane chunk and channel slice.  The grid
+// is (x-y tiles, plane chunks, channel slices).  Workgroups reach the 8 XCDs
+// round-robin by launch index b; XCD b % 8 takes a contiguous eighth of the tile
+// order, so that tiles sharing input rows and planes run together under one L2 (the
+// input copies are the convolution's bottleneck).  Within a channel slice the tiles go
+// in bands of four tile rows in y: x fastest, then y within the band, then the plane
+// chunks, then the bands (the last band may be shorter).
+struct ConvTile {
+    int x0, y0, zc, slice;
+};
+__device__ __forceinline__ ConvTile conv_tile(int nx) {
+    const int nxt = (nx + kTX - 1) / kTX;
     const int nblk = (int)(gridDim.x * gridDim.y * gridDim.z);
     const int b = (int)(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z));
     const int xcd = b % 8, per = nblk / 8, extra = nblk % 8;
     const int t = xcd * per + min(xcd, extra) + b / 8;
-    // Within a channel slice the tiles go in bands of kYB tile rows in y: x fastest,
-    // then y within the band, then the plane chunks, then the bands (the last band
-    // may be shorter), so that tiles sharing input rows or planes are close in order.
     constexpr int kYB = 4;
     const int nyt = (int)gridDim.x / nxt, nzc = (int)gridDim.y;
     const int per_slice = (int)gridDim.x * nzc;
@@ -113,9 +117,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const int band = rem / (nxt * kYB * nzc), in_band = rem % (nxt * kYB * nzc);
     const int h = min(kYB, nyt - band * kYB);
     const int xt = in_band % nxt, yin = (in_band / nxt) % h, zc = in_band / (nxt * h);
-    const int x0 = xt * kTX, y0 = (band * kYB + yin) * kTY;
-    const int z0 = zc * ZC;
-    const int co0 = slice * 16 * NT;
+    return ConvTile{xt * kTX, (band * kYB + yin) * kTY, zc, slice};
+}
+
+template <int NT, int ZC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_conv_fwd(ConvArgs a) {
+    __shared__ __attribute__((aligned(16))) uint16_t slab[(ZC + 2) * kPlane * kVS];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // each tile reads 5/3 x 6/4 of its own input (ZC = 3)
+    const ConvTile T = conv_tile(a.nx);
+    const int x0 = T.x0, y0 = T.y0;
+    const int z0 = T.zc * ZC;
+    const int co0 = T.slice * 16 * NT;
     const int m = lane & 15, kb = lane >> 4;
     f32x4 acc[ZC][4][NT];
 #pragma unroll
@@ -252,6 +265,166 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             }
         }
     }
+}
+
+// Single-stage form for 16 input channels: a workgroup marches through a run of zr
+// output planes of its 4 x 64 tile.  Input plane z0 - 1 + i lives in ring slot i & 3
+// (four distinct LDS arrays, chosen at compile time by a loop unrolled four times);
+// while output plane p is computed from slots p, p + 1, p + 2, input plane z0 + p + 2
+// is copied straight into slot p + 3, so each plane is copied once per run and the
+// copy runs under the products (the compiler keeps a read of one slot from waiting
+// on the copy into another only while every read names its slot at compile time).
+// A plane's BF16 results are stored at the next step, after that step's copy is
+// issued, so a barrier (which waits for the copies) never waits for fresh stores.
+// One plane of accumulators, 240 VGPRs: two workgroups per CU.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_conv_zm(ConvArgs a, int zr) {
+    __shared__ __attribute__((aligned(16))) uint16_t s0[kPlane * kVS], s1[kPlane * kVS], s2[kPlane * kVS],
+        s3[kPlane * kVS];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const ConvTile T = conv_tile(a.nx);
+    const int x0 = T.x0, y0 = T.y0;
+    const int z0 = T.zc * zr, co0 = T.slice * 16;
+    const int n = min(zr, a.nz - z0);  // output planes of this run, at least one
+    const int m = lane & 15, kb = lane >> 4, chan = 8 * (kb & 1);
+    const int yy = y0 + wave, c = co0 + 4 * kb;
+    // weights (once: a single stage) and biases
+    const __amdgpu_buffer_rsrc_t rw =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t *>(a.w), (short)0, (int)a.wbytes, kRawBuffer);
+    const uint32_t woff = 2u * (uint32_t)((co0 + m) * a.kpad + (kb >> 1) * a.cin + chan);
+    bf16x8 B[kKC];
+#pragma unroll
+    for (int q = 0; q < kKC; ++q) {
+        const int tap = 2 * q + (kb >> 1);
+        B[q] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rw, tap < 27 ? woff : kNoOff,
+                                                                                  2u * (uint32_t)(2 * q * a.cin), 0));
+    }
+    float bias[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bias[i] = a.b ? a.b[c + i] : 0.f;
+    const __amdgpu_buffer_rsrc_t rx =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t *>(a.x), (short)0, (int)a.xbytes, kRawBuffer);
+    uint32_t poff[kPS];
+#pragma unroll
+    for (int it = 0; it < kPS; ++it) {
+        const int e = tid + 256 * it, bv = e >> 1, h = e & 1;
+        const int xx = x0 + bv % kBX - 1, yq = y0 + bv / kBX - 1;
+        const bool in = xx >= 0 && xx < a.nx && yq >= 0 && yq < a.ny;
+        poff[it] = in ? 2u * (uint32_t)((yq * a.nx + xx) * a.ldx + a.offx + 8 * h) : kNoOff;
+    }
+    auto copy_plane = [&](int zz, uint16_t *slot) __attribute__((always_inline)) {
+        const bool zin = zz >= 0 && zz < a.nz;  // else the plane reads as zeros
+        const uint32_t zoff = zin ? (uint32_t)zz * a.plane_bytes : 0u;
+#pragma unroll
+        for (int it = 0; it < kPS; ++it) {
+            const int e0 = 256 * it + 64 * wave, e = e0 + lane;
+            if (e0 >= 2 * kPlane) break;  // wave-uniform
+            if (e < 2 * kPlane)
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rx, (lds_void *)(slot + 8 * e0), 16, zin ? poff[it] : kNoOff,
+                                                         zoff, 0, 0);
+        }
+    };
+    // BF16 results of the previous plane, stored after the next copy is issued (the
+    // FP32 results, written in training only, leave at once)
+    uint2 pend0 = make_uint2(0u, 0u), pend1 = pend0, pend2 = pend0, pend3 = pend0;
+    int pend_z = -1;
+    auto flush = [&]() __attribute__((always_inline)) {
+        const bool row = pend_z >= 0 && yy < a.ny;
+#pragma unroll
+        for (int t4 = 0; t4 < 4; ++t4) {
+            const int xx = x0 + 16 * t4 + m;
+            if (row && xx < a.nx) {
+                const int64_t vm = ((int64_t)pend_z * a.ny + yy) * a.nx + xx;
+                *reinterpret_cast<uint2 *>(a.y + vm * a.ldy + a.offy + c) =
+                    t4 == 0 ? pend0 : t4 == 1 ? pend1 : t4 == 2 ? pend2 : pend3;
+            }
+        }
+    };
+    // Output plane z0 + p reads the slots of input planes z0 + p - 1 .. z0 + p + 1
+    // (ring slots p, p + 1, p + 2, mod 4) while input plane z0 + p + 2 is copied into
+    // slot p + 3; the loop runs four planes per trip so that every slot is a fixed
+    // array in each of them.  ring(i): slot i, a constant once the loop is unrolled.
+    auto ring = [&](int i) -> uint16_t * {
+        i &= 3;
+        return i == 0 ? s0 : i == 1 ? s1 : i == 2 ? s2 : s3;
+    };
+    copy_plane(z0 - 1, s0);
+    copy_plane(z0, s1);
+    copy_plane(z0 + 1, s2);
+    for (int p0 = 0; p0 < n; p0 += 4) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int p = p0 + k;
+            if (p >= n) break;
+            // This plane's inputs have landed (each wave waits for its own copies, the
+            // barrier for all of them) and every wave is done with slot k + 3's plane.
+            // The wait is explicit: the compiler does not carry the copy issued in the
+            // last step of a trip around the loop's back edge.
+            __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+            __syncthreads();
+            flush();
+            if (p + 2 <= n) copy_plane(z0 + p + 2, ring(k + 3));
+            // The slot a lane reads is fixed per chunk except where the chunk's two taps
+            // lie in different planes (taps 8 and 9): there both slots are read and each
+            // lane keeps its own, so that every LDS read names one slot at compile time
+            // (a read the compiler cannot place waits for the copy in flight).
+            auto read_a = [&](int q, bf16x8(&A)[4]) {
+                const int tap = 2 * q + (kb >> 1);
+                const int dy = (tap / 3) % 3, dx = tap % 3;
+                const int dz0 = (2 * q) / 9, dz1 = (2 * q + 1) / 9;
+                const int base = (wave + dy) * kBX + m + dx;
+#pragma unroll
+                for (int t4 = 0; t4 < 4; ++t4) {
+                    const int o = (base + 16 * t4) * kVS + chan;
+                    uint4 av = *reinterpret_cast<const uint4 *>(&ring(k + dz0)[o]);
+                    if (dz1 != dz0 && 2 * q + 1 < 27) {
+                        // combined by masks: a select of the two loads would fold into
+                        // one load from a selected slot
+                        const uint4 a1 = *reinterpret_cast<const uint4 *>(&ring(k + dz1)[o]);
+                        const uint32_t k1 = 0u - (uint32_t)(kb >> 1), k0 = ~k1;
+                        av = make_uint4((av.x & k0) | (a1.x & k1), (av.y & k0) | (a1.y & k1), (av.z & k0) | (a1.z & k1),
+                                        (av.w & k0) | (a1.w & k1));
+                    }
+                    if (tap >= 27) av = make_uint4(0u, 0u, 0u, 0u);
+                    A[t4] = __builtin_bit_cast(bf16x8, av);
+                }
+            };
+            f32x4 acc[4];
+#pragma unroll
+            for (int t4 = 0; t4 < 4; ++t4) acc[t4] = (f32x4){0.f, 0.f, 0.f, 0.f};
+            bf16x8 Af[2][4];
+            read_a(0, Af[0]);
+#pragma unroll
+            for (int q = 0; q < kKC; ++q) {
+                if (q + 1 < kKC) read_a(q + 1, Af[(q + 1) & 1]);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int t4 = 0; t4 < 4; ++t4)
+                    acc[t4] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(B[q], Af[q & 1][t4], acc[t4], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+#pragma unroll
+            for (int t4 = 0; t4 < 4; ++t4) {
+                float v[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    v[i] = acc[t4][i] + bias[i];
+                    if (a.relu) v[i] = fmaxf(v[i], 0.f);
+                }
+                const uint2 o = make_uint2((uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16),
+                                           (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16));
+                if (t4 == 0) pend0 = o;
+                else if (t4 == 1) pend1 = o;
+                else if (t4 == 2) pend2 = o;
+                else pend3 = o;
+                const int xx = x0 + 16 * t4 + m;
+                if (a.y32 && yy < a.ny && xx < a.nx)
+                    *reinterpret_cast<float4 *>(a.y32 + (((int64_t)p + z0) * a.ny + yy) * a.nx * a.cout +
+                                                (int64_t)xx * a.cout + c) = make_float4(v[0], v[1], v[2], v[3]);
+            }
+            pend_z = z0 + p;
+        }
+    }
+    flush();
 }
 
 // wt[ci][tap' * cout + co] = w[co][(26 - tap') * cin + ci]
@@ -703,6 +876,15 @@ static int launch_conv(ConvArgs a, int64_t nx2, int64_t ny2, int64_t nz2, void *
     a.wbytes = (uint32_t)wbytes;
     const int64_t nxy = (int64_t)((nx + kTX - 1) / kTX) * ((ny + kTY - 1) / kTY);
     if (nxy > 0x7fffffff) return -1;
+    if (cin == kCC && a.cin1 == cin) {
+        // one stage: the z-marching form, runs of zr planes (4 .. 32), about six
+        // rounds of two workgroups per CU on a large grid
+        const int64_t zr = std::min<int64_t>(32, std::max<int64_t>(4, nxy * (tiles / nt) * nz / kZmWorkgroups));
+        const dim3 g((unsigned)nxy, (unsigned)((nz + zr - 1) / zr), (unsigned)(tiles / nt)), blk(256);
+        (void)hipGetLastError();
+        hipLaunchKernelGGL(k_conv_zm, g, blk, 0, static_cast<hipStream_t>(stream), a, (int)zr);
+        return status(hipGetLastError());
+    }
     const bool large = nxy * ((nz + 3) / 4) * (tiles / nt) >= kZcLargeGrid;
     const int zc = large ? 4 : 3;
     const dim3 g((unsigned)nxy, (unsigned)((nz + zc - 1) / zc), (unsigned)(tiles / nt)), blk(256);

@@ -97,17 +97,18 @@ def test_conv3d_forward(U, cin, cout, xs, ys, relu):
     assert np.all(yb[..., :offy] == 0) and np.all(yb[..., offy + cout:] == 0)
 
 
-def test_conv3d_forward_on_a_large_grid(U):
-    """The launch form for large grids (four output planes per workgroup, taken from
-    2048 workgroups on): 26 x 258 x 130 voxels, 16 -> 32 channels written at offset
-    16 of 48-channel rows, ragged in every direction (26 planes in chunks of 4, 258
-    rows in tiles of 4, 130 voxels in tiles of 64).  Boxes at the corners and inside
-    are compared with the oracle; every output voxel is written, the other channels
-    are left alone."""
+@pytest.mark.parametrize("shape,cin", [((26, 258, 130), 16), ((26, 258, 130), 32), ((98, 516, 130), 16)])
+def test_conv3d_forward_on_a_large_grid(U, shape, cin):
+    """The launch forms for large grids, ragged in every direction (x in tiles of 64,
+    y in tiles of 4), 32 output channels written at offset 16 of 48-channel rows:
+    16 input channels march through runs of planes (runs of 4 on 26 planes, of 24 on
+    98 planes, the last run short); 32 take four output planes per workgroup (2048
+    workgroups or more).  Boxes at the corners and inside are compared with the
+    oracle; every output voxel is written, the other channels are left alone."""
     import torch
 
-    rng = np.random.default_rng(7)
-    shape, cin, cout, ldy, offy = (26, 258, 130), 16, 32, 48, 16
+    rng = np.random.default_rng(7 + cin + shape[0])
+    cout, ldy, offy = 32, 48, 16
     nwg = -(-shape[2] // 64) * -(-shape[1] // 4) * -(-shape[0] // 4) * (cout // 16)
     assert nwg >= 2048
     x = _bf(rng, *shape, cin)
@@ -121,7 +122,8 @@ def test_conv3d_forward_on_a_large_grid(U):
     got32, gotb = _host(y32), _host(y)
     xp = np.pad(x, ((1, 1), (1, 1), (1, 1), (0, 0)))
     nz, ny, nx = shape
-    for z0, y0, x0 in [(0, 0, 0), (nz - 6, ny - 9, nx - 70), (9, 120, 30), (0, ny - 5, 60), (nz - 3, 2, nx - 3)]:
+    for z0, y0, x0 in [(0, 0, 0), (nz - 6, ny - 9, nx - 70), (9, 120, 30), (0, ny - 5, 60), (nz - 3, 2, nx - 3),
+                       (20, 200, 60)]:
         dz, dy, dx = min(6, nz - z0), min(9, ny - y0), min(70, nx - x0)
         ref = C.conv3d(xp[z0:z0 + dz + 2, y0:y0 + dy + 2, x0:x0 + dx + 2], w, b, relu=True)[1:-1, 1:-1, 1:-1]
         box = (slice(z0, z0 + dz), slice(y0, y0 + dy), slice(x0, x0 + dx))
@@ -130,6 +132,12 @@ def test_conv3d_forward_on_a_large_grid(U):
     # every output written (no sentinel left), the other channels untouched
     assert np.all(got32 >= 0) and np.all(gotb[..., offy:offy + cout] >= 0)
     assert np.all(gotb[..., :offy] == -7.0) and np.all(gotb[..., offy + cout:] == -7.0)
+    # a second launch gives the same bits everywhere (the copies of the next planes
+    # run under the products: a missing wait shows here first)
+    y2 = torch.full(shape + (cout,), -7.0, dtype=torch.float32, device="cuda")
+    U.unet_conv3d_fwd(_dev_bf16(x), cin, 0, _dev_bf16(_wmat(w, cin, U.unet_kpad(cin))), _dev_f32(b), y, ldy, offy,
+                      y2, shape, cin, cout, True)
+    assert np.array_equal(_host(y2), got32)
 
 
 @pytest.mark.parametrize("shape,c1,c2,cout", [((6, 10, 70), 16, 32, 16), ((26, 258, 130), 16, 32, 32),
