@@ -90,7 +90,7 @@ constexpr int kPS = (2 * kPlane + 255) / 256;  // 16-byte loads per thread and i
 // input planes, and each stage's loads are exposed once per ZC planes, so larger
 // grids take ZC = 4; small ones keep ZC = 3 for more workgroups.
 constexpr int kZcLargeGrid = 2048;  // workgroups at ZC = 4 from which ZC = 4 is used
-constexpr int kZmWorkgroups = 3072; // the z-marching form aims for about this many workgroups
+constexpr int kZmWorkgroups = 1536; // the z-marching form aims for about this many workgroups
 // s_waitcnt vmcnt(0) (expcnt and lgkmcnt at their maxima: not waited for) on gfx9
 constexpr int kWaitVmcnt0 = 0x0F70;
 
@@ -877,8 +877,9 @@ static int launch_conv(ConvArgs a, int64_t nx2, int64_t ny2, int64_t nz2, void *
     const int64_t nxy = (int64_t)((nx + kTX - 1) / kTX) * ((ny + kTY - 1) / kTY);
     if (nxy > 0x7fffffff) return -1;
     if (cin == kCC && a.cin1 == cin) {
-        // one stage: the z-marching form, runs of zr planes (4 .. 32), about six
-        // rounds of two workgroups per CU on a large grid
+        // one stage: the z-marching form, runs of zr planes (4 .. 32), about three
+        // rounds of two workgroups per CU on a large grid (timed best among 768 ..
+        // 6144 workgroups)
         const int64_t zr = std::min<int64_t>(32, std::max<int64_t>(4, nxy * (tiles / nt) * nz / kZmWorkgroups));
         const dim3 g((unsigned)nxy, (unsigned)((nz + zr - 1) / zr), (unsigned)(tiles / nt)), blk(256);
         (void)hipGetLastError();

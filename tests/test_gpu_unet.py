@@ -101,7 +101,7 @@ def test_conv3d_forward(U, cin, cout, xs, ys, relu):
 def test_conv3d_forward_on_a_large_grid(U, shape, cin):
     """The launch forms for large grids, ragged in every direction (x in tiles of 64,
     y in tiles of 4), 32 output channels written at offset 16 of 48-channel rows:
-    16 input channels march through runs of planes (runs of 4 on 26 planes, of 24 on
+    16 input channels march through runs of planes (runs of 6 on 26 planes, of 32 on
     98 planes, the last run short); 32 take four output planes per workgroup (2048
     workgroups or more).  Boxes at the corners and inside are compared with the
     oracle; every output voxel is written, the other channels are left alone."""
