@@ -62,6 +62,15 @@ int unet_conv3d_fwd_cat(const uint16_t *x, int32_t ldx, int32_t offx, int32_t ci
                         int32_t offy, float *y32, int32_t nz, int32_t ny, int32_t nx, int32_t cin, int32_t cout,
                         int32_t relu, void *stream);
 
+/* The network's last convolution and its head in one pass: y = ReLU(b + W * x)
+ * (unet_conv3d_fwd with 16 input and 16 output channels), then out[v] = hb[0] +
+ * base[v] + sum_c hw[c] y[v, c] on the BF16-rounded y, in channel order, as
+ * unet_head_fwd forms it; y itself is not stored.  base may be NULL (zero); out is
+ * FP32 per voxel.  The other requirements are unet_conv3d_fwd's; else -1. */
+int unet_conv3d_fwd_head(const uint16_t *x, int32_t ldx, int32_t offx, const uint16_t *w, const float *b,
+                         const float *hw, const float *hb, const float *base, float *out, int32_t nz, int32_t ny,
+                         int32_t nx, void *stream);
+
 /* Weights of the backward-data convolution: wt[ci, tap' * cout + co] =
  * w[co, (26 - tap') * cin + ci]; wt has kpad = unet_kpad(cout).  Running
  * unet_conv3d_fwd with wt (cin and cout swapped, no bias, no ReLU) on dy gives dx. */

@@ -62,6 +62,11 @@ struct ConvArgs {
     const uint16_t *x2;
     int ldx2, offx2, cin1, up2;
     uint32_t x2bytes, plane2_bytes;
+    // The network's 1x1x1 head fused into the last convolution (z-marching form,
+    // 16 channels): hout[v] = hb + hbase[v] + sum_c hw[c] y[v, c] on the BF16 outputs,
+    // which are then not stored.
+    const float *hw, *hb, *hbase;
+    float *hout;
 };
 
 typedef __attribute__((address_space(3))) void lds_void;
@@ -276,7 +281,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // on the copy into another only while every read names its slot at compile time).
 // A plane's BF16 results are stored at the next step, after that step's copy is
 // issued, so a barrier (which waits for the copies) never waits for fresh stores.
-// One plane of accumulators, 240 VGPRs: two workgroups per CU.
+// One plane of accumulators, 240 VGPRs: two workgroups per CU.  HEAD: the head is
+// applied in the epilogue and only its FP32 output is stored.
+template <bool HEAD>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_conv_zm(ConvArgs a, int zr) {
     __shared__ __attribute__((aligned(16))) uint16_t s0[kPlane * kVS], s1[kPlane * kVS], s2[kPlane * kVS],
         s3[kPlane * kVS];
@@ -298,9 +305,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         B[q] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rw, tap < 27 ? woff : kNoOff,
                                                                                   2u * (uint32_t)(2 * q * a.cin), 0));
     }
-    float bias[4];
+    float bias[4], hw[4], hb = 0.f;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) bias[i] = a.b ? a.b[c + i] : 0.f;
+    for (int i = 0; i < 4; ++i) {
+        bias[i] = a.b ? a.b[c + i] : 0.f;
+        hw[i] = HEAD ? a.hw[c + i] : 0.f;
+    }
+    if (HEAD) hb = a.hb[0];
     const __amdgpu_buffer_rsrc_t rx =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t *>(a.x), (short)0, (int)a.xbytes, kRawBuffer);
     uint32_t poff[kPS];
@@ -326,6 +337,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     // BF16 results of the previous plane, stored after the next copy is issued (the
     // FP32 results, written in training only, leave at once)
     uint2 pend0 = make_uint2(0u, 0u), pend1 = pend0, pend2 = pend0, pend3 = pend0;
+    float hpend0 = 0.f, hpend1 = 0.f, hpend2 = 0.f, hpend3 = 0.f;  // HEAD: the head's outputs
     int pend_z = -1;
     auto flush = [&]() __attribute__((always_inline)) {
         const bool row = pend_z >= 0 && yy < a.ny;
@@ -334,8 +346,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             const int xx = x0 + 16 * t4 + m;
             if (row && xx < a.nx) {
                 const int64_t vm = ((int64_t)pend_z * a.ny + yy) * a.nx + xx;
-                *reinterpret_cast<uint2 *>(a.y + vm * a.ldy + a.offy + c) =
-                    t4 == 0 ? pend0 : t4 == 1 ? pend1 : t4 == 2 ? pend2 : pend3;
+                if (HEAD) {
+                    if (kb == 3) a.hout[vm] = t4 == 0 ? hpend0 : t4 == 1 ? hpend1 : t4 == 2 ? hpend2 : hpend3;
+                } else {
+                    *reinterpret_cast<uint2 *>(a.y + vm * a.ldy + a.offy + c) =
+                        t4 == 0 ? pend0 : t4 == 1 ? pend1 : t4 == 2 ? pend2 : pend3;
+                }
             }
         }
     };
@@ -361,6 +377,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             // last step of a trip around the loop's back edge.
             __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
             __syncthreads();
+            // HEAD: this plane's base values, loaded before this step's stores and copy
+            // so that waiting for them waits for nothing younger
+            float hbase[4] = {0.f, 0.f, 0.f, 0.f};
+            if (HEAD && a.hbase && kb == 0 && yy < a.ny) {
+#pragma unroll
+                for (int t4 = 0; t4 < 4; ++t4) {
+                    const int xx = x0 + 16 * t4 + m;
+                    if (xx < a.nx) hbase[t4] = a.hbase[((int64_t)(z0 + p) * a.ny + yy) * a.nx + xx];
+                }
+            }
             flush();
             if (p + 2 <= n) copy_plane(z0 + p + 2, ring(k + 3));
             // The slot a lane reads is fixed per chunk except where the chunk's two taps
@@ -412,7 +438,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                 }
                 const uint2 o = make_uint2((uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16),
                                            (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16));
-                if (t4 == 0) pend0 = o;
+                if (HEAD) {
+                    // the head's sum in channel order, as unet_head_fwd forms it from the
+                    // stored BF16 values: lanes of group kb add channels 4 kb .. 4 kb + 3
+                    // and pass the sum to group kb + 1 (16 lanes up)
+                    float hs = hb + hbase[t4];
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) {
+                        if (g > 0) {
+                            const float up = __shfl_up(hs, 16, 64);
+                            if (kb == g) hs = up;
+                        }
+                        if (kb == g) {
+                            hs = fmaf(hw[0], bf2f((uint16_t)(o.x & 0xffffu)), hs);
+                            hs = fmaf(hw[1], bf2f((uint16_t)(o.x >> 16)), hs);
+                            hs = fmaf(hw[2], bf2f((uint16_t)(o.y & 0xffffu)), hs);
+                            hs = fmaf(hw[3], bf2f((uint16_t)(o.y >> 16)), hs);
+                        }
+                    }
+                    if (t4 == 0) hpend0 = hs;
+                    else if (t4 == 1) hpend1 = hs;
+                    else if (t4 == 2) hpend2 = hs;
+                    else hpend3 = hs;
+                } else if (t4 == 0) pend0 = o;
                 else if (t4 == 1) pend1 = o;
                 else if (t4 == 2) pend2 = o;
                 else pend3 = o;
@@ -853,8 +901,8 @@ int32_t unet_kpad(int32_t cin) { return kpad_of(cin); }
 // both convolution entry points: a.x2 is a.x and a.cin1 a.cin for a single input
 static int launch_conv(ConvArgs a, int64_t nx2, int64_t ny2, int64_t nz2, void *stream) {
     const int nx = a.nx, ny = a.ny, nz = a.nz, cin = a.cin, cout = a.cout;
-    if (!a.x || !a.x2 || !a.w || !a.y || nz <= 0 || ny <= 0 || nx <= 0 || cin % 16 || a.cin1 % 16 || a.cin1 <= 0 ||
-        a.cin1 > cin || !ch_ok(a.ldx, a.offx, a.cin1) || (a.cin1 < cin && !ch_ok(a.ldx2, a.offx2, cin - a.cin1)) ||
+    if (!a.x || !a.x2 || !a.w || (!a.y && !a.hout) || nz <= 0 || ny <= 0 || nx <= 0 || cin % 16 || a.cin1 % 16 ||
+        a.cin1 <= 0 || a.cin1 > cin || !ch_ok(a.ldx, a.offx, a.cin1) || (a.cin1 < cin && !ch_ok(a.ldx2, a.offx2, cin - a.cin1)) ||
         !ch_ok(a.ldy, a.offy, cout) || (a.ldx % 8) || (a.offx % 8) || (a.ldx2 % 8) || (a.offx2 % 8) || (a.ldy % 8) ||
         (a.offy % 8))
         return -1;
@@ -883,7 +931,10 @@ static int launch_conv(ConvArgs a, int64_t nx2, int64_t ny2, int64_t nz2, void *
         const int64_t zr = std::min<int64_t>(32, std::max<int64_t>(4, nxy * (tiles / nt) * nz / kZmWorkgroups));
         const dim3 g((unsigned)nxy, (unsigned)((nz + zr - 1) / zr), (unsigned)(tiles / nt)), blk(256);
         (void)hipGetLastError();
-        hipLaunchKernelGGL(k_conv_zm, g, blk, 0, static_cast<hipStream_t>(stream), a, (int)zr);
+        if (a.hout)
+            hipLaunchKernelGGL(k_conv_zm<true>, g, blk, 0, static_cast<hipStream_t>(stream), a, (int)zr);
+        else
+            hipLaunchKernelGGL(k_conv_zm<false>, g, blk, 0, static_cast<hipStream_t>(stream), a, (int)zr);
         return status(hipGetLastError());
     }
     const bool large = nxy * ((nz + 3) / 4) * (tiles / nt) >= kZcLargeGrid;
@@ -902,7 +953,17 @@ int unet_conv3d_fwd(const uint16_t *x, int32_t ldx, int32_t offx, const uint16_t
                     int32_t ldy, int32_t offy, float *y32, int32_t nz, int32_t ny, int32_t nx, int32_t cin,
                     int32_t cout, int32_t relu, void *stream) {
     ConvArgs a{x, w, b, y, y32, ldx, offx, ldy, offy, nz, ny, nx, cin, cout, 0, relu, 0, 0, 0,
-               x, ldx, offx, cin, 0, 0, 0};
+               x, ldx, offx, cin, 0, 0, 0, nullptr, nullptr, nullptr, nullptr};
+    return launch_conv(a, nx, ny, nz, stream);
+}
+
+int unet_conv3d_fwd_head(const uint16_t *x, int32_t ldx, int32_t offx, const uint16_t *w, const float *b,
+                         const float *hw, const float *hb, const float *base, float *out, int32_t nz, int32_t ny,
+                         int32_t nx, void *stream) {
+    if (!hw || !hb || !out) return -1;
+    // 16 -> 16 channels with ReLU, then the head; the BF16 outputs are not stored
+    ConvArgs a{x, w, b, nullptr, nullptr, ldx, offx, 16, 0, nz, ny, nx, 16, 16, 0, 1, 0, 0, 0,
+               x, ldx, offx, 16, 0, 0, 0, hw, hb, base, out};
     return launch_conv(a, nx, ny, nz, stream);
 }
 
@@ -912,7 +973,7 @@ int unet_conv3d_fwd_cat(const uint16_t *x, int32_t ldx, int32_t offx, int32_t ci
                         void *stream) {
     if (nz % 2 || ny % 2 || nx % 2) return -1;  // x2 holds the half-resolution grid
     ConvArgs a{x, w, b, y, y32, ldx, offx, ldy, offy, nz, ny, nx, cin, cout, 0, relu, 0, 0, 0,
-               x2, ldx2, offx2, cin1, 1, 0, 0};
+               x2, ldx2, offx2, cin1, 1, 0, 0, nullptr, nullptr, nullptr, nullptr};
     if (cin1 >= cin) return -1;
     return launch_conv(a, nx / 2, ny / 2, nz / 2, stream);
 }

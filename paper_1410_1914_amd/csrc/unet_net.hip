@@ -170,9 +170,10 @@ struct unet_net {
             run(conv_cat(D2A, act(A_CAT2), kC2, act(A_D3B), kC3, act(A_D2A), 1));
             run(conv(D2B, act(A_D2A), kC2, 0, act(A_D2B), kC2, 0, 1, true));
             run(conv_cat(D1A, act(A_CAT1), kC1, act(A_D2B), kC2, act(A_D1A), 0));
-            run(conv(D1B, act(A_D1A), kC1, 0, act(A_D1B), kC1, 0, 0, true));
-            run(to_hip(unet_head_fwd(act(A_D1B), kC1, p() + P.w[kLayers], p() + P.b[kLayers], base, out, vox[0],
-                                     kC1, st)));
+            // the last convolution with the head in its epilogue: D1B is never stored
+            static_assert(kC1 == 16, "unet_conv3d_fwd_head is the 16-channel form");
+            run(to_hip(unet_conv3d_fwd_head(act(A_D1A), kC1, 0, pb() + P.w[D1B], p() + P.b[D1B], p() + P.w[kLayers],
+                                            p() + P.b[kLayers], base, out, d0[0], d0[1], d0[2], st)));
             return e;
         }
         run(conv(E1A, feat, kIn, 0, act(A_A1), kC1, 0, 0, true));

@@ -26,6 +26,7 @@ _i32, _i64, _f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
 SIGNATURES = {
     "unet_kpad": ([_i32], _i32),
     "unet_conv3d_fwd": ([_P, _i32, _i32, _P, _P, _P, _i32, _i32, _P, _i32, _i32, _i32, _i32, _i32, _i32, _P], _i32),
+    "unet_conv3d_fwd_head": ([_P, _i32, _i32, _P, _P, _P, _P, _P, _P, _i32, _i32, _i32, _P], _i32),
     "unet_conv3d_fwd_cat": ([_P, _i32, _i32, _i32, _P, _i32, _i32, _P, _P, _P, _i32, _i32, _P, _i32, _i32, _i32, _i32,
                              _i32, _i32, _P], _i32),
     "unet_conv3d_wtrans": ([_P, _P, _i32, _i32, _P], _i32),
@@ -121,6 +122,12 @@ def unet_conv3d_fwd_cat(x, ldx, offx, cin1, x2, ldx2, offx2, w, b, y, ldy, offy,
     nz, ny, nx = shape
     _call("unet_conv3d_fwd_cat", _ptr(x), ldx, offx, cin1, _ptr(x2), ldx2, offx2, _ptr(w), _ptr(b), _ptr(y), ldy, offy,
           _ptr(y32), nz, ny, nx, cin, cout, int(relu), _stream())
+
+
+def unet_conv3d_fwd_head(x, ldx, offx, w, b, hw, hb, base, out, shape):
+    nz, ny, nx = shape
+    _call("unet_conv3d_fwd_head", _ptr(x), ldx, offx, _ptr(w), _ptr(b), _ptr(hw), _ptr(hb), _ptr(base), _ptr(out),
+          nz, ny, nx, _stream())
 
 
 def unet_conv3d_wtrans(w, wt, cin, cout):

@@ -465,6 +465,10 @@ def test_convolution_refuses_bad_operands_without_touching_the_device():
 
     assert cat(shape=(4, 5, 4)) == -1 and cat(cin1=48) == -1 and cat(cin1=0) == -1
     assert cat(x2=base + 8) == -1 and cat(ldx2=24) == -1 and cat(cin=40) == -1
+    # the head form: weights, bias and output required, pointers aligned
+    head = lambda x=base, hw=base, out=base: lib.unet_conv3d_fwd_head(x, 16, 0, base, None, hw, base, None, out, 4, 4,
+                                                                       4, None)
+    assert head(hw=None) == -1 and head(out=None) == -1 and head(x=base + 8) == -1
 
 
 def test_device_preparation_refuses_a_bad_scratch_without_touching_the_device():

@@ -177,6 +177,37 @@ def test_conv3d_forward_over_a_concatenation_with_an_upsampled_tensor(U, shape, 
         assert np.allclose(outs[1][1], ref, rtol=1e-4, atol=1e-4)
 
 
+@pytest.mark.parametrize("shape,with_base", [((6, 10, 70), True), ((26, 258, 130), False), ((98, 40, 130), True)])
+def test_last_convolution_with_the_head(U, shape, with_base):
+    """unet_conv3d_fwd_head equals unet_conv3d_fwd (16 -> 16, ReLU) followed by
+    unet_head_fwd, bit for bit, with and without a base field, on ragged grids whose
+    z runs end short; the small one also against the oracle's convolution and head."""
+    import torch
+
+    rng = np.random.default_rng(shape[0] + with_base)
+    x = _bf(rng, *shape, 16)
+    w = _bf(rng, 16, 27, 16, scale=0.2)
+    b = _bf(rng, 16)
+    hw, hb = rng.standard_normal(16), rng.standard_normal(1)
+    base = rng.standard_normal(shape) if with_base else None
+    xd, wd, bd = _dev_bf16(x), _dev_bf16(_wmat(w, 16, U.unet_kpad(16))), _dev_f32(b)
+    hwd, hbd = _dev_f32(hw), _dev_f32(hb)
+    based = _dev_f32(base) if with_base else None
+    y = torch.zeros(shape + (16,), dtype=torch.bfloat16, device="cuda")
+    U.unet_conv3d_fwd(xd, 16, 0, wd, bd, y, 16, 0, None, shape, 16, 16, True)
+    sep = torch.zeros(shape, dtype=torch.float32, device="cuda")
+    U.unet_head_fwd(y, 16, hwd, hbd, based, sep, int(np.prod(shape)), 16)
+    fused = torch.full(shape, -7.0, dtype=torch.float32, device="cuda")
+    U.unet_conv3d_fwd_head(xd, 16, 0, wd, bd, hwd, hbd, based, fused, shape)
+    assert np.array_equal(_host(fused), _host(sep))
+    if np.prod(shape) <= 5000:
+        # the head reads the BF16-rounded convolution: round the oracle's the same way
+        # (an FP32 sum next to a rounding boundary may round one BF16 step apart)
+        yr = torch.tensor(C.conv3d(x, w, b, relu=True), dtype=torch.float32).to(torch.bfloat16).double().numpy()
+        ref = yr @ hw + hb[0] + (base if with_base else 0.0)
+        assert np.allclose(_host(fused), ref, rtol=1e-3, atol=0.15)
+
+
 @pytest.mark.parametrize("cin,cout", [(16, 16), (48, 16), (32, 64), (192, 64)])
 def test_conv3d_backward_data(U, cin, cout):
     import torch
